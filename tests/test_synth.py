@@ -1,0 +1,68 @@
+"""The seeded input generators produce simple undirected CSR graphs, reproducibly."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.mark.parametrize("scale,ef", [(8, 4), (12, 8), (16, 8)])
+def test_rmat_valid_and_deterministic(scale, ef):
+    g = synth.rmat(scale, ef, seed=1)
+    synth.validate(g)
+    assert g.n == 1 << scale
+    assert 0 < g.arcs <= 2 * ef * g.n
+    h = synth.rmat(scale, ef, seed=1)
+    assert np.array_equal(g.off, h.off) and np.array_equal(g.nbr, h.nbr)
+    k = synth.rmat(scale, ef, seed=2)
+    assert not (len(k.nbr) == len(g.nbr) and np.array_equal(k.nbr, g.nbr))
+    # no relabelling: vertex 0 is the top hub of a (0.57, 0.19, 0.19, 0.05) R-MAT
+    assert g.deg[0] == g.deg.max()
+
+
+def test_rmat_independent_of_thread_count():
+    code = ("import synth,hashlib;g=synth.rmat(14,8,seed=7);"
+            "print(hashlib.sha1(g.off.tobytes()+g.nbr.tobytes()).hexdigest())")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for t in ("1", "4"):
+        env = dict(os.environ, OMP_NUM_THREADS=t, PYTHONPATH=root)
+        outs.append(subprocess.check_output([sys.executable, "-c", code], env=env, cwd=root))
+    assert outs[0] == outs[1]
+
+
+@pytest.mark.parametrize("g", [synth.worked_example(), synth.complete(7), synth.star(9),
+                               synth.path(6), synth.cycle(9), synth.barbell(5), synth.torus3d(4),
+                               synth.erdos_renyi(50, 0.1, 3)])
+def test_small_graphs_valid(g):
+    synth.validate(g)
+
+
+def test_torus_degrees():
+    g = synth.torus3d(5)
+    assert g.n == 125 and np.all(g.deg == 6)
+
+
+def test_validate_rejects():
+    g = synth.path(4)
+    bad = synth.Graph(g.off.copy(), g.nbr.copy())
+    bad.nbr[0] = 0  # self-loop at vertex 0
+    with pytest.raises(ValueError):
+        synth.validate(bad)
+    asym = synth.Graph(np.array([0, 1, 1], np.int64), np.array([1], np.int32))
+    with pytest.raises(ValueError):
+        synth.validate(asym)
+
+
+def test_query_generators():
+    g = synth.rmat(12, 8, seed=1)
+    q = synth.batched_queries(g, 256, seed=2)
+    assert np.all(g.deg[q.seeds] >= 1)
+    assert np.all((q.eps >= 1e-7) & (q.eps <= 1e-5))
+    assert set(np.unique(q.alpha)) <= {0.01, 0.05}
+    s = synth.uniform_seeds(g, 16, seed=2)
+    assert np.array_equal(s, synth.uniform_seeds(g, 16, seed=2))
+    assert synth.largest_component_min_vertex(g) == 0
