@@ -1,0 +1,182 @@
+/*
+ * plc.h -- C ABI of libplc, a gfx950 (MI355X) implementation of parallel
+ * local graph clustering: round-synchronous PR-Nibble followed by the sweep
+ * cut, after Shun, Roosta-Khorasani, Fountoulakis and Mahoney, "Parallel
+ * Local Graph Clustering" (arXiv 1604.07515).
+ *
+ * Conventions
+ *  - Every call returns a plc_status: PLC_OK (0) or a negative code.  No C++
+ *    exception crosses this boundary.
+ *  - A context is used by one host thread at a time.
+ *  - Device memory: the caller hands the library one device buffer (the
+ *    arena) at plc_init and keeps it alive until plc_destroy.  The library
+ *    never allocates device memory itself; every graph, query state and
+ *    result lives in the arena, so the arena size is the memory budget.
+ *  - Streams: all device work is issued on the hipStream_t given at plc_init
+ *    (passed as void*; NULL means the default stream).
+ *  - Graphs are undirected and unweighted (Sec. 2, "Graph Notation"): CSR
+ *    with row offsets off[0..n] and neighbour ids nbr[0..off[n]), every
+ *    undirected edge stored as two arcs, d(v) = off[v+1] - off[v],
+ *    2m = off[n].
+ */
+#ifndef PLC_H
+#define PLC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t plc_status;
+#define PLC_OK 0
+#define PLC_E_INVALID (-1)  /* bad argument, bad graph, bad query parameter   */
+#define PLC_E_NOMEM (-2)    /* the arena cannot hold the graph or the query   */
+#define PLC_E_BUSY (-3)     /* no batch slot or memory free now; retry later  */
+#define PLC_E_NOTREADY (-4) /* the query has not finished                     */
+#define PLC_E_NOTFOUND (-5) /* unknown or released query id                   */
+#define PLC_E_LIMIT (-6)    /* max_rounds reached (watchdog)                  */
+#define PLC_E_HIP (-7)      /* HIP runtime error; the context is unusable     */
+
+/* Push rules of PR-Nibble (Sec. 3.3). */
+#define PLC_RULE_OPT 0u  /* optimized rule ("An Optimization", Fig. alg:pr-nibble2):
+                            p[v] += (2a/(1+a)) r[v]; r[w] += ((1-a)/(1+a)) r[v]/d(v); r[v] = 0 */
+#define PLC_RULE_ORIG 1u /* original rule (Fig. alg:pr-nibble):
+                            p[v] += a r[v]; r[w] += (1-a) r[v]/(2 d(v)); r[v] = (1-a) r[v]/2 */
+
+/* plc_graph_load flags */
+#define PLC_GRAPH_VALIDATE 1u /* check symmetry, sorted rows, no self-loops or
+                                 duplicates, ids < n; PLC_E_INVALID otherwise */
+
+typedef struct plc_ctx plc_ctx;
+typedef struct plc_graph plc_graph;
+
+typedef struct {
+  int32_t max_rounds;  /* watchdog on PR-Nibble rounds per query; 0 = 1<<20 */
+  int32_t batch_slots; /* concurrent queries in the batched path; 0 = 256   */
+  int32_t reserved[6];
+} plc_options;
+
+/*
+ * One PR-Nibble query (Sec. 3.3): seed vertex x with d(x) >= 1, teleport
+ * alpha in (0,1), tolerance eps (finite, 1e-250 <= eps).  The first round
+ * always pushes the seed; afterwards a vertex is active in a round when
+ * r[v] >= eps * d(v) at the start of that round.
+ */
+typedef struct {
+  int32_t seed;
+  uint32_t rule; /* PLC_RULE_OPT or PLC_RULE_ORIG */
+  double alpha;
+  double eps;
+} plc_query;
+
+typedef struct {
+  int64_t n;           /* vertices                              */
+  int64_t arcs;        /* 2m                                    */
+  int64_t max_degree;
+  int64_t bytes;       /* arena bytes held by the graph          */
+} plc_graph_info;
+
+/* Summary of a finished query.  cut, vol and phi describe the best sweep
+ * prefix S_kstar (Sec. 3.1): phi = cut / min(vol, 2m - vol). */
+typedef struct {
+  int32_t status;     /* PLC_OK, PLC_E_LIMIT or PLC_E_NOMEM             */
+  int32_t rounds;     /* rounds that pushed at least one vertex         */
+  int64_t pushes;     /* sum over rounds of |frontier|                  */
+  int64_t edges;      /* sum over rounds of sum_{v in frontier} d(v)    */
+  int64_t support;    /* N = |{v : p[v] > 0}|                           */
+  int64_t kstar;      /* cluster = first kstar vertices of the sweep    */
+  int64_t cut;        /* |boundary(S_kstar)|                            */
+  int64_t vol;        /* vol(S_kstar)                                   */
+  double phi;         /* conductance of S_kstar                         */
+  int64_t r_nnz;      /* nonzeros of r at exit                          */
+} plc_result_info;
+
+/* Status code to a static string. */
+const char* plc_status_str(plc_status s);
+
+/*
+ * Create a context on HIP device `device`, using the caller-owned device
+ * buffer [dev_arena, dev_arena + arena_bytes) (256-byte aligned) as the only
+ * device memory and `hip_stream` (a hipStream_t, may be NULL) for all work.
+ * opt may be NULL.  On success *out receives the context.
+ */
+plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, size_t arena_bytes,
+                    void* hip_stream, const plc_options* opt);
+
+/* Wait for outstanding work and free the library's host state.  Graphs and
+ * results of the context become invalid.  The arena is not touched. */
+plc_status plc_destroy(plc_ctx* ctx);
+
+/*
+ * Copy a host CSR graph (Sec. 2) into the arena and prepare its per-vertex
+ * state.  offsets: n+1 entries of 32 or 64 bits (offsets_bits), host memory;
+ * nbrs: num_arcs int32 ids, host memory.  The caller may free both on
+ * return.  Errors: PLC_E_INVALID (sizes, offsets not monotone, or a failed
+ * PLC_GRAPH_VALIDATE check), PLC_E_NOMEM (arena too small).
+ */
+plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs, const void* offsets,
+                          int32_t offsets_bits, const int32_t* nbrs, uint32_t flags,
+                          plc_graph** out);
+
+plc_status plc_graph_free(plc_ctx* ctx, plc_graph* g);
+plc_status plc_graph_info_get(const plc_graph* g, plc_graph_info* out);
+
+/*
+ * Plain path: run `count` queries one after another, each as round-
+ * synchronous PR-Nibble (Sec. 3.3, Figs. alg:pr-nibble / alg:pr-nibble2)
+ * followed by the sweep cut (Sec. 3.1, Theorem 1), blocking until all are
+ * done.  ids[i] (may be NULL) receives a handle whose vectors stay in the
+ * arena until plc_release; infos[i] (may be NULL) receives the summary.
+ * A query rejected by parameter checks gets status PLC_E_INVALID in its info
+ * and id 0, and the call still runs the others; the return value is the
+ * first error met, or PLC_OK.
+ */
+plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count, uint64_t* ids,
+                   plc_result_info* infos);
+
+/* Summary of a finished query. PLC_E_NOTFOUND for unknown ids,
+ * PLC_E_NOTREADY for queries still in flight. */
+plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);
+
+/*
+ * Copy a finished query's vectors to caller-owned host buffers (NULL skips
+ * one): sweep_ids[support] = the support in sweep order (non-increasing
+ * p/d, ties by ascending id), sweep_p[support] = p at those vertices, so the
+ * cluster is sweep_ids[0..kstar); r_ids[r_nnz], r_vals[r_nnz] = nonzeros of
+ * the final residual in unspecified order.
+ */
+plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_ids, double* sweep_p,
+                           int32_t* r_ids, double* r_vals);
+
+/* Return a finished query's arena memory. */
+plc_status plc_release(plc_ctx* ctx, uint64_t id);
+
+/* Arena bytes currently free (largest free block in *largest, may be NULL). */
+plc_status plc_arena_free_bytes(plc_ctx* ctx, size_t* total, size_t* largest);
+
+/*
+ * Device-time accounting of the plain path, measured with HIP events recorded
+ * on the context's stream around kernel launches (off by default).  Only
+ * rounds that pushed something are counted for the scatter and self kernels.
+ *   scatter: the edgeMap kernel; units = pushed edges, entries = pushes
+ *   self:    the vertexMap + frontier-scan kernel; units = pushes
+ *   sweep:   the whole sweep-cut sequence; units = support volume vol(S_N),
+ *            entries = support size N
+ */
+typedef struct {
+  int64_t launches;
+  double ms;       /* summed device time */
+  int64_t units;
+  int64_t entries;
+} plc_kernel_time;
+
+plc_status plc_timing_enable(plc_ctx* ctx, int32_t on);  /* also resets the counters */
+plc_status plc_timing_get(plc_ctx* ctx, plc_kernel_time* scatter, plc_kernel_time* self,
+                          plc_kernel_time* sweep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLC_H */

@@ -1,0 +1,278 @@
+"""Python binding of libplc: parallel local graph clustering on MI355X (gfx950).
+
+Argument marshalling only.  Every step of PR-Nibble and the sweep cut runs in
+the HIP kernels of ``libplc.so``; this module passes pointers and sizes
+through the C ABI of ``include/plc.h``.  PyTorch supplies the device arena
+(one uint8 tensor) and the stream.  If the library has not been built, or no
+GPU is present, the calls raise: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libplc.so")
+
+PLC_OK = 0
+PLC_E_INVALID = -1
+PLC_E_NOMEM = -2
+PLC_E_BUSY = -3
+PLC_E_NOTREADY = -4
+PLC_E_NOTFOUND = -5
+PLC_E_LIMIT = -6
+PLC_E_HIP = -7
+PLC_RULE_OPT = 0
+PLC_RULE_ORIG = 1
+PLC_GRAPH_VALIDATE = 1
+
+# Every symbol include/plc.h declares.
+SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
+           "plc_graph_info_get", "plc_run", "plc_result_info_get", "plc_result_copy",
+           "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get")
+
+
+class PlcError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s: %s (%d)" % (what, status_str(code), code))
+        self.code = code
+
+
+class plc_options(C.Structure):
+    _fields_ = [("max_rounds", C.c_int32), ("batch_slots", C.c_int32),
+                ("reserved", C.c_int32 * 6)]
+
+
+class plc_query(C.Structure):
+    _fields_ = [("seed", C.c_int32), ("rule", C.c_uint32), ("alpha", C.c_double),
+                ("eps", C.c_double)]
+
+
+class plc_graph_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("arcs", C.c_int64), ("max_degree", C.c_int64),
+                ("bytes", C.c_int64)]
+
+
+class plc_result_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("rounds", C.c_int32), ("pushes", C.c_int64),
+                ("edges", C.c_int64), ("support", C.c_int64), ("kstar", C.c_int64),
+                ("cut", C.c_int64), ("vol", C.c_int64), ("phi", C.c_double),
+                ("r_nnz", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class plc_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double), ("units", C.c_int64),
+                ("entries", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libplc.so (after torch, so that one HIP runtime serves both)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libplc.so is not built (run __graft_entry__.build() or "
+                          "python paper_1604_07515_amd/build.py)")
+    import torch  # noqa: F401  -- loads the HIP runtime torch was built with
+    lib = C.CDLL(path)
+    P, I32, I64, U32, U64, D, SZ = (C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64,
+                                    C.c_double, C.c_size_t)
+    sig = {
+        "plc_status_str": ([I32], C.c_char_p),
+        "plc_init": ([C.POINTER(P), I32, P, SZ, P, C.POINTER(plc_options)], I32),
+        "plc_destroy": ([P], I32),
+        "plc_graph_load": ([P, I64, I64, P, I32, P, U32, C.POINTER(P)], I32),
+        "plc_graph_free": ([P, P], I32),
+        "plc_graph_info_get": ([P, C.POINTER(plc_graph_info)], I32),
+        "plc_run": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
+                     C.POINTER(plc_result_info)], I32),
+        "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
+        "plc_result_copy": ([P, U64, P, P, P, P], I32),
+        "plc_release": ([P, U64], I32),
+        "plc_arena_free_bytes": ([P, C.POINTER(SZ), C.POINTER(SZ)], I32),
+        "plc_timing_enable": ([P, I32], I32),
+        "plc_timing_get": ([P, C.POINTER(plc_kernel_time), C.POINTER(plc_kernel_time),
+                            C.POINTER(plc_kernel_time)], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    try:
+        return load_library().plc_status_str(code).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def _check(code: int, what: str) -> int:
+    if code != PLC_OK:
+        raise PlcError(code, what)
+    return code
+
+
+def _ptr(a: np.ndarray) -> C.c_void_p:
+    return C.c_void_p(a.ctypes.data)
+
+
+@dataclass
+class Result:
+    """Vectors of a finished query (host copies)."""
+    info: dict
+    sweep_ids: np.ndarray   # support in sweep order
+    sweep_p: np.ndarray     # p at those vertices
+    r_ids: np.ndarray       # nonzeros of r (unspecified order)
+    r_vals: np.ndarray
+
+    @property
+    def cluster(self) -> np.ndarray:
+        return self.sweep_ids[: self.info["kstar"]]
+
+    def dense_p(self, n: int) -> np.ndarray:
+        p = np.zeros(n)
+        p[self.sweep_ids] = self.sweep_p
+        return p
+
+    def dense_r(self, n: int) -> np.ndarray:
+        r = np.zeros(n)
+        r[self.r_ids] = self.r_vals
+        return r
+
+
+class Graph:
+    def __init__(self, ctx: "Context", handle: C.c_void_p, n: int, arcs: int):
+        self.ctx, self.handle, self.n, self.arcs = ctx, handle, n, arcs
+
+    def info(self) -> dict:
+        gi = plc_graph_info()
+        _check(self.ctx.lib.plc_graph_info_get(self.handle, C.byref(gi)), "plc_graph_info_get")
+        return {k: getattr(gi, k) for k, _ in gi._fields_}
+
+    def free(self):
+        if self.handle:
+            _check(self.ctx.lib.plc_graph_free(self.ctx.handle, self.handle), "plc_graph_free")
+            self.handle = None
+
+
+class Context:
+    """A libplc context on one GPU, with a torch-owned arena and stream."""
+
+    def __init__(self, arena_bytes: int, device: int = 0, stream=None, max_rounds: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libplc needs a GPU; torch.cuda.is_available() is False")
+        self.lib = load_library()
+        self.device = device
+        dev = torch.device("cuda", device)
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
+        base = self.arena.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        opt = plc_options()
+        opt.max_rounds = max_rounds
+        h = C.c_void_p()
+        _check(self.lib.plc_init(C.byref(h), device, C.c_void_p(aligned), int(arena_bytes),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(opt)), "plc_init")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.plc_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def load_graph(self, off: np.ndarray, nbr: np.ndarray, validate: bool = False) -> Graph:
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+        n = len(off) - 1
+        h = C.c_void_p()
+        _check(self.lib.plc_graph_load(self.handle, n, len(nbr), _ptr(off), 64, _ptr(nbr),
+                                       PLC_GRAPH_VALIDATE if validate else 0, C.byref(h)),
+               "plc_graph_load")
+        return Graph(self, h, n, len(nbr))
+
+    @staticmethod
+    def queries(seeds, alpha, eps, rule=PLC_RULE_OPT):
+        seeds = np.atleast_1d(np.asarray(seeds, dtype=np.int64))
+        k = len(seeds)
+        alpha = np.broadcast_to(np.asarray(alpha, np.float64), (k,))
+        eps = np.broadcast_to(np.asarray(eps, np.float64), (k,))
+        rule = np.broadcast_to(np.asarray(rule, np.int64), (k,))
+        qa = (plc_query * k)()
+        for i in range(k):
+            qa[i].seed = int(seeds[i])
+            qa[i].rule = int(rule[i])
+            qa[i].alpha = float(alpha[i])
+            qa[i].eps = float(eps[i])
+        return qa
+
+    def run(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+        """Plain path: queries one after another.  Returns (ids, infos)."""
+        qa = self.queries(seeds, alpha, eps, rule)
+        k = len(qa)
+        ids = (C.c_uint64 * k)()
+        infos = (plc_result_info * k)()
+        rc = self.lib.plc_run(self.handle, g.handle, qa, k, ids, infos)
+        if check and rc not in (PLC_OK,):
+            raise PlcError(rc, "plc_run")
+        return list(ids), [x.as_dict() for x in infos]
+
+    def result(self, qid: int, release: bool = False) -> Result:
+        info = plc_result_info()
+        _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)), "plc_result_info_get")
+        N, R = info.support, info.r_nnz
+        ids = np.empty(N, np.int32)
+        p = np.empty(N, np.float64)
+        rid = np.empty(R, np.int32)
+        rv = np.empty(R, np.float64)
+        _check(self.lib.plc_result_copy(self.handle, qid, _ptr(ids), _ptr(p), _ptr(rid), _ptr(rv)),
+               "plc_result_copy")
+        if release:
+            self.release(qid)
+        return Result(info.as_dict(), ids, p, rid, rv)
+
+    def release(self, qid: int):
+        _check(self.lib.plc_release(self.handle, qid), "plc_release")
+
+    def arena_free(self):
+        t, l = C.c_size_t(), C.c_size_t()
+        _check(self.lib.plc_arena_free_bytes(self.handle, C.byref(t), C.byref(l)), "plc_arena_free")
+        return t.value, l.value
+
+    def timing(self, on: bool):
+        _check(self.lib.plc_timing_enable(self.handle, int(on)), "plc_timing_enable")
+
+    def timing_get(self) -> dict:
+        a, b, c = plc_kernel_time(), plc_kernel_time(), plc_kernel_time()
+        _check(self.lib.plc_timing_get(self.handle, C.byref(a), C.byref(b), C.byref(c)),
+               "plc_timing_get")
+        return {"scatter": a.as_dict(), "self": b.as_dict(), "sweep": c.as_dict()}
+
+
+def plain_arena_bytes(n: int, arcs: int) -> int:
+    """Arena bytes the plain path needs for one graph (plus result space)."""
+    per_vertex = 8 + 16 + 8 + 4 * 2 + 8 * 3 + 4 * 2 + 8 * 2 + 4 * 2 + 4 + 8 + 4 + 8 + 4 + 8
+    scan = 3 * 32 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
+    return int(per_vertex * n + 4 * arcs + 4 * (arcs // 1024 + 2) + 1024 * (n // 2048 + 2)
+               + scan + (1 << 20) * 64)

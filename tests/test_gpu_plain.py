@@ -1,0 +1,158 @@
+"""GPU parity of the plain path (one query at a time) against the oracle.
+
+Every call goes through the C ABI of libplc (via the ctypes binding).
+Inputs are seeded synthetic graphs; sizes span several scan blocks, edge
+tiles and radix tiles with ragged tails.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from parity import check_query
+
+pytestmark = pytest.mark.gpu
+
+OPT, ORIG = 0, 1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def plc():
+    import paper_1604_07515_amd as plc
+    return plc
+
+
+@pytest.fixture(scope="module")
+def ctx(plc):
+    c = plc.Context(arena_bytes=3 << 30)
+    yield c
+    c.close()
+
+
+GRAPHS = {
+    "rmat10": lambda: synth.rmat(10, 8, seed=3),
+    "rmat13": lambda: synth.rmat(13, 8, seed=4),
+    "rmat16": lambda: synth.rmat(16, 8, seed=1),
+    "barbell12": lambda: synth.barbell(12),
+    "star300": lambda: synth.star(300),
+    "k40": lambda: synth.complete(40),
+    "torus12": lambda: synth.torus3d(12),
+    "k2": lambda: synth.path(2),
+}
+_cache = {}
+
+
+def graph(ctx, name):
+    if name not in _cache:
+        g = GRAPHS[name]()
+        _cache[name] = (g, ctx.load_graph(g.off, g.nbr, validate=True))
+    return _cache[name]
+
+
+CASES = []
+for gname in ("rmat10", "rmat13", "barbell12", "star300", "k40", "torus12", "k2"):
+    for rule in (OPT, ORIG):
+        for eps in (1e-3, 1e-5, 1e-7):
+            CASES.append((gname, rule, eps))
+
+
+@pytest.mark.parametrize("gname,rule,eps", CASES)
+def test_parity_small(ctx, gname, rule, eps):
+    g, hg = graph(ctx, gname)
+    seeds = [int(s) for s in synth.uniform_seeds(g, 2, seed=7)]
+    alpha = 0.01 if rule == OPT else 0.05
+    say("case", gname, rule, eps, seeds)
+    ids, infos = ctx.run(hg, seeds, alpha, eps, rule)
+    for qid, s in zip(ids, seeds):
+        res = ctx.result(qid, release=True)
+        check_query(g, res, s, alpha, eps, rule)
+
+
+def test_parity_rmat16_seed0_full(ctx):
+    """2^16 vertices, avg degree ~16, alpha=0.01, eps=1e-7, seed 0 (largest component)."""
+    g, hg = graph(ctx, "rmat16")
+    x = synth.largest_component_min_vertex(g)
+    say("case rmat16 seed", x)
+    ids, infos = ctx.run(hg, [x], 0.01, 1e-7, OPT)
+    res = ctx.result(ids[0], release=True)
+    rep = check_query(g, res, x, 0.01, 1e-7, OPT)
+    say("report", rep)
+    assert rep["rounds"] > 50 and rep["support"] > 30000
+
+
+def test_same_query_twice_is_identical_and_state_resets(ctx):
+    g, hg = graph(ctx, "rmat13")
+    seeds = [int(s) for s in synth.uniform_seeds(g, 3, seed=11)]
+    say("case repeat", seeds)
+    ids1, _ = ctx.run(hg, seeds, 0.02, 1e-6, OPT)
+    ids2, _ = ctx.run(hg, seeds[::-1], 0.02, 1e-6, OPT)
+    r1 = [ctx.result(i, release=True) for i in ids1]
+    r2 = [ctx.result(i, release=True) for i in ids2][::-1]
+    for a, b, s in zip(r1, r2, seeds):
+        assert a.info["rounds"] == b.info["rounds"]
+        assert np.array_equal(a.sweep_ids, b.sweep_ids)
+        assert np.allclose(a.sweep_p, b.sweep_p, rtol=1e-12, atol=0)
+        check_query(g, b, s, 0.02, 1e-6, OPT)
+
+
+def test_invalid_queries_rejected(ctx, plc):
+    g = synth.from_edges(6, [(0, 1), (1, 2), (2, 3)])  # 4 and 5 isolated
+    hg = ctx.load_graph(g.off, g.nbr, validate=True)
+    bad = [(4, 0.01, 1e-4), (9, 0.01, 1e-4), (-1, 0.01, 1e-4), (0, 0.0, 1e-4), (0, 1.0, 1e-4),
+           (0, 0.01, 0.0), (0, 0.01, float("nan")), (0, 0.01, float("inf"))]
+    for s, a, e in bad:
+        ids, infos = ctx.run(hg, [s], a, e, OPT, check=False)
+        assert ids[0] == 0 and infos[0]["status"] == plc.PLC_E_INVALID
+    # a good query in the same call still runs
+    ids, infos = ctx.run(hg, [4, 0], [0.01, 0.01], [1e-4, 1e-4], OPT, check=False)
+    assert infos[0]["status"] == plc.PLC_E_INVALID and infos[1]["status"] == 0
+    res = ctx.result(ids[1], release=True)
+    check_query(g, res, 0, 0.01, 1e-4, OPT)
+    hg.free()
+
+
+def test_invalid_graphs_rejected(ctx, plc):
+    g = synth.path(5)
+    nbr = g.nbr.copy()
+    nbr[0] = 0  # self-loop
+    with pytest.raises(plc.PlcError) as e:
+        ctx.load_graph(g.off, nbr, validate=True)
+    assert e.value.code == plc.PLC_E_INVALID
+    off = g.off.copy()
+    off[2] = off[3] + 1  # not monotone
+    with pytest.raises(plc.PlcError):
+        ctx.load_graph(off, g.nbr)
+
+
+def test_watchdog_limit(plc):
+    g = synth.path(2)
+    with plc.Context(arena_bytes=64 << 20, max_rounds=5) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        ids, infos = c.run(hg, [0], 0.01, 1e-7, OPT, check=False)
+        assert infos[0]["status"] == plc.PLC_E_LIMIT and infos[0]["rounds"] == 5
+        res = c.result(ids[0], release=True)
+        part = oracle.prnibble(g.off, g.nbr, 0, 0.01, 1e-7, OPT, max_rounds=5)
+        assert np.allclose(res.dense_p(2), part.p, rtol=1e-12, atol=0)
+
+
+def test_arena_exhausted(plc):
+    g = synth.rmat(12, 8, seed=1)
+    with plc.Context(arena_bytes=1 << 20) as c:
+        with pytest.raises(plc.PlcError) as e:
+            c.load_graph(g.off, g.nbr)
+        assert e.value.code == plc.PLC_E_NOMEM
+
+
+def test_seed_above_threshold_pushes_once(ctx):
+    g, hg = graph(ctx, "star300")
+    ids, infos = ctx.run(hg, [0], 0.01, 0.5, OPT)  # eps * d(0) = 150 > 1
+    res = ctx.result(ids[0], release=True)
+    assert infos[0]["rounds"] == 1 and infos[0]["pushes"] == 1
+    check_query(g, res, 0, 0.01, 0.5, OPT)
