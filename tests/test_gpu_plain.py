@@ -143,7 +143,7 @@ def test_watchdog_limit(plc):
 
 
 def test_arena_exhausted(plc):
-    g = synth.rmat(12, 8, seed=1)
+    g = synth.rmat(15, 8, seed=1)  # needs several MiB of plain-path state
     with plc.Context(arena_bytes=1 << 20) as c:
         with pytest.raises(plc.PlcError) as e:
             c.load_graph(g.off, g.nbr)
