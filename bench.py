@@ -34,8 +34,14 @@ SCATTER_B_PER_EDGE = 20
 SCATTER_B_PER_ENTRY = 24
 
 WORKLOADS = {
-    "plain22": dict(scale=22, ef=16, nseeds=16, alpha=0.01, eps=1e-7),
-    "plain16": dict(scale=16, ef=8, nseeds=1, alpha=0.01, eps=1e-7),
+    # 16 seeds one after another on the 2^22 graph (plain path)
+    "plain22": dict(scale=22, ef=16, nseeds=16, alpha=0.01, eps=1e-7, batched=False),
+    # the 2^16 graph from vertex 0 of the largest component
+    "plain16": dict(scale=16, ef=8, nseeds=1, alpha=0.01, eps=1e-7, batched=False),
+    # 256 seeds in one batch on the 2^22 graph, eps log-uniform in [1e-7, 1e-5],
+    # alpha in {0.01, 0.05}
+    "batched22": dict(scale=22, ef=16, nseeds=256, eps_lo=1e-7, eps_hi=1e-5, batched=True,
+                      slots=256),
 }
 
 
@@ -72,27 +78,47 @@ def main():
     wl = WORKLOADS[args.workload]
     t0 = time.time()
     g = synth.rmat(wl["scale"], wl["ef"], seed=1)
-    if args.workload == "plain16":
-        seeds = np.array([synth.largest_component_min_vertex(g)], np.int32)
+    if wl["batched"]:
+        qs = synth.batched_queries(g, wl["nseeds"], seed=2, eps_lo=wl["eps_lo"],
+                                   eps_hi=wl["eps_hi"])
+        seeds, alphas, epss = qs.seeds, qs.alpha, qs.eps
     else:
-        seeds = synth.uniform_seeds(g, wl["nseeds"], seed=2)
+        if args.workload == "plain16":
+            seeds = np.array([synth.largest_component_min_vertex(g)], np.int32)
+        else:
+            seeds = synth.uniform_seeds(g, wl["nseeds"], seed=2)
+        alphas = np.full(len(seeds), wl["alpha"])
+        epss = np.full(len(seeds), wl["eps"])
     log("graph n=%d arcs=%d maxdeg=%d (%.1fs)" % (g.n, g.arcs, g.deg.max(), time.time() - t0))
 
     arena = plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20)
+    if wl["batched"]:
+        arena += plc.batch_arena_bytes(g.n, g.arcs, wl["slots"])
     ctx = plc.Context(arena_bytes=arena, device=0)
     hg = ctx.load_graph(g.off, g.nbr)
-    alpha, eps = wl["alpha"], wl["eps"]
+    if wl["batched"]:
+        got = ctx.batch_reserve(hg, wl["slots"])
+        log("batch slots granted: %d" % got)
 
     def step(lat, acc):
-        for s in seeds:
+        if wl["batched"]:
             q0 = time.perf_counter()
-            ids, infos = ctx.run(hg, [int(s)], alpha, eps)
+            ids, infos = ctx.run_batched(hg, seeds, alphas, epss)
             lat.append(time.perf_counter() - q0)
-            acc["edges"] += infos[0]["edges"]
-            acc["pushes"] += infos[0]["pushes"]
-            acc["rounds"] += infos[0]["rounds"]
-            acc["support"] += infos[0]["support"]
-            ctx.release(ids[0])
+        else:
+            ids, infos = [], []
+            for s, al, ep in zip(seeds, alphas, epss):
+                q0 = time.perf_counter()
+                i1, f1 = ctx.run(hg, [int(s)], float(al), float(ep))
+                lat.append(time.perf_counter() - q0)
+                ids += i1
+                infos += f1
+        for qid, info in zip(ids, infos):
+            acc["edges"] += info["edges"]
+            acc["pushes"] += info["pushes"]
+            acc["rounds"] += info["rounds"]
+            acc["support"] += info["support"]
+            ctx.release(qid)
 
     for i in range(args.warmup):
         step([], {"edges": 0, "pushes": 0, "rounds": 0, "support": 0})
@@ -131,12 +157,18 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "rmat%d_ef%d_plain_%dseeds" % (wl["scale"], wl["ef"], len(seeds)),
-            "n": g.n, "arcs": g.arcs, "alpha": alpha, "eps": eps, "rule": "optimized",
-            "queries_per_step": len(seeds), "path": "plain (one query at a time)",
+            "workload": "rmat%d_ef%d_%s_%dseeds" % (wl["scale"], wl["ef"],
+                                                     "batched" if wl["batched"] else "plain",
+                                                     len(seeds)),
+            "n": g.n, "arcs": g.arcs, "rule": "optimized", "queries_per_step": len(seeds),
+            "alpha": sorted(set(float(x) for x in alphas)),
+            "eps": [float(epss.min()), float(epss.max())],
+            "path": ("batched (%d slots, one round of every query per launch)" % wl["slots"]
+                     if wl["batched"] else "plain (one query at a time)"),
         },
         "queries_per_s": nq / elapsed,
-        "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                       "what": "per batch call" if wl["batched"] else "per query"},
         "per_query": {"edges": acc["edges"] / nq, "pushes": acc["pushes"] / nq,
                       "rounds": acc["rounds"] / nq, "support": acc["support"] / nq},
         "kernels": tm,
@@ -158,8 +190,8 @@ def main():
         budget = args.cpu_budget
         c0 = time.perf_counter()
         done, e_sum = 0, 0
-        for s in seeds:
-            r = oracle.prnibble(g.off, g.nbr, int(s), alpha, eps)
+        for s, al, ep in zip(seeds, alphas, epss):
+            r = oracle.prnibble(g.off, g.nbr, int(s), float(al), float(ep))
             oracle.sweep(g.off, g.nbr, r.p)
             done += 1
             e_sum += r.edges

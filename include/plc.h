@@ -136,6 +136,48 @@ plc_status plc_graph_info_get(const plc_graph* g, plc_graph_info* out);
 plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count, uint64_t* ids,
                    plc_result_info* infos);
 
+/*
+ * Batched path.  Many queries advance together: every global step runs one
+ * PR-Nibble round for all admitted queries in the same kernel launches, and
+ * the queries whose frontier emptied are swept together.  Results are the
+ * same as plc_run's (same kernels' arithmetic; only the order of atomic
+ * additions differs).
+ *
+ * plc_batch_reserve: give graph g a batch engine with up to `slots`
+ * concurrent queries (1..1024).  Each slot holds dense per-vertex state
+ * (about 40 bytes per vertex), so fewer slots are granted when the arena is
+ * short (max(64 MiB, 1/16 of the free arena) stays free for result blocks);
+ * *granted (may be NULL) receives the number.  PLC_E_NOMEM if not even
+ * one slot fits.  Calling it again re-creates the engine (pending and running
+ * queries are dropped).
+ */
+plc_status plc_batch_reserve(plc_ctx* ctx, plc_graph* g, int32_t slots, int32_t* granted);
+
+/*
+ * Queue `count` queries on graph g's batch engine (non-blocking).  ids[i]
+ * receives each query's handle, or 0 with the first error returned when a
+ * query fails the parameter checks.  Queued queries are admitted into free
+ * slots at the start of the next plc_progress step, in submission order.
+ */
+plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
+                      uint64_t* ids);
+
+/*
+ * Run one global step of g's batch engine: admit queued queries into free
+ * slots, run one round for every admitted query, sweep the queries whose
+ * frontier emptied in an earlier step, and retire finished queries.  Blocks
+ * until the step's device work is done.  *in_flight (may be NULL) receives
+ * the number of queries queued or running after the step.
+ */
+plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight);
+
+/* *done = 1 if query `id` has finished (its result is ready), else 0. */
+plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);
+
+/* Submit `count` queries and step g's batch engine until all have finished. */
+plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
+                           uint64_t* ids, plc_result_info* infos);
+
 /* Summary of a finished query. PLC_E_NOTFOUND for unknown ids,
  * PLC_E_NOTREADY for queries still in flight. */
 plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);

@@ -32,7 +32,8 @@ PLC_GRAPH_VALIDATE = 1
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
            "plc_graph_info_get", "plc_run", "plc_result_info_get", "plc_result_copy",
-           "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get")
+           "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
+           "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_run_batched")
 
 
 class PlcError(RuntimeError):
@@ -105,6 +106,12 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "plc_timing_enable": ([P, I32], I32),
         "plc_timing_get": ([P, C.POINTER(plc_kernel_time), C.POINTER(plc_kernel_time),
                             C.POINTER(plc_kernel_time)], I32),
+        "plc_batch_reserve": ([P, P, I32, C.POINTER(I32)], I32),
+        "plc_submit": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64)], I32),
+        "plc_progress": ([P, P, C.POINTER(I32)], I32),
+        "plc_poll": ([P, U64, C.POINTER(I32)], I32),
+        "plc_run_batched": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
+                             C.POINTER(plc_result_info)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -238,6 +245,42 @@ class Context:
             raise PlcError(rc, "plc_run")
         return list(ids), [x.as_dict() for x in infos]
 
+    # ---- batched path
+    def batch_reserve(self, g: Graph, slots: int) -> int:
+        got = C.c_int32()
+        _check(self.lib.plc_batch_reserve(self.handle, g.handle, int(slots), C.byref(got)),
+               "plc_batch_reserve")
+        return got.value
+
+    def submit(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+        qa = self.queries(seeds, alpha, eps, rule)
+        ids = (C.c_uint64 * len(qa))()
+        rc = self.lib.plc_submit(self.handle, g.handle, qa, len(qa), ids)
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_submit")
+        return list(ids)
+
+    def progress(self, g: Graph) -> int:
+        left = C.c_int32()
+        _check(self.lib.plc_progress(self.handle, g.handle, C.byref(left)), "plc_progress")
+        return left.value
+
+    def poll(self, qid: int) -> bool:
+        done = C.c_int32()
+        _check(self.lib.plc_poll(self.handle, qid, C.byref(done)), "plc_poll")
+        return bool(done.value)
+
+    def run_batched(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+        """Batched path: submit all and step until every query has finished."""
+        qa = self.queries(seeds, alpha, eps, rule)
+        k = len(qa)
+        ids = (C.c_uint64 * k)()
+        infos = (plc_result_info * k)()
+        rc = self.lib.plc_run_batched(self.handle, g.handle, qa, k, ids, infos)
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_run_batched")
+        return list(ids), [x.as_dict() for x in infos]
+
     def result(self, qid: int, release: bool = False) -> Result:
         info = plc_result_info()
         _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)), "plc_result_info_get")
@@ -270,9 +313,22 @@ class Context:
         return {"scatter": a.as_dict(), "self": b.as_dict(), "sweep": c.as_dict()}
 
 
+def batch_arena_bytes(n: int, arcs: int, slots: int) -> int:
+    """Arena bytes for a batch engine with `slots` slots (on top of the plain path)."""
+    per_slot = 40 * n
+    nf_cap = min(max(2 * n, 1 << 22), slots * n)
+    nf_cap = max(nf_cap, n)
+    e_cap = max(2 * arcs, 1 << 26)
+    s_cap = max(min(2 * n, slots * n), n)
+    fixed = (28 * nf_cap + 4 * (e_cap // 1024 + 2) + 96 * (max(nf_cap, s_cap) // 1024 + 2)
+             + 56 * s_cap + 512 * slots + (1 << 20))
+    return int((per_slot * slots + fixed) * 17 // 16 + (192 << 20))
+
+
 def plain_arena_bytes(n: int, arcs: int) -> int:
-    """Arena bytes the plain path needs for one graph (plus result space)."""
-    per_vertex = 8 + 16 + 8 + 4 * 2 + 8 * 3 + 4 * 2 + 8 * 2 + 4 * 2 + 4 + 8 + 4 + 8 + 4 + 8
-    scan = 3 * 32 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
-    return int(per_vertex * n + 4 * arcs + 4 * (arcs // 1024 + 2) + 1024 * (n // 2048 + 2)
-               + scan + (1 << 20) * 64)
+    """Arena bytes the plain path needs for one graph, plus 64 MiB for results."""
+    per_vertex = 152          # offsets, state records, frontier, sweep buffers
+    per_arc = 4               # neighbour ids
+    tiles = 4 * (arcs // 1024 + 2)
+    scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
+    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20))

@@ -1,0 +1,765 @@
+// batch.hip -- gfx950 kernels of the batched path: the same round-synchronous
+// PR-Nibble round (Sec. 3.3) and sweep cut (Sec. 3.1, Theorem 1) as the plain
+// path, applied to many queries in the same launches.
+//
+// A global step runs one round for every scheduled slot:
+//   k_b_plan      (one workgroup) picks the slots whose frontier is non-empty,
+//                 within the round-buffer capacity, and lays their frontiers
+//                 end to end (entry prefix per slot).
+//   k_b_self      vertexMap(UpdateSelf) on every scheduled entry + single-pass
+//                 scan of degrees over the concatenated frontiers.
+//   k_b_scatter   edgeMap(UpdateNgh) over all scheduled edges in 1024-edge
+//                 tiles; threshold crossings append to the owning slot's next
+//                 frontier.  Entries of a tile are slot-sorted, so appends are
+//                 counted per slot in LDS and reserved with one global atomic
+//                 per slot and tile.
+//   k_b_round_end (one workgroup) per-slot bookkeeping and frontier swap.
+// Queries whose frontier emptied are swept together: their supports form
+// the segments of one merge sort (segment = query), then the rank map,
+// volume scan, boundary deltas and boundary scan run over the concatenation
+// and one workgroup per segment takes the exact argmin.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch_device.h"
+#include "device_util.h"
+#include "sort.h"
+
+namespace plc {
+
+constexpr int kMaxSlots = 1024;
+constexpr int kSlotRange = 256;  // per-tile slot range aggregated in LDS
+
+__device__ __forceinline__ int slot_of(const int32_t* pref, int B, long long g) {
+  // largest q in [0, B) with pref[q] <= g (pref[B] = total > g)
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((long long)pref[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int seg_of(const long long* off, int nseg, long long k) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- init
+
+__global__ void k_b_init(BatchArgs a) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    VRec rec;
+    rec.r = 0.0;
+    rec.deg = (int32_t)(a.off[v + 1] - a.off[v]);
+    rec.rank = 0;
+    for (int q = 0; q < a.B; q++) {
+      a.vr[(int64_t)q * a.n + v] = rec;
+      a.p[(int64_t)q * a.n + v] = 0.0;
+    }
+  }
+}
+
+__global__ void k_b_admit(BatchArgs a, const Admit* adm, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    Admit ad = adm[i];
+    if (ad.slot < 0 || ad.slot >= a.B || ad.seed < 0 || ad.seed >= a.n) continue;
+    Slot& S = a.slots[ad.slot];
+    if (ad.rule == 1) {
+      S.cs = ad.alpha;
+      S.cn = (1.0 - ad.alpha) / 2.0;
+      S.keep = (1.0 - ad.alpha) / 2.0;
+      S.opt = 0;
+    } else {
+      S.cs = 2.0 * ad.alpha / (1.0 + ad.alpha);
+      S.cn = (1.0 - ad.alpha) / (1.0 + ad.alpha);
+      S.keep = 0.0;
+      S.opt = 1;
+    }
+    S.eps = ad.eps;
+    S.seed = ad.seed;
+    S.max_rounds = ad.max_rounds;
+    S.par = 0;
+    S.cnt[0] = 1;
+    S.cnt[1] = 0;
+    S.rounds = 0;
+    S.edge_next[0] = ad.seed_deg;
+    S.edge_next[1] = 0;
+    S.pushes = 0;
+    S.edges = 0;
+    S.support_cnt = 0;
+    S.touched_cnt = 1;
+    S.fbase = -1;
+    S.nf = 0;
+    S.limited = 0;
+    S.fault = 0;
+    S.round_edges = 0;
+    S.kstar = 0;
+    S.best_cut = 0;
+    S.best_vol = 0;
+    S.best_den = 0;
+    S.phi = 0.0;
+    S.rnnz = 0;
+    const int64_t base = (int64_t)ad.slot * a.n;
+    a.fbuf[2 * base] = ad.seed;
+    a.touched[base] = ad.seed;
+    a.vr[base + ad.seed].r = 1.0;
+    S.status = SL_PUSH;
+  }
+}
+
+// ---------------------------------------------------------------- round
+
+__global__ __launch_bounds__(kMaxSlots) void k_b_plan(BatchArgs a) {
+  __shared__ long long sh[kMaxSlots / 64 + 1];
+  const int q = threadIdx.x;
+  BatchCtl* c = a.ctl;
+  long long nf = 0, e = 0;
+  if (q < a.B) {
+    Slot& S = a.slots[q];
+    S.fbase = -1;
+    S.nf = 0;
+    S.round_edges = 0;
+    if (S.status == SL_PUSH) {
+      int cur = S.cnt[S.par];
+      if (cur <= 0) {
+        S.status = SL_PUSHED;
+      } else if (S.rounds >= S.max_rounds) {
+        S.limited = 1;
+        S.status = SL_PUSHED;
+      } else {
+        nf = cur < a.n ? cur : a.n;
+        e = S.edge_next[S.par];
+      }
+    }
+  }
+  long long tot_nf, tot_e;
+  long long ex_nf = block_excl_scan<kMaxSlots>(nf, &tot_nf, sh);
+  long long ex_e = block_excl_scan<kMaxSlots>(e, &tot_e, sh);
+  // Slots are taken in order while the round buffers can hold them.
+  const bool inc = nf > 0 && ex_nf + nf <= a.nf_cap && ex_e + e <= a.e_cap;
+  long long inf = inc ? nf : 0, ie = inc ? e : 0;
+  long long tot_inf, tot_ie;
+  long long p_nf = block_excl_scan<kMaxSlots>(inf, &tot_inf, sh);
+  (void)block_excl_scan<kMaxSlots>(ie, &tot_ie, sh);
+  if (q < a.B) {
+    a.fprefix[q] = (int32_t)p_nf;
+    Slot& S = a.slots[q];
+    if (inc) {
+      S.fbase = (int32_t)p_nf;
+      S.nf = (int32_t)inf;
+      S.round_edges = ie;
+    }
+  }
+  if (q == 0) {
+    a.fprefix[a.B] = (int32_t)tot_inf;
+    c->nf_total = (int32_t)tot_inf;
+    c->e_total = tot_ie;
+    c->ntiles = (int)((tot_ie + kEdgeTile - 1) / kEdgeTile);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int NF = c->nf_total;
+  if (NF <= 0) return;
+  const int B = a.B;
+  __shared__ int32_t s_pref[kMaxSlots + 1];
+  __shared__ long long sh[kBlock / 64 + 1];
+  __shared__ long long s_excl;
+  __shared__ int s_tk[2];
+  __shared__ int s_qlo, s_qhi;
+  __shared__ int s_csup[kScanBlock], s_cstay[kScanBlock];
+  __shared__ unsigned long long s_estay[kScanBlock];
+  __shared__ int s_bsup[kScanBlock], s_bstay[kScanBlock];
+  for (int j = threadIdx.x; j <= B; j += kBlock) s_pref[j] = a.fprefix[j];
+  ScanSite* site = &c->scan[BSCAN_FRONTIER];
+  scan_clear_prev(site, a.desc[BSCAN_FRONTIER], a.desc_cap);
+  unsigned long long* desc = a.desc[BSCAN_FRONTIER] + (size_t)site->parity * a.desc_cap;
+  const int nblk = (NF + kScanBlock - 1) / kScanBlock;
+  const int64_t n = a.n;
+  __syncthreads();
+
+  for (;;) {
+    bool last;
+    int b = scan_ticket(site, nblk, s_tk, &last);
+    if (b >= nblk) break;
+    if (threadIdx.x == 0) {
+      long long g0 = (long long)b * kScanBlock;
+      long long g1 = g0 + kScanBlock - 1 < NF - 1 ? g0 + kScanBlock - 1 : NF - 1;
+      s_qlo = slot_of(s_pref, B, g0);
+      s_qhi = slot_of(s_pref, B, g1);
+    }
+    __syncthreads();
+    const int qlo = s_qlo;
+    const int range = s_qhi - qlo + 1;  // <= kScanBlock: each entry is one slot
+    for (int j = threadIdx.x; j < range; j += kBlock) {
+      s_csup[j] = 0;
+      s_cstay[j] = 0;
+      s_estay[j] = 0ull;
+    }
+    __syncthreads();
+    int32_t vk[kScanItems], dk[kScanItems], qk[kScanItems], rsup[kScanItems], rstay[kScanItems];
+    long long dsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const long long g = (long long)b * kScanBlock + k * kBlock + threadIdx.x;
+      vk[k] = -1;
+      dk[k] = 0;
+      qk[k] = 0;
+      rsup[k] = -1;
+      rstay[k] = -1;
+      if (g < NF) {
+        const int q = slot_of(s_pref, B, g);
+        const Slot& S = a.slots[q];
+        const int i = (int)(g - s_pref[q]);
+        const int par = S.par;
+        const int64_t base = (int64_t)q * n;
+        const int32_t v = a.fbuf[(2 * base) + (int64_t)par * n + i];
+        VRec rec = a.vr[base + v];
+        const double rho = rec.r;
+        const int32_t d = rec.deg;
+        const double pold = a.p[base + v];
+        a.p[base + v] = pold + S.cs * rho;
+        const double nr = S.opt ? -0.0 : S.keep * rho;
+        a.vr[base + v].r = nr;
+        a.coef[g] = (S.cn * rho) / (double)d;
+        a.rowp[g] = a.off[v];
+        a.eslot[g] = q;
+        vk[k] = v;
+        dk[k] = d;
+        qk[k] = q;
+        if (pold == 0.0) rsup[k] = atomicAdd(&s_csup[q - qlo], 1);
+        if (!S.opt && nr >= S.eps * (double)d) {
+          rstay[k] = atomicAdd(&s_cstay[q - qlo], 1);
+          atomicAdd(&s_estay[q - qlo], (unsigned long long)d);
+        }
+      }
+      dsum += dk[k];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < range; j += kBlock) {
+      Slot& S = a.slots[qlo + j];
+      s_bsup[j] = s_csup[j] > 0 ? atomicAdd(&S.support_cnt, s_csup[j]) : 0;
+      if (s_cstay[j] > 0) {
+        const int nxt = S.par ^ 1;
+        s_bstay[j] = atomicAdd(&S.cnt[nxt], s_cstay[j]);
+        atomicAdd((unsigned long long*)&S.edge_next[nxt], s_estay[j]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      if (vk[k] < 0) continue;
+      const int q = qk[k];
+      const int64_t base = (int64_t)q * n;
+      if (rsup[k] >= 0) {
+        const long long pos = (long long)s_bsup[q - qlo] + rsup[k];
+        if (pos < n) a.support[base + pos] = vk[k]; else c->fault = 1;
+      }
+      if (rstay[k] >= 0) {
+        const long long pos = (long long)s_bstay[q - qlo] + rstay[k];
+        const int nxt = a.slots[q].par ^ 1;
+        if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = vk[k]; else c->fault = 1;
+      }
+    }
+    long long agg;
+    (void)block_excl_scan<kBlock>(dsum, &agg, sh);
+    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    __syncthreads();
+    long long run = s_excl;
+    for (int k = 0; k < kScanItems; k++) {
+      const long long g = (long long)b * kScanBlock + k * kBlock + threadIdx.x;
+      long long tot;
+      long long ex = block_excl_scan<kBlock>(dk[k], &tot, sh);
+      if (g < NF) {
+        const long long s = run + ex;
+        a.estart[g] = s;
+        long long t0 = (s + kEdgeTile - 1) / kEdgeTile;
+        long long t1 = (s + dk[k] - 1) / kEdgeTile;
+        if (t1 >= a.tile_cap) { c->fault = 1; t1 = a.tile_cap - 1; }
+        for (long long tt = t0; tt <= t1; tt++) a.tile_start[tt] = (int32_t)g;
+      }
+      run += tot;
+    }
+    if (b == nblk - 1 && threadIdx.x == 0) {
+      if (run != c->e_total) c->fault = 1;  // planned and scanned edge counts must agree
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int NF = c->nf_total;
+  if (NF <= 0) return;
+  const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
+  const long long E = c->e_total;
+  const int64_t n = a.n;
+  __shared__ int32_t s_start[kEdgeTile + 1];
+  __shared__ int64_t s_row[kEdgeTile + 1];
+  __shared__ double s_coef[kEdgeTile + 1];
+  __shared__ int32_t s_slot[kEdgeTile + 1];
+  __shared__ int s_cfn[kSlotRange], s_ctv[kSlotRange], s_bfn[kSlotRange], s_btv[kSlotRange];
+  __shared__ unsigned long long s_efn[kSlotRange];
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long e0 = (long long)tile * kEdgeTile;
+    const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
+    const int i0 = a.tile_start[tile];
+    const int i1 = tile + 1 < ntiles ? a.tile_start[tile + 1] : NF - 1;
+    if (i0 < 0 || i1 < i0 || i1 >= NF || i1 - i0 + 1 > kEdgeTile + 1) {
+      c->fault = 1;
+      continue;
+    }
+    const int cnt = i1 - i0 + 1;
+    for (int j = threadIdx.x; j < cnt; j += kBlock) {
+      s_start[j] = (int32_t)(a.estart[i0 + j] - e0);
+      s_row[j] = a.rowp[i0 + j];
+      s_coef[j] = a.coef[i0 + j];
+      s_slot[j] = a.eslot[i0 + j];
+    }
+    for (int j = threadIdx.x; j < kSlotRange; j += kBlock) {
+      s_cfn[j] = 0;
+      s_ctv[j] = 0;
+      s_efn[j] = 0ull;
+    }
+    __syncthreads();
+    const int qlo = s_slot[0];
+    const int range = s_slot[cnt - 1] - qlo + 1;
+    int32_t w[kEdgesPerThread], q[kEdgesPerThread];
+    double cf[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      const int rel = k * kBlock + (int)threadIdx.x;
+      w[k] = -1;
+      q[k] = 0;
+      cf[k] = 0.0;
+      if (e0 + rel < e1) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
+        }
+        w[k] = a.nbr[s_row[lo] + (rel - s_start[lo])];
+        cf[k] = s_coef[lo];
+        q[k] = s_slot[lo];
+      }
+    }
+    int32_t dw[kEdgesPerThread];
+    double old[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      dw[k] = 0;
+      old[k] = 0.0;
+      if (w[k] >= 0) {
+        VRec* rec = a.vr + (int64_t)q[k] * n + w[k];
+        dw[k] = rec->deg;
+        old[k] = unsafeAtomicAdd(&rec->r, cf[k]);
+      }
+    }
+    // decisions: rank within (slot, list) from LDS counters, or a direct
+    // global reservation when the tile spans more slots than the LDS range
+    int rfn[kEdgesPerThread], rtv[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      rfn[k] = -1;
+      rtv[k] = -1;
+      if (w[k] < 0) continue;
+      const double thr = a.slots[q[k]].eps * (double)dw[k];
+      const bool cross = old[k] < thr && old[k] + cf[k] >= thr;
+      const bool first = __double_as_longlong(old[k]) == 0;
+      const int j = q[k] - qlo;
+      Slot& S = a.slots[q[k]];
+      const int nxt = S.par ^ 1;
+      const int64_t base = (int64_t)q[k] * n;
+      if (j < kSlotRange) {
+        if (cross) {
+          rfn[k] = atomicAdd(&s_cfn[j], 1);
+          atomicAdd(&s_efn[j], (unsigned long long)dw[k]);
+        }
+        if (first) rtv[k] = atomicAdd(&s_ctv[j], 1);
+      } else {
+        if (cross) {
+          long long pos = atomicAdd(&S.cnt[nxt], 1);
+          atomicAdd((unsigned long long*)&S.edge_next[nxt], (unsigned long long)dw[k]);
+          if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = w[k]; else c->fault = 1;
+        }
+        if (first) {
+          long long pos = atomicAdd(&S.touched_cnt, 1);
+          if (pos < n) a.touched[base + pos] = w[k]; else c->fault = 1;
+        }
+      }
+    }
+    __syncthreads();
+    const int rr = range < kSlotRange ? range : kSlotRange;
+    for (int j = threadIdx.x; j < rr; j += kBlock) {
+      Slot& S = a.slots[qlo + j];
+      const int nxt = S.par ^ 1;
+      s_bfn[j] = 0;
+      s_btv[j] = 0;
+      if (s_cfn[j] > 0) {
+        s_bfn[j] = atomicAdd(&S.cnt[nxt], s_cfn[j]);
+        atomicAdd((unsigned long long*)&S.edge_next[nxt], s_efn[j]);
+      }
+      if (s_ctv[j] > 0) s_btv[j] = atomicAdd(&S.touched_cnt, s_ctv[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      if (rfn[k] < 0 && rtv[k] < 0) continue;
+      const int j = q[k] - qlo;
+      const int64_t base = (int64_t)q[k] * n;
+      if (rfn[k] >= 0) {
+        const int nxt = a.slots[q[k]].par ^ 1;
+        const long long pos = (long long)s_bfn[j] + rfn[k];
+        if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = w[k]; else c->fault = 1;
+      }
+      if (rtv[k] >= 0) {
+        const long long pos = (long long)s_btv[j] + rtv[k];
+        if (pos < n) a.touched[base + pos] = w[k]; else c->fault = 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
+  const int q = threadIdx.x;
+  if (q >= a.B) return;
+  Slot& S = a.slots[q];
+  if (S.fbase < 0 || S.status != SL_PUSH) return;
+  S.pushes += S.nf;
+  S.edges += S.round_edges;
+  S.rounds += 1;
+  S.cnt[S.par] = 0;
+  S.edge_next[S.par] = 0;
+  S.par ^= 1;
+  S.fbase = -1;
+  if (S.cnt[S.par] == 0) S.status = SL_PUSHED;
+}
+
+// ---------------------------------------------------------------- sweep
+
+__global__ __launch_bounds__(kBlock) void k_sw_keys(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int nseg = c->sw_nseg;
+  const long long total = c->sw_total;
+  __shared__ long long s_off[kMaxSlots];
+  for (int j = threadIdx.x; j < nseg; j += kBlock) s_off[j] = a.segs[j].elem_off;
+  if (blockIdx.x == 0 && threadIdx.x == 0) c->sort_flip = 0;
+  __syncthreads();
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const int s = seg_of(s_off, nseg, k);
+    const SweepSeg& sg = a.segs[s];
+    const int64_t base = (int64_t)sg.slot * a.n;
+    const int32_t v = a.support[base + (k - s_off[s])];
+    const double ratio = a.p[base + v] / (double)a.vr[base + v].deg;
+    SortElem e;
+    e.key = ~(unsigned long long)__double_as_longlong(ratio);
+    e.id = v;
+    e.seg = s;
+    a.sbuf[0][k] = e;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_rank(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const long long total = c->sw_total;
+  const SortElem* el = a.sbuf[c->sort_flip & 1];
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const SortElem e = el[k];
+    const SweepSeg& sg = a.segs[e.seg];
+    const long long i = k - sg.elem_off;
+    const int64_t base = (int64_t)sg.slot * a.n;
+    a.vr[base + e.id].rank = (int32_t)(i + 1);
+    a.sdeg[k] = a.vr[base + e.id].deg;
+    if (sg.out_ids) {
+      sg.out_ids[i] = e.id;
+      sg.out_p[i] = a.p[base + e.id];
+    }
+    a.scnt[k] = 0;
+  }
+}
+
+// Inclusive scan of src[k] (or of sdeg - 2*scnt when cut) into dst, and,
+// for the volume scan, the edge-tile map over the concatenated supports.
+template <bool CUT>
+__global__ __launch_bounds__(kBlock) void k_sw_scan(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const long long total = c->sw_total;
+  if (total <= 0) return;
+  __shared__ long long sh[kBlock / 64 + 1];
+  __shared__ long long s_excl;
+  __shared__ int s_tk[2];
+  const int site_id = CUT ? BSCAN_CUT : BSCAN_VOL;
+  ScanSite* site = &c->scan[site_id];
+  scan_clear_prev(site, a.desc[site_id], a.desc_cap);
+  unsigned long long* desc = a.desc[site_id] + (size_t)site->parity * a.desc_cap;
+  const int nblk = (int)((total + kScanBlock - 1) / kScanBlock);
+  for (;;) {
+    bool last;
+    int b = scan_ticket(site, nblk, s_tk, &last);
+    if (b >= nblk) break;
+    long long xk[kScanItems];
+    long long xsum = 0;
+    for (int k = 0; k < kScanItems; k++) {
+      const long long i = (long long)b * kScanBlock + k * kBlock + threadIdx.x;
+      xk[k] = 0;
+      if (i < total) xk[k] = CUT ? (long long)a.sdeg[i] - 2ll * a.scnt[i] : (long long)a.sdeg[i];
+      xsum += xk[k];
+    }
+    long long agg;
+    (void)block_excl_scan<kBlock>(xsum, &agg, sh);
+    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    __syncthreads();
+    long long run = s_excl;
+    for (int k = 0; k < kScanItems; k++) {
+      const long long i = (long long)b * kScanBlock + k * kBlock + threadIdx.x;
+      long long tot;
+      long long ex = block_excl_scan<kBlock>(xk[k], &tot, sh);
+      if (i < total) {
+        const long long s = run + ex;
+        if (CUT) {
+          a.scut[i] = s + xk[k];
+        } else {
+          a.svol[i] = s + xk[k];
+          long long t0 = (s + kEdgeTile - 1) / kEdgeTile;
+          long long t1 = (s + xk[k] - 1) / kEdgeTile;
+          if (t1 >= a.tile_cap) { c->fault = 1; t1 = a.tile_cap - 1; }
+          for (long long tt = t0; tt <= t1; tt++) a.tile_start[tt] = (int32_t)i;
+        }
+      }
+      run += tot;
+    }
+    if (!CUT && b == nblk - 1 && threadIdx.x == 0) {
+      c->sw_etotal = run;
+      c->sw_ntiles = (int)((run + kEdgeTile - 1) / kEdgeTile);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const long long total = c->sw_total;
+  if (total <= 0) return;
+  const int ntiles = (int64_t)c->sw_ntiles > a.tile_cap ? (int)a.tile_cap : c->sw_ntiles;
+  const long long E = c->sw_etotal;
+  const SortElem* el = a.sbuf[c->sort_flip & 1];
+  __shared__ int32_t s_start[kEdgeTile + 1];
+  __shared__ int64_t s_row[kEdgeTile + 1];
+  __shared__ int32_t s_cnt[kEdgeTile + 1];
+  __shared__ int32_t s_own[kEdgeTile + 1];
+  __shared__ int32_t s_slot[kEdgeTile + 1];
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long long e0 = (long long)tile * kEdgeTile;
+    const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
+    const int i0 = a.tile_start[tile];
+    const int i1 = tile + 1 < ntiles ? a.tile_start[tile + 1] : (int)(total - 1);
+    if (i0 < 0 || i1 < i0 || i1 >= total || i1 - i0 + 1 > kEdgeTile + 1) {
+      c->fault = 1;
+      continue;
+    }
+    const int cnt = i1 - i0 + 1;
+    for (int j = threadIdx.x; j < cnt; j += kBlock) {
+      const long long k = i0 + j;
+      const SortElem e = el[k];
+      const SweepSeg& sg = a.segs[e.seg];
+      s_start[j] = (int32_t)(a.svol[k] - a.sdeg[k] - e0);
+      s_row[j] = a.off[e.id];
+      s_own[j] = (int32_t)(k - sg.elem_off + 1);
+      s_slot[j] = sg.slot;
+      s_cnt[j] = 0;
+    }
+    __syncthreads();
+    int32_t rw[kEdgesPerThread];
+    int own[kEdgesPerThread];
+#pragma unroll
+    for (int kk = 0; kk < kEdgesPerThread; kk++) {
+      const int rel = kk * kBlock + (int)threadIdx.x;
+      own[kk] = -1;
+      rw[kk] = 0;
+      if (e0 + rel < e1) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
+        }
+        const int32_t w = a.nbr[s_row[lo] + (rel - s_start[lo])];
+        rw[kk] = a.vr[(int64_t)s_slot[lo] * a.n + w].rank;
+        own[kk] = lo;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < kEdgesPerThread; kk++)
+      if (own[kk] >= 0 && rw[kk] != 0 && rw[kk] < s_own[own[kk]]) atomicAdd(&s_cnt[own[kk]], 1);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kBlock)
+      if (s_cnt[j] != 0) atomicAdd(&a.scnt[i0 + j], s_cnt[j]);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool b_cand_better(long long oc, long long od, long long ok,
+                                              long long xc, long long xd, long long xk) {
+  if (ok <= 0) return false;
+  if (xk <= 0) return true;
+  if (ratio_lt(oc, od, xc, xd)) return true;
+  return !ratio_lt(xc, xd, oc, od) && ok < xk;
+}
+
+// One workgroup per segment: exact argmin of cut/min(vol, 2m - vol).
+__global__ __launch_bounds__(kBlock) void k_sw_argmin(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int s = blockIdx.x;
+  if (s >= c->sw_nseg) return;
+  const SweepSeg sg = a.segs[s];
+  const long long off = sg.elem_off;
+  const long long bv = off > 0 ? a.svol[off - 1] : 0;
+  const long long bc = off > 0 ? a.scut[off - 1] : 0;
+  const long long vt = a.vol_total;
+  __shared__ long long s_c[kBlock], s_d[kBlock], s_k[kBlock];
+  long long mc = -1, md = 1, mk = 0;
+  for (int i = threadIdx.x; i < sg.n_elem; i += kBlock) {
+    const long long cut = a.scut[off + i] - bc;
+    const long long vol = a.svol[off + i] - bv;
+    const long long den = vol < vt - vol ? vol : vt - vol;
+    if (den > 0 && b_cand_better(cut, den, i + 1, mc, md, mk)) { mc = cut; md = den; mk = i + 1; }
+  }
+  s_c[threadIdx.x] = mc; s_d[threadIdx.x] = md; s_k[threadIdx.x] = mk;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const int u = threadIdx.x + o;
+      if (b_cand_better(s_c[u], s_d[u], s_k[u], s_c[threadIdx.x], s_d[threadIdx.x],
+                        s_k[threadIdx.x])) {
+        s_c[threadIdx.x] = s_c[u];
+        s_d[threadIdx.x] = s_d[u];
+        s_k[threadIdx.x] = s_k[u];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    Slot& S = a.slots[sg.slot];
+    const long long k = s_k[0];
+    S.kstar = k > 0 ? k : 0;
+    S.best_cut = k > 0 ? s_c[0] : 0;
+    S.best_den = k > 0 ? s_d[0] : 0;
+    S.best_vol = k > 0 ? a.svol[off + k - 1] - bv : 0;
+    S.phi = k > 0 ? (double)s_c[0] / (double)s_d[0] : 0.0;
+  }
+}
+
+// Gather the nonzeros of r of every swept query and reset its slot state.
+__global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int nseg = c->sw_nseg;
+  const long long total = c->sw_touch_total;
+  __shared__ long long s_toff[kMaxSlots];
+  __shared__ int s_cnt[kBlock], s_base[kBlock];
+  __shared__ int s_lo;
+  for (int j = threadIdx.x; j < nseg; j += kBlock) s_toff[j] = a.segs[j].touch_off;
+  __syncthreads();
+  for (long long x0 = (long long)blockIdx.x * kBlock; x0 < total; x0 += (long long)gridDim.x * kBlock) {
+    if (threadIdx.x == 0) s_lo = seg_of(s_toff, nseg, x0);
+    s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int slo = s_lo;
+    const long long x = x0 + threadIdx.x;
+    int s = -1, rk = -1;
+    int32_t v = 0;
+    double rv = 0.0;
+    if (x < total) {
+      s = seg_of(s_toff, nseg, x);
+      const SweepSeg& sg = a.segs[s];
+      const int64_t base = (int64_t)sg.slot * a.n;
+      v = a.touched[base + (x - s_toff[s])];
+      VRec* rec = a.vr + base + v;
+      rv = rec->r;
+      rec->r = 0.0;
+      rec->rank = 0;
+      a.p[base + v] = 0.0;
+      if (rv != 0.0) rk = atomicAdd(&s_cnt[s - slo], 1);  // s - slo < kBlock
+    }
+    __syncthreads();
+    {
+      const int j = threadIdx.x;
+      if (slo + j < nseg && s_cnt[j] > 0)
+        s_base[j] = atomicAdd(&a.slots[a.segs[slo + j].slot].rnnz, s_cnt[j]);
+    }
+    __syncthreads();
+    if (rk >= 0) {
+      const SweepSeg& sg = a.segs[s];
+      const long long pos = (long long)s_base[s - slo] + rk;
+      if (pos >= sg.n_touch) c->fault = 1;
+      else if (sg.out_rid) { sg.out_rid[pos] = v; sg.out_rval[pos] = rv; }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_batch_init(hipStream_t s, const BatchArgs& a) {
+  int grid = (int)((a.n + kBlock - 1) / kBlock);
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_b_init, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_b_admit, dim3(1), dim3(256), 0, s, a, adm, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self) {
+  hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kMaxSlots), 0, s, a);
+  hipLaunchKernelGGL(k_b_self, dim3(grid_self), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter) {
+  hipLaunchKernelGGL(k_b_scatter, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_round_end(hipStream_t s, const BatchArgs& a) {
+  hipLaunchKernelGGL(k_b_round_end, dim3(1), dim3(kMaxSlots), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
+                              int grid) {
+  if (nseg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sw_keys, dim3(grid), dim3(kBlock), 0, s, a);
+  SortArgs sa;
+  sa.buf[0] = a.sbuf[0];
+  sa.buf[1] = a.sbuf[1];
+  sa.count = &a.ctl->sw_total;
+  sa.flip = &a.ctl->sort_flip;
+  sa.done = &a.ctl->done[0];
+  sa.active = nullptr;
+  sa.active_value = 0;
+  hipError_t e = launch_sort(s, sa, max_elems, grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sw_rank, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_scan<false>, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_count, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_scan<true>, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_argmin, dim3(nseg), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_finish, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace plc

@@ -15,7 +15,9 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstddef>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <new>
 #include <set>
@@ -24,6 +26,7 @@
 
 #include "../../include/plc.h"
 #include "arena.h"
+#include "batch_device.h"
 #include "plc_device.h"
 
 using plc::Arena;
@@ -52,6 +55,32 @@ struct KTime {
   int64_t entries = 0;
 };
 
+enum { HS_FREE = 0, HS_RUN = 1, HS_PUSHED = 2, HS_SWEEP = 3 };
+
+struct SweepHdr {
+  int32_t nseg;
+  int32_t total;
+  long long touch_total;
+};
+
+// Host side of a graph's batch engine.
+struct BatchEngine {
+  int B = 0;
+  plc::BatchArgs args{};
+  std::vector<void*> blocks;
+  plc::Slot* slots_h = nullptr;      // pinned mirror of the slot array
+  plc::SweepSeg* segs_h = nullptr;   // pinned sweep plan
+  plc::Admit* adm_h = nullptr;       // pinned admission list
+  plc::Admit* adm_d = nullptr;       // device admission list
+  plc::BatchCtl* ctl_h = nullptr;    // pinned mirror of the control block
+  SweepHdr* hdr_h = nullptr;         // pinned sweep header
+  std::vector<int> state;            // HS_*
+  std::vector<uint64_t> qid;
+  std::vector<Result> sweeping;      // result blocks filled by the sweep in flight
+  std::deque<std::pair<uint64_t, plc_query>> queue;
+  size_t bytes = 0;
+};
+
 }  // namespace
 
 struct plc_graph {
@@ -61,6 +90,7 @@ struct plc_graph {
   std::vector<void*> blocks;
   std::vector<int32_t> deg;  // host copy of degrees, for query validation
   PlainArgs args{};
+  BatchEngine* batch = nullptr;
 };
 
 struct plc_ctx {
@@ -70,6 +100,7 @@ struct plc_ctx {
   plc_options opt{};
   Ctl* ctl_host = nullptr;  // pinned
   std::map<uint64_t, Result> results;
+  std::set<uint64_t> inflight;  // submitted to a batch engine, not finished
   uint64_t next_id = 1;
   bool broken = false;
   std::set<plc_graph*> graphs;
@@ -136,6 +167,8 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
   return PLC_OK;
 }
 
+static void batch_free(plc_ctx* ctx, plc_graph* g);
+
 static void free_events(plc_ctx* c) {
   for (auto& e : c->ev_scatter) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
   for (auto& e : c->ev_self) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
@@ -149,7 +182,10 @@ extern "C" plc_status plc_destroy(plc_ctx* ctx) {
   if (!ctx) return PLC_E_INVALID;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (plc_graph* g : ctx->graphs) delete g;
+  for (plc_graph* g : ctx->graphs) {
+    batch_free(ctx, g);
+    delete g;
+  }
   free_events(ctx);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   delete ctx;
@@ -242,7 +278,6 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   const size_t N = (size_t)n;
   const size_t nscan = N / plc::kScanBlock + 2;
   const size_t ntile = (size_t)num_arcs / plc::kEdgeTile + 2;
-  const size_t nsort = N / plc::kSortTile + 2;
   PlainArgs& a = g->args;
   a.n = n;
   a.vol_total = num_arcs;
@@ -257,27 +292,22 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.estart = static_cast<int64_t*>(take(8 * N));
   a.rowp = static_cast<int64_t*>(take(8 * N));
   a.tile_start = static_cast<int32_t*>(take(4 * ntile));
+  a.tile_cap = (int64_t)ntile;
+  a.desc_cap = (int32_t)nscan;
   for (int s = 0; s < plc::NUM_SCANS; s++)
-    a.desc[s] = static_cast<plc::ScanDesc*>(take(sizeof(plc::ScanDesc) * nscan));
+    a.desc[s] = static_cast<unsigned long long*>(take(2 * 8 * nscan));
   a.support = static_cast<int32_t*>(take(4 * N));
   a.touched = static_cast<int32_t*>(take(4 * N));
-  a.keyA = static_cast<unsigned long long*>(take(8 * N));
-  a.keyB = static_cast<unsigned long long*>(take(8 * N));
-  a.idA = static_cast<int32_t*>(take(4 * N));
-  a.idB = static_cast<int32_t*>(take(4 * N));
-  a.hist = static_cast<uint32_t*>(take(4 * 256 * nsort));
+  a.sbuf[0] = static_cast<plc::SortElem*>(take(sizeof(plc::SortElem) * N));
+  a.sbuf[1] = static_cast<plc::SortElem*>(take(sizeof(plc::SortElem) * N));
   a.sdeg = static_cast<int32_t*>(take(4 * N));
   a.svol = static_cast<int64_t*>(take(8 * N));
   a.scnt = static_cast<int32_t*>(take(4 * N));
   a.sp = static_cast<double*>(take(8 * N));
+  a.sid = static_cast<int32_t*>(take(4 * N));
   a.rid = static_cast<int32_t*>(take(4 * N));
   a.rval = static_cast<double*>(take(8 * N));
   a.bbest = static_cast<long long*>(take(24 * nscan));
-  a.hist_tiles = (int32_t)nsort;
-  a.tile_cap = (int64_t)ntile;
-  int bits = 1;
-  while (bits < 31 && ((int64_t)1 << bits) < n) bits++;
-  a.id_bits = bits;
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -298,7 +328,7 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
     return fail();
   if (hipMemsetAsync(a.ctl, 0, sizeof(Ctl), s) != hipSuccess) return fail();
   for (int k = 0; k < plc::NUM_SCANS; k++)
-    if (hipMemsetAsync(a.desc[k], 0, sizeof(plc::ScanDesc) * nscan, s) != hipSuccess) return fail();
+    if (hipMemsetAsync(a.desc[k], 0, 2 * 8 * nscan, s) != hipSuccess) return fail();
   if (plc::launch_graph_init(s, a) != hipSuccess) return fail();
   if (hipStreamSynchronize(s) != hipSuccess) return fail();
   ctx->graphs.insert(g);
@@ -310,6 +340,7 @@ extern "C" plc_status plc_graph_free(plc_ctx* ctx, plc_graph* g) {
   if (!ctx || !g || !ctx->graphs.count(g)) return PLC_E_INVALID;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  batch_free(ctx, g);
   graph_release_blocks(ctx, g);
   ctx->graphs.erase(g);
   delete g;
@@ -397,7 +428,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   // Next query starts with a chunk that covers this one's rounds.
   ctx->chunk_rounds = std::min(256, std::max(4, h.round + 2));
-  if (h.overflow) {
+  if (h.fault) {
     ctx->broken = true;
     return PLC_E_HIP;
   }
@@ -450,7 +481,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     res.p = reinterpret_cast<double*>(b + off_p);
     res.rid = reinterpret_cast<int32_t*>(b + off_rid);
     res.rval = reinterpret_cast<double*>(b + off_rval);
-    const int32_t* sorted = h.sort_flip ? a.idB : a.idA;
+    const int32_t* sorted = a.sid;
     if (N) {
       HIPCHK(ctx, hipMemcpyAsync(res.ids, sorted, 4 * N, hipMemcpyDeviceToDevice, s));
       HIPCHK(ctx, hipMemcpyAsync(res.p, a.sp, 8 * N, hipMemcpyDeviceToDevice, s));
@@ -498,7 +529,7 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
 extern "C" plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out) {
   if (!ctx || !out) return PLC_E_INVALID;
   auto it = ctx->results.find(id);
-  if (it == ctx->results.end()) return PLC_E_NOTFOUND;
+  if (it == ctx->results.end()) return ctx->inflight.count(id) ? PLC_E_NOTREADY : PLC_E_NOTFOUND;
   *out = it->second.info;
   return PLC_OK;
 }
@@ -570,4 +601,391 @@ extern "C" plc_status plc_timing_get(plc_ctx* ctx, plc_kernel_time* scatter, plc
   put_time(ctx->t_self, self);
   put_time(ctx->t_sweep, sweep);
   return PLC_OK;
+}
+
+// ---------------------------------------------------------------- batched path
+
+static void batch_free(plc_ctx* ctx, plc_graph* g) {
+  BatchEngine* E = g->batch;
+  if (!E) return;
+  for (void* b : E->blocks) ctx->arena.release(b);
+  for (auto& r : E->sweeping)
+    if (r.block) ctx->arena.release(r.block);
+  for (int q = 0; q < E->B; q++)
+    if (E->state[q] != HS_FREE) ctx->inflight.erase(E->qid[q]);
+  for (auto& pq : E->queue) ctx->inflight.erase(pq.first);
+  if (E->slots_h) (void)hipHostFree(E->slots_h);
+  if (E->segs_h) (void)hipHostFree(E->segs_h);
+  if (E->adm_h) (void)hipHostFree(E->adm_h);
+  if (E->ctl_h) (void)hipHostFree(E->ctl_h);
+  if (E->hdr_h) (void)hipHostFree(E->hdr_h);
+  delete E;
+  g->batch = nullptr;
+}
+
+// Round-buffer and sweep-buffer capacities (entries, edges, sort elements).
+// A single query never exceeds them (frontier <= n, edges <= 2m, support <= n),
+// so every step makes progress.
+static void batch_caps(const plc_graph* g, int B, int64_t* nf_cap, int64_t* e_cap,
+                       int64_t* s_cap) {
+  const int64_t n = g->n, arcs = std::max<int64_t>(g->arcs, 1);
+  *nf_cap = std::min<int64_t>(std::max<int64_t>(2 * n, 1 << 22), (int64_t)B * n);
+  *nf_cap = std::max<int64_t>(*nf_cap, n);
+  *nf_cap = std::min<int64_t>(*nf_cap, INT32_MAX / 2);
+  *e_cap = std::max<int64_t>(2 * arcs, 1 << 26);
+  *s_cap = std::max<int64_t>(std::min<int64_t>(2 * n, (int64_t)B * n), n);
+  *s_cap = std::min<int64_t>(*s_cap, INT32_MAX / 2);
+}
+
+static size_t batch_fixed_bytes(const plc_graph* g, int B) {
+  int64_t nf_cap, e_cap, s_cap;
+  batch_caps(g, B, &nf_cap, &e_cap, &s_cap);
+  const int64_t tile_cap = e_cap / plc::kEdgeTile + 2;
+  const int64_t desc_cap = std::max(nf_cap, s_cap) / plc::kScanBlock + 2;
+  size_t b = 0;
+  b += 28 * (size_t)nf_cap + 4 * (size_t)tile_cap + 3 * 16 * (size_t)desc_cap;
+  b += (2 * sizeof(plc::SortElem) + 4 + 8 + 4 + 8) * (size_t)s_cap;
+  b += (sizeof(plc::Slot) + sizeof(plc::SweepSeg) + sizeof(plc::Admit) + 8) * (size_t)B;
+  b += 64 * 1024;
+  return b;
+}
+
+static size_t batch_slot_bytes(const plc_graph* g) {
+  return (sizeof(plc::VRec) + 8 + 8 + 4 + 4) * (size_t)g->n;  // vr, p, 2 frontiers, support, touched
+}
+
+static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
+  BatchEngine* E = new (std::nothrow) BatchEngine();
+  if (!E) return PLC_E_NOMEM;
+  g->batch = E;
+  E->B = B;
+  int64_t nf_cap, e_cap, s_cap;
+  batch_caps(g, B, &nf_cap, &e_cap, &s_cap);
+  const int64_t tile_cap = e_cap / plc::kEdgeTile + 2;
+  const int64_t desc_cap = std::max(nf_cap, s_cap) / plc::kScanBlock + 2;
+  const size_t n = (size_t)g->n;
+  bool nomem = false;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = ctx->arena.alloc(bytes);
+    if (!p) { nomem = true; return nullptr; }
+    E->blocks.push_back(p);
+    E->bytes += (bytes + Arena::kAlign - 1) & ~(Arena::kAlign - 1);
+    return p;
+  };
+  plc::BatchArgs& a = E->args;
+  a.n = g->n;
+  a.vol_total = g->arcs;
+  a.off = g->args.off;
+  a.nbr = g->args.nbr;
+  a.B = B;
+  a.slots = static_cast<plc::Slot*>(take(sizeof(plc::Slot) * B));
+  a.vr = static_cast<plc::VRec*>(take(sizeof(plc::VRec) * n * B));
+  a.p = static_cast<double*>(take(8 * n * B));
+  a.fbuf = static_cast<int32_t*>(take(4 * 2 * n * B));
+  a.support = static_cast<int32_t*>(take(4 * n * B));
+  a.touched = static_cast<int32_t*>(take(4 * n * B));
+  a.ctl = static_cast<plc::BatchCtl*>(take(sizeof(plc::BatchCtl)));
+  a.fprefix = static_cast<int32_t*>(take(4 * ((size_t)B + 1)));
+  a.eslot = static_cast<int32_t*>(take(4 * (size_t)nf_cap));
+  a.coef = static_cast<double*>(take(8 * (size_t)nf_cap));
+  a.estart = static_cast<int64_t*>(take(8 * (size_t)nf_cap));
+  a.rowp = static_cast<int64_t*>(take(8 * (size_t)nf_cap));
+  a.nf_cap = (int32_t)nf_cap;
+  a.e_cap = e_cap;
+  a.tile_start = static_cast<int32_t*>(take(4 * (size_t)tile_cap));
+  a.tile_cap = tile_cap;
+  a.desc_cap = (int32_t)desc_cap;
+  for (int k = 0; k < plc::BNUM_SCANS; k++)
+    a.desc[k] = static_cast<unsigned long long*>(take(2 * 8 * (size_t)desc_cap));
+  a.segs = static_cast<plc::SweepSeg*>(take(sizeof(plc::SweepSeg) * B));
+  a.sbuf[0] = static_cast<plc::SortElem*>(take(sizeof(plc::SortElem) * (size_t)s_cap));
+  a.sbuf[1] = static_cast<plc::SortElem*>(take(sizeof(plc::SortElem) * (size_t)s_cap));
+  a.sdeg = static_cast<int32_t*>(take(4 * (size_t)s_cap));
+  a.svol = static_cast<int64_t*>(take(8 * (size_t)s_cap));
+  a.scnt = static_cast<int32_t*>(take(4 * (size_t)s_cap));
+  a.scut = static_cast<int64_t*>(take(8 * (size_t)s_cap));
+  a.s_cap = s_cap;
+  E->adm_d = static_cast<plc::Admit*>(take(sizeof(plc::Admit) * B));
+  if (nomem) {
+    batch_free(ctx, g);
+    return PLC_E_NOMEM;
+  }
+  E->state.assign(B, HS_FREE);
+  E->qid.assign(B, 0);
+  if (hipHostMalloc(reinterpret_cast<void**>(&E->slots_h), sizeof(plc::Slot) * B,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->segs_h), sizeof(plc::SweepSeg) * B,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->adm_h), sizeof(plc::Admit) * B,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->ctl_h), sizeof(plc::BatchCtl),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->hdr_h), sizeof(SweepHdr),
+                    hipHostMallocDefault) != hipSuccess) {
+    batch_free(ctx, g);
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, hipMemsetAsync(a.slots, 0, sizeof(plc::Slot) * B, s));
+  HIPCHK(ctx, hipMemsetAsync(a.ctl, 0, sizeof(plc::BatchCtl), s));
+  for (int k = 0; k < plc::BNUM_SCANS; k++)
+    HIPCHK(ctx, hipMemsetAsync(a.desc[k], 0, 2 * 8 * (size_t)desc_cap, s));
+  HIPCHK(ctx, plc::launch_batch_init(s, a));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return PLC_OK;
+}
+
+extern "C" plc_status plc_batch_reserve(plc_ctx* ctx, plc_graph* g, int32_t slots,
+                                        int32_t* granted) {
+  if (!ctx || !g || !ctx->graphs.count(g) || slots < 1 || slots > 1024) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  (void)hipSetDevice(ctx->device);
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  batch_free(ctx, g);
+  // Largest slot count that fits the free arena (one block per array),
+  // keeping headroom for the result blocks of finished queries.
+  int B = slots;
+  const size_t per = batch_slot_bytes(g);
+  const size_t free_now = ctx->arena.free_bytes();
+  const size_t headroom = std::max<size_t>((size_t)64 << 20, free_now / 16);
+  const size_t budget = free_now > headroom ? free_now - headroom : 0;
+  while (B > 0) {
+    size_t need = batch_fixed_bytes(g, B) + per * (size_t)B;
+    if (need <= budget) break;
+    B--;
+  }
+  while (B > 0) {
+    plc_status st = batch_create(ctx, g, B);
+    if (st == PLC_OK) break;
+    if (st != PLC_E_NOMEM) return st;
+    B = B * 3 / 4;  // fragmentation: retry smaller
+  }
+  if (granted) *granted = B;
+  return B > 0 ? PLC_OK : PLC_E_NOMEM;
+}
+
+extern "C" plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
+                                 uint64_t* ids) {
+  if (!ctx || !g || !ctx->graphs.count(g) || count < 0 || (count > 0 && !q)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  if (!g->batch) return PLC_E_INVALID;
+  plc_status first = PLC_OK;
+  for (int32_t i = 0; i < count; i++) {
+    if (!query_ok(g, q[i])) {
+      if (ids) ids[i] = 0;
+      if (first == PLC_OK) first = PLC_E_INVALID;
+      continue;
+    }
+    uint64_t id = ctx->next_id++;
+    g->batch->queue.emplace_back(id, q[i]);
+    ctx->inflight.insert(id);
+    if (ids) ids[i] = id;
+  }
+  return first;
+}
+
+static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
+  BatchEngine& E = *g->batch;
+  plc::BatchArgs& a = E.args;
+  hipStream_t s = ctx->stream;
+  // 1. admission into free slots, in submission order
+  int nadm = 0;
+  for (int q = 0; q < E.B && !E.queue.empty(); q++) {
+    if (E.state[q] != HS_FREE) continue;
+    const uint64_t id = E.queue.front().first;
+    const plc_query qq = E.queue.front().second;
+    E.queue.pop_front();
+    plc::Admit& ad = E.adm_h[nadm++];
+    ad.slot = q;
+    ad.seed = qq.seed;
+    ad.rule = (int32_t)qq.rule;
+    ad.max_rounds = ctx->opt.max_rounds;
+    ad.alpha = qq.alpha;
+    ad.eps = qq.eps;
+    ad.seed_deg = g->deg[qq.seed];
+    ad.pad = 0;
+    E.state[q] = HS_RUN;
+    E.qid[q] = id;
+  }
+  if (nadm > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(E.adm_d, E.adm_h, sizeof(plc::Admit) * nadm,
+                               hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, plc::launch_batch_admit(s, a, E.adm_d, nadm));
+  }
+  // 2. one round for every running query
+  bool any_run = false;
+  for (int q = 0; q < E.B; q++) any_run |= E.state[q] == HS_RUN;
+  if (any_run) {
+    HIPCHK(ctx, plc::launch_batch_plan_self(s, a, ctx->grid_self));
+    if (ctx->timing) {
+      if (ctx->ev_scatter.empty()) ctx->ev_scatter.emplace_back();
+      HIPCHK(ctx, ev_pair(ctx->ev_scatter[0]));
+      HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].a, s));
+    }
+    HIPCHK(ctx, plc::launch_batch_scatter(s, a, ctx->grid_scatter));
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].b, s));
+    HIPCHK(ctx, plc::launch_batch_round_end(s, a));
+  }
+  // 3. sweep the queries whose frontier emptied in an earlier step
+  int nseg = 0;
+  long long total = 0, touch_total = 0, vol_bound = 0;
+  E.sweeping.clear();
+  for (int q = 0; q < E.B; q++) {
+    if (E.state[q] != HS_PUSHED) continue;
+    const plc::Slot& S = E.slots_h[q];
+    const long long N = S.support_cnt, T = S.touched_cnt;
+    if (nseg > 0 && (total + N > a.s_cap || vol_bound + S.edges > a.e_cap)) continue;
+    Result res;
+    size_t off_p = (4 * (size_t)N + 255) & ~(size_t)255;
+    size_t off_rid = off_p + ((8 * (size_t)N + 255) & ~(size_t)255);
+    size_t off_rval = off_rid + ((4 * (size_t)T + 255) & ~(size_t)255);
+    res.block = ctx->arena.alloc(off_rval + 8 * (size_t)T);
+    plc::SweepSeg& sg = E.segs_h[nseg];
+    sg.slot = q;
+    sg.n_elem = (int32_t)N;
+    sg.elem_off = total;
+    sg.touch_off = touch_total;
+    sg.n_touch = (int32_t)T;
+    sg.pad = 0;
+    if (res.block) {
+      char* b = static_cast<char*>(res.block);
+      res.ids = reinterpret_cast<int32_t*>(b);
+      res.p = reinterpret_cast<double*>(b + off_p);
+      res.rid = reinterpret_cast<int32_t*>(b + off_rid);
+      res.rval = reinterpret_cast<double*>(b + off_rval);
+    }
+    sg.out_ids = res.ids;
+    sg.out_p = res.p;
+    sg.out_rid = res.rid;
+    sg.out_rval = res.rval;
+    E.sweeping.push_back(res);
+    E.state[q] = HS_SWEEP;
+    total += N;
+    touch_total += T;
+    vol_bound += S.edges;
+    nseg++;
+  }
+  if (nseg > 0) {
+    E.hdr_h->nseg = nseg;
+    E.hdr_h->total = (int32_t)total;
+    E.hdr_h->touch_total = touch_total;
+    HIPCHK(ctx, hipMemcpyAsync(a.segs, E.segs_h, sizeof(plc::SweepSeg) * nseg,
+                               hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, hipMemcpyAsync(reinterpret_cast<char*>(a.ctl) + offsetof(plc::BatchCtl, sw_nseg),
+                               E.hdr_h, sizeof(SweepHdr), hipMemcpyHostToDevice, s));
+    if (ctx->timing) {
+      HIPCHK(ctx, ev_pair(ctx->ev_sweep));
+      HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
+    }
+    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, a.s_cap, ctx->grid_sweep));
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
+  }
+  // 4. read back and wait
+  HIPCHK(ctx, hipMemcpyAsync(E.slots_h, a.slots, sizeof(plc::Slot) * E.B, hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipMemcpyAsync(E.ctl_h, a.ctl, sizeof(plc::BatchCtl), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (E.ctl_h->fault) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  if (ctx->timing) {
+    float ms = 0;
+    if (any_run) {
+      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_scatter[0].a, ctx->ev_scatter[0].b));
+      ctx->t_scatter.ms += ms;
+      ctx->t_scatter.launches++;
+      ctx->t_scatter.units += E.ctl_h->e_total;
+      ctx->t_scatter.entries += E.ctl_h->nf_total;
+    }
+    if (nseg > 0) {
+      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_sweep.a, ctx->ev_sweep.b));
+      ctx->t_sweep.ms += ms;
+      ctx->t_sweep.launches++;
+      ctx->t_sweep.units += E.ctl_h->sw_etotal;
+      ctx->t_sweep.entries += total;
+    }
+  }
+  // 5. retire swept queries; note the ones whose frontier emptied
+  for (int i = 0; i < nseg; i++) {
+    const int q = E.segs_h[i].slot;
+    const plc::Slot& S = E.slots_h[q];
+    Result& res = E.sweeping[i];
+    plc_result_info& info = res.info;
+    info.status = !res.block ? PLC_E_NOMEM : (S.limited ? PLC_E_LIMIT : PLC_OK);
+    info.rounds = S.rounds;
+    info.pushes = S.pushes;
+    info.edges = S.edges;
+    info.support = S.support_cnt;
+    info.kstar = S.kstar;
+    info.cut = S.best_cut;
+    info.vol = S.best_vol;
+    info.phi = S.phi;
+    info.r_nnz = S.rnnz;
+    if (S.fault) {
+      ctx->broken = true;
+      return PLC_E_HIP;
+    }
+    const uint64_t id = E.qid[q];
+    ctx->results[id] = res;
+    ctx->inflight.erase(id);
+    E.state[q] = HS_FREE;
+    E.qid[q] = 0;
+  }
+  E.sweeping.clear();
+  int running = 0;
+  for (int q = 0; q < E.B; q++) {
+    if (E.state[q] == HS_RUN && E.slots_h[q].status == plc::SL_PUSHED) E.state[q] = HS_PUSHED;
+    running += E.state[q] != HS_FREE;
+  }
+  if (in_flight) *in_flight = running + (int32_t)E.queue.size();
+  return PLC_OK;
+}
+
+extern "C" plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
+  if (!ctx || !g || !ctx->graphs.count(g)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  if (!g->batch) return PLC_E_INVALID;
+  (void)hipSetDevice(ctx->device);
+  return batch_step(ctx, g, in_flight);
+}
+
+extern "C" plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done) {
+  if (!ctx || !done) return PLC_E_INVALID;
+  if (ctx->results.count(id)) { *done = 1; return PLC_OK; }
+  if (ctx->inflight.count(id)) { *done = 0; return PLC_OK; }
+  return PLC_E_NOTFOUND;
+}
+
+extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_query* q,
+                                      int32_t count, uint64_t* ids, plc_result_info* infos) {
+  if (!ctx || !g || !ctx->graphs.count(g) || count < 0 || (count > 0 && !q)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  if (!g->batch) return PLC_E_INVALID;
+  std::vector<uint64_t> local(count > 0 ? count : 1);
+  plc_status first = plc_submit(ctx, g, q, count, local.data());
+  if (first == PLC_E_HIP) return first;
+  (void)hipSetDevice(ctx->device);
+  int32_t left = 1;
+  while (left > 0) {
+    plc_status st = batch_step(ctx, g, &left);
+    if (st != PLC_OK) return st;
+  }
+  for (int32_t i = 0; i < count; i++) {
+    if (ids) ids[i] = local[i];
+    if (infos) {
+      auto it = local[i] ? ctx->results.find(local[i]) : ctx->results.end();
+      if (it == ctx->results.end()) {
+        std::memset(&infos[i], 0, sizeof(plc_result_info));
+        infos[i].status = PLC_E_INVALID;
+      } else {
+        infos[i] = it->second.info;
+        if (infos[i].status != PLC_OK && first == PLC_OK) first = infos[i].status;
+      }
+    }
+  }
+  return first;
 }

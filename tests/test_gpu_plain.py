@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_query
+from parity import check_query, check_same
 
 pytestmark = pytest.mark.gpu
 
@@ -96,9 +96,7 @@ def test_same_query_twice_is_identical_and_state_resets(ctx):
     r1 = [ctx.result(i, release=True) for i in ids1]
     r2 = [ctx.result(i, release=True) for i in ids2][::-1]
     for a, b, s in zip(r1, r2, seeds):
-        assert a.info["rounds"] == b.info["rounds"]
-        assert np.array_equal(a.sweep_ids, b.sweep_ids)
-        assert np.allclose(a.sweep_p, b.sweep_p, rtol=1e-12, atol=0)
+        check_same(g, a, b)
         check_query(g, b, s, 0.02, 1e-6, OPT)
 
 
