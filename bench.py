@@ -1,18 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of PR-Nibble + sweep cut on one MI355X.
 
-Workload (default, "plain22"): undirected R-MAT graph (a,b,c,d) =
-(0.57,0.19,0.19,0.05), 2^22 vertices, 16 * 2^22 edge samples (avg degree ~31
-after symmetrising and removing self-loops and duplicates), int32 ids with
-int64 offsets; 16 seeds drawn uniformly from vertices of degree >= 1, run one
-after another (alpha = 0.01, eps = 1e-7, optimized push rule, FP64 p and r).
-A step is those 16 queries, each a full PR-Nibble push followed by the sweep
-cut, with the graph already resident in HBM.
+Default run (about two minutes): three workloads on synthetic undirected
+R-MAT graphs, (a,b,c,d) = (0.57,0.19,0.19,0.05), edge factor 16 (average
+degree ~31 after symmetrising and removing self-loops and duplicates),
+int32 ids, int64 offsets, FP64 p and r, optimized push rule:
 
-Prints one JSON line: pushed edges/s (value), queries/s, per-query latency
-p50/p99, the HBM-roofline fraction of the edge-scatter kernel (HIP events on
-the library's stream, summed over the timed steps), and the oracle timed on a
-bounded sample on the host as a CPU baseline.
+* plain22 (the line's `value`): 2^22 vertices, 16 seeds drawn uniformly
+  from vertices of degree >= 1, run one after another, alpha = 0.01,
+  eps = 1e-7.  A step is those 16 queries, each a full PR-Nibble push
+  followed by the sweep cut, graph resident in HBM.
+* batched22: the same graph, 256 seeds in one batch (256 slots), eps
+  log-uniform in [1e-7, 1e-5], alpha in {0.01, 0.05}; a step is the batch.
+* serve24: 2^24 vertices, seeds drawn proportionally to degree, eps
+  log-uniform in [1e-7, 1e-4], alpha = 0.01, continuous batching over 64
+  slots: the saturation rate (all queries queued at once) and Poisson
+  arrivals at 50% and 90% of it, with p50/p99 latency.
+
+Prints one JSON line.  The roofline object describes the edge-scatter
+kernel, timed with HIP events on the library's stream over the timed steps.
+The CPU baseline is the oracle timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -33,25 +40,163 @@ HBM_PEAK_GBS = 8000.0
 SCATTER_B_PER_EDGE = 20
 SCATTER_B_PER_ENTRY = 24
 
-WORKLOADS = {
-    # 16 seeds one after another on the 2^22 graph (plain path)
-    "plain22": dict(scale=22, ef=16, nseeds=16, alpha=0.01, eps=1e-7, batched=False),
-    # the 2^16 graph from vertex 0 of the largest component
-    "plain16": dict(scale=16, ef=8, nseeds=1, alpha=0.01, eps=1e-7, batched=False),
-    # 256 seeds in one batch on the 2^22 graph, eps log-uniform in [1e-7, 1e-5],
-    # alpha in {0.01, 0.05}
-    "batched22": dict(scale=22, ef=16, nseeds=256, eps_lo=1e-7, eps_hi=1e-5, batched=True,
-                      slots=256),
-}
-
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def percentile(xs, q):
+def pct(xs, q):
     import numpy as np
-    return float(np.percentile(np.asarray(xs), q)) if xs else None
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def roofline(tm):
+    sc = tm["scatter"]
+    by = SCATTER_B_PER_EDGE * sc["units"] + SCATTER_B_PER_ENTRY * sc["entries"]
+    gbs = by / (sc["ms"] * 1e-3) / 1e9 if sc["ms"] > 0 else 0.0
+    return {
+        "kernel": "scatter (edgeMap UpdateNgh)", "bound": "hbm", "achieved": gbs,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+        "bytes_model": "20 B per pushed edge + 24 B per pushed vertex",
+        "launches": sc["launches"], "avg_launch_us": sc["ms"] * 1e3 / max(sc["launches"], 1),
+        "edges_per_s": sc["units"] / (sc["ms"] * 1e-3) if sc["ms"] > 0 else 0.0,
+    }
+
+
+def timed_steps(ctx, step, steps, warmup):
+    import torch
+    acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
+    for i in range(warmup):
+        step([], dict(acc))
+        log("  warmup step %d done" % i)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(lat, acc)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing_get()
+    ctx.timing(False)
+    return elapsed, lat, acc, tm
+
+
+def account(acc, infos, ids, ctx):
+    for qid, info in zip(ids, infos):
+        acc["edges"] += info["edges"]
+        acc["pushes"] += info["pushes"]
+        acc["rounds"] += info["rounds"]
+        acc["support"] += info["support"]
+        acc["queries"] += 1
+        ctx.release(qid)
+
+
+def bench_plain(plc, synth, g, steps, warmup):
+    import numpy as np
+    seeds = synth.uniform_seeds(g, 16, seed=2)
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+
+    def step(lat, acc):
+        for s in seeds:
+            q0 = time.perf_counter()
+            ids, infos = ctx.run(hg, [int(s)], 0.01, 1e-7)
+            lat.append(time.perf_counter() - q0)
+            account(acc, infos, ids, ctx)
+
+    elapsed, lat, acc, tm = timed_steps(ctx, step, steps, warmup)
+    ctx.close()
+    nq = acc["queries"]
+    return {
+        "seeds": seeds, "elapsed": elapsed, "edges_per_s": acc["edges"] / elapsed,
+        "queries_per_s": nq / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "what": "per query"},
+        "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
+        "kernels": tm, "roofline": roofline(tm),
+    }
+
+
+def bench_batched(plc, synth, g, steps, warmup, slots=256):
+    qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                      + plc.batch_arena_bytes(g.n, g.arcs, slots) + (512 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+    got = ctx.batch_reserve(hg, slots)
+
+    def step(lat, acc):
+        q0 = time.perf_counter()
+        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps)
+        lat.append(time.perf_counter() - q0)
+        account(acc, infos, ids, ctx)
+
+    elapsed, lat, acc, tm = timed_steps(ctx, step, steps, warmup)
+    ctx.close()
+    nq = acc["queries"]
+    return {
+        "queries": qs, "workload": "rmat%d_ef16_batched_256seeds" % (g.n.bit_length() - 1),
+        "slots": got, "edges_per_s": acc["edges"] / elapsed, "queries_per_s": nq / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                       "what": "per batch of 256"},
+        "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
+        "eps": [float(qs.eps.min()), float(qs.eps.max())], "alpha": [0.01, 0.05],
+        "kernels": tm, "roofline": roofline(tm),
+    }
+
+
+def bench_serving(plc, synth, scale, nq, slots=64):
+    import numpy as np
+    from paper_1604_07515_amd import serve
+    t0 = time.time()
+    g = synth.rmat(scale, 16, seed=1)
+    log("serving graph 2^%d: n=%d arcs=%d (%.1fs)" % (scale, g.n, g.arcs, time.time() - t0))
+    rng = np.random.default_rng(2)
+    seeds = synth.degree_weighted_seeds(g, nq, rng)
+    eps = 10.0 ** rng.uniform(-7, -4, nq)
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                      + plc.batch_arena_bytes(g.n, g.arcs, slots) + (1 << 30))
+    hg = ctx.load_graph(g.off, g.nbr)
+    got = ctx.batch_reserve(hg, slots)
+    serve.saturation(ctx, hg, seeds[:256], 0.01, eps[:256])  # warm-up
+    sat = serve.saturation(ctx, hg, seeds, 0.01, eps)
+    out = {"workload": "rmat%d_ef16_serving_poisson" % scale, "n": g.n, "arcs": g.arcs,
+           "slots": got, "queries_per_run": nq, "alpha": 0.01, "eps": [1e-7, 1e-4],
+           "seeds": "proportional to degree",
+           "saturation": {"queries_per_s": sat.queries_per_s,
+                          "edges_per_s": sat.edges / sat.wall_s,
+                          "p50_ms": sat.percentile_ms(50), "p99_ms": sat.percentile_ms(99)},
+           "poisson": []}
+    for frac in (0.5, 0.9):
+        qps = frac * sat.queries_per_s
+        arr = serve.poisson_arrivals(nq, qps, np.random.default_rng(3))
+        rep = serve.serve(ctx, hg, seeds, 0.01, eps, arr)
+        out["poisson"].append({"offered_qps": qps, "served_qps": rep.queries_per_s,
+                               "p50_ms": rep.percentile_ms(50), "p99_ms": rep.percentile_ms(99),
+                               "max_in_flight": rep.max_in_flight})
+        log("  poisson %.0f qps: p50 %.2f ms p99 %.2f ms" % (qps, rep.percentile_ms(50),
+                                                            rep.percentile_ms(99)))
+    ctx.close()
+    return out
+
+
+def cpu_baseline(oracle, g, work, budget):
+    """The oracle, single-threaded, on the first queries of the workload list."""
+    c0 = time.perf_counter()
+    done = e_sum = 0
+    for s, al, ep in work:
+        r = oracle.prnibble(g.off, g.nbr, int(s), float(al), float(ep))
+        oracle.sweep(g.off, g.nbr, r.p)
+        done += 1
+        e_sum += r.edges
+        if time.perf_counter() - c0 > budget:
+            break
+    ct = time.perf_counter() - c0
+    return {"value": e_sum / ct, "unit": "pushed edges/s", "cores": 1, "kind": "oracle",
+            "queries_per_s": done / ct,
+            "sample": "%d queries (the 16 plain seeds, then the batched seeds in order), "
+                      "single-threaded oracle push + sweep, %.1f s" % (done, ct)}
 
 
 def main():
@@ -59,7 +204,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="plain22", choices=sorted(WORKLOADS))
+    ap.add_argument("--only", choices=["plain", "batched", "serving"], default=None,
+                    help="run one workload only (the others are reported as skipped)")
+    ap.add_argument("--serve-scale", type=int, default=24)
+    ap.add_argument("--serve-queries", type=int, default=2048)
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
     args = ap.parse_args()
@@ -69,143 +217,63 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-
     import synth
     import paper_1604_07515_amd as plc
 
-    wl = WORKLOADS[args.workload]
     t0 = time.time()
-    g = synth.rmat(wl["scale"], wl["ef"], seed=1)
-    if wl["batched"]:
-        qs = synth.batched_queries(g, wl["nseeds"], seed=2, eps_lo=wl["eps_lo"],
-                                   eps_hi=wl["eps_hi"])
-        seeds, alphas, epss = qs.seeds, qs.alpha, qs.eps
-    else:
-        if args.workload == "plain16":
-            seeds = np.array([synth.largest_component_min_vertex(g)], np.int32)
-        else:
-            seeds = synth.uniform_seeds(g, wl["nseeds"], seed=2)
-        alphas = np.full(len(seeds), wl["alpha"])
-        epss = np.full(len(seeds), wl["eps"])
-    log("graph n=%d arcs=%d maxdeg=%d (%.1fs)" % (g.n, g.arcs, g.deg.max(), time.time() - t0))
+    g = synth.rmat(22, 16, seed=1)
+    log("graph 2^22: n=%d arcs=%d maxdeg=%d (%.1fs)" % (g.n, g.arcs, g.deg.max(), time.time() - t0))
+    want = lambda w: args.only is None or args.only == w
+    plain = bench_plain(plc, synth, g, args.steps, args.warmup) if want("plain") else None
+    if plain:
+        log("plain: %.3g edges/s, %.1f queries/s" % (plain["edges_per_s"], plain["queries_per_s"]))
+    bat = bench_batched(plc, synth, g, max(2, args.steps // 2), 1) if want("batched") else None
+    if bat:
+        log("batched: %.3g edges/s, %.1f queries/s" % (bat["edges_per_s"], bat["queries_per_s"]))
+    srv = bench_serving(plc, synth, args.serve_scale, args.serve_queries) if want("serving") else None
 
-    arena = plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20)
-    if wl["batched"]:
-        arena += plc.batch_arena_bytes(g.n, g.arcs, wl["slots"])
-    ctx = plc.Context(arena_bytes=arena, device=0)
-    hg = ctx.load_graph(g.off, g.nbr)
-    if wl["batched"]:
-        got = ctx.batch_reserve(hg, wl["slots"])
-        log("batch slots granted: %d" % got)
-
-    def step(lat, acc):
-        if wl["batched"]:
-            q0 = time.perf_counter()
-            ids, infos = ctx.run_batched(hg, seeds, alphas, epss)
-            lat.append(time.perf_counter() - q0)
-        else:
-            ids, infos = [], []
-            for s, al, ep in zip(seeds, alphas, epss):
-                q0 = time.perf_counter()
-                i1, f1 = ctx.run(hg, [int(s)], float(al), float(ep))
-                lat.append(time.perf_counter() - q0)
-                ids += i1
-                infos += f1
-        for qid, info in zip(ids, infos):
-            acc["edges"] += info["edges"]
-            acc["pushes"] += info["pushes"]
-            acc["rounds"] += info["rounds"]
-            acc["support"] += info["support"]
-            ctx.release(qid)
-
-    for i in range(args.warmup):
-        step([], {"edges": 0, "pushes": 0, "rounds": 0, "support": 0})
-        log("warmup step %d done" % i)
-    torch.cuda.synchronize()
-    ctx.timing(True)
-    lat = []
-    acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0}
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        step(lat, acc)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    tm = ctx.timing_get()
-    ctx.timing(False)
-    log("timed %d steps in %.3fs" % (args.steps, elapsed))
-
-    nq = args.steps * len(seeds)
-    edges_per_s = acc["edges"] / elapsed
-    sc = tm["scatter"]
-    scatter_bytes = SCATTER_B_PER_EDGE * sc["units"] + SCATTER_B_PER_ENTRY * sc["entries"]
-    scatter_gbs = scatter_bytes / (sc["ms"] * 1e-3) / 1e9 if sc["ms"] > 0 else 0.0
-
+    main_res = plain or bat
     out = {
         "metric": METRIC,
-        "value": edges_per_s,
+        "value": main_res["edges_per_s"] if main_res else None,
         "unit": "pushed edges/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": main_res["ms_per_step"] if main_res else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {
-            "workload": "rmat%d_ef%d_%s_%dseeds" % (wl["scale"], wl["ef"],
-                                                     "batched" if wl["batched"] else "plain",
-                                                     len(seeds)),
-            "n": g.n, "arcs": g.arcs, "rule": "optimized", "queries_per_step": len(seeds),
-            "alpha": sorted(set(float(x) for x in alphas)),
-            "eps": [float(epss.min()), float(epss.max())],
-            "path": ("batched (%d slots, one round of every query per launch)" % wl["slots"]
-                     if wl["batched"] else "plain (one query at a time)"),
-        },
-        "queries_per_s": nq / elapsed,
-        "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
-                       "what": "per batch call" if wl["batched"] else "per query"},
-        "per_query": {"edges": acc["edges"] / nq, "pushes": acc["pushes"] / nq,
-                      "rounds": acc["rounds"] / nq, "support": acc["support"] / nq},
-        "kernels": tm,
-        "roofline": {
-            "kernel": "k_scatter",
-            "bound": "hbm",
-            "achieved": scatter_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": scatter_gbs / HBM_PEAK_GBS,
-            "traffic": None,
-            "bytes_model": "20 B per pushed edge + 24 B per pushed vertex",
-            "avg_launch_us": sc["ms"] * 1e3 / max(sc["launches"], 1),
-        },
+        "config": ({"workload": "rmat22_ef16_plain_16seeds", "n": g.n, "arcs": g.arcs,
+                    "alpha": 0.01, "eps": 1e-7, "rule": "optimized", "queries_per_step": 16,
+                    "path": "plain (one query at a time)"} if plain else
+                   {"workload": bat["workload"], "n": g.n, "arcs": g.arcs}),
     }
-
+    if main_res:
+        out["queries_per_s"] = main_res["queries_per_s"]
+        out["latency_ms"] = main_res["latency_ms"]
+        out["per_query"] = main_res["per_query"]
+        out["roofline"] = main_res["roofline"]
+        out["kernels"] = main_res["kernels"]
+    if bat:
+        out["batched"] = {k: v for k, v in bat.items() if k != "queries"}
+        if plain:
+            out["batched"]["queries_per_s_vs_plain"] = bat["queries_per_s"] / plain["queries_per_s"]
+    if srv:
+        out["serving"] = srv
     if args.cpu_budget > 0:
         import oracle
-        budget = args.cpu_budget
-        c0 = time.perf_counter()
-        done, e_sum = 0, 0
-        for s, al, ep in zip(seeds, alphas, epss):
-            r = oracle.prnibble(g.off, g.nbr, int(s), float(al), float(ep))
-            oracle.sweep(g.off, g.nbr, r.p)
-            done += 1
-            e_sum += r.edges
-            if time.perf_counter() - c0 > budget:
-                break
-        ct = time.perf_counter() - c0
-        out["cpu_baseline"] = {
-            "value": e_sum / ct, "unit": "pushed edges/s", "cores": 1, "kind": "oracle",
-            "queries_per_s": done / ct,
-            "sample": "first %d of the %d seeds of one step, single-threaded oracle "
-                      "(push + sweep), %.1f s" % (done, len(seeds), ct),
-        }
+        work = []
+        if plain:
+            work += [(s, 0.01, 1e-7) for s in plain["seeds"]]
+        if bat:
+            q = bat["queries"]
+            work += list(zip(q.seeds, q.alpha, q.eps))
+        if work:
+            out["cpu_baseline"] = cpu_baseline(oracle, g, work, args.cpu_budget)
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -167,9 +167,12 @@ plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t co
  * slots, run one round for every admitted query, sweep the queries whose
  * frontier emptied in an earlier step, and retire finished queries.  Blocks
  * until the step's device work is done.  *in_flight (may be NULL) receives
- * the number of queries queued or running after the step.
+ * the number of queries queued or running after the step.  The ids of the
+ * queries that finished in this step are written to done_ids[0..*n_done)
+ * (done_ids may be NULL; at most done_cap are written, *n_done counts all).
  */
-plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight);
+plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uint64_t* done_ids,
+                        int32_t done_cap, int32_t* n_done);
 
 /* *done = 1 if query `id` has finished (its result is ready), else 0. */
 plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);

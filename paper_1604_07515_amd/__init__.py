@@ -108,7 +108,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                             C.POINTER(plc_kernel_time)], I32),
         "plc_batch_reserve": ([P, P, I32, C.POINTER(I32)], I32),
         "plc_submit": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64)], I32),
-        "plc_progress": ([P, P, C.POINTER(I32)], I32),
+        "plc_progress": ([P, P, C.POINTER(I32), C.POINTER(U64), I32, C.POINTER(I32)], I32),
         "plc_poll": ([P, U64, C.POINTER(I32)], I32),
         "plc_run_batched": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
                              C.POINTER(plc_result_info)], I32),
@@ -260,9 +260,18 @@ class Context:
             raise PlcError(rc, "plc_submit")
         return list(ids)
 
-    def progress(self, g: Graph) -> int:
+    def progress(self, g: Graph, finished: list | None = None) -> int:
+        """One global step of the batch engine; returns queries still queued or
+        running.  Ids of queries that finished in the step are appended to
+        `finished` when a list is given."""
         left = C.c_int32()
-        _check(self.lib.plc_progress(self.handle, g.handle, C.byref(left)), "plc_progress")
+        nd = C.c_int32()
+        cap = 1024
+        buf = (C.c_uint64 * cap)()
+        _check(self.lib.plc_progress(self.handle, g.handle, C.byref(left), buf, cap, C.byref(nd)),
+               "plc_progress")
+        if finished is not None:
+            finished.extend(buf[i] for i in range(min(nd.value, cap)))
         return left.value
 
     def poll(self, qid: int) -> bool:
@@ -280,6 +289,11 @@ class Context:
         if check and rc != PLC_OK:
             raise PlcError(rc, "plc_run_batched")
         return list(ids), [x.as_dict() for x in infos]
+
+    def result_info(self, qid: int) -> dict:
+        info = plc_result_info()
+        _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)), "plc_result_info_get")
+        return info.as_dict()
 
     def result(self, qid: int, release: bool = False) -> Result:
         info = plc_result_info()

@@ -788,7 +788,8 @@ extern "C" plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q,
   return first;
 }
 
-static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
+static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uint64_t* done_ids,
+                             int32_t done_cap, int32_t* n_done) {
   BatchEngine& E = *g->batch;
   plc::BatchArgs& a = E.args;
   hipStream_t s = ctx->stream;
@@ -881,7 +882,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
       HIPCHK(ctx, ev_pair(ctx->ev_sweep));
       HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
     }
-    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, a.s_cap, ctx->grid_sweep));
+    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, total, ctx->grid_sweep));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
   }
   // 4. read back and wait
@@ -932,6 +933,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
     const uint64_t id = E.qid[q];
     ctx->results[id] = res;
     ctx->inflight.erase(id);
+    if (done_ids && i < done_cap) done_ids[i] = id;
     E.state[q] = HS_FREE;
     E.qid[q] = 0;
   }
@@ -942,15 +944,17 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
     running += E.state[q] != HS_FREE;
   }
   if (in_flight) *in_flight = running + (int32_t)E.queue.size();
+  if (n_done) *n_done = nseg;
   return PLC_OK;
 }
 
-extern "C" plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight) {
-  if (!ctx || !g || !ctx->graphs.count(g)) return PLC_E_INVALID;
+extern "C" plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight,
+                                   uint64_t* done_ids, int32_t done_cap, int32_t* n_done) {
+  if (!ctx || !g || !ctx->graphs.count(g) || done_cap < 0) return PLC_E_INVALID;
   if (ctx->broken) return PLC_E_HIP;
   if (!g->batch) return PLC_E_INVALID;
   (void)hipSetDevice(ctx->device);
-  return batch_step(ctx, g, in_flight);
+  return batch_step(ctx, g, in_flight, done_ids, done_cap, n_done);
 }
 
 extern "C" plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done) {
@@ -971,7 +975,7 @@ extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_quer
   (void)hipSetDevice(ctx->device);
   int32_t left = 1;
   while (left > 0) {
-    plc_status st = batch_step(ctx, g, &left);
+    plc_status st = batch_step(ctx, g, &left, nullptr, 0, nullptr);
     if (st != PLC_OK) return st;
   }
   for (int32_t i = 0; i < count; i++) {
