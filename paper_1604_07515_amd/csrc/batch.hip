@@ -57,7 +57,7 @@ __global__ void k_b_init(BatchArgs a) {
     VRec rec;
     rec.r = 0.0;
     rec.deg = (int32_t)(a.off[v + 1] - a.off[v]);
-    rec.rank = 0;
+    rec.rank = a.hotcode[v];
     for (int q = 0; q < a.B; q++) {
       a.vr[(int64_t)q * a.n + v] = rec;
       a.p[(int64_t)q * a.n + v] = 0.0;
@@ -294,6 +294,48 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
   }
 }
 
+// Append w to slot q's next frontier and/or touched list with direct global
+// reservations (used for the few decisions taken outside the tile loop).
+__device__ __forceinline__ void b_decide_direct(const BatchArgs& a, int q, int32_t w, int32_t dw,
+                                                double old, double c, int* fault) {
+  Slot& S = a.slots[q];
+  const double thr = S.eps * (double)dw;
+  const int64_t base = (int64_t)q * a.n;
+  if (old < thr && old + c >= thr) {
+    const int nxt = S.par ^ 1;
+    long long pos = atomicAdd(&S.cnt[nxt], 1);
+    atomicAdd((unsigned long long*)&S.edge_next[nxt], (unsigned long long)dw);
+    if (pos < a.n) a.fbuf[2 * base + (int64_t)nxt * a.n + pos] = w; else *fault = 1;
+  }
+  if (__double_as_longlong(old) == 0) {
+    long long pos = atomicAdd(&S.touched_cnt, 1);
+    if (pos < a.n) a.touched[base + pos] = w; else *fault = 1;
+  }
+}
+
+// Add the LDS sums of slot hs's hot destinations to r (one atomic each) and
+// clear them.  Every thread of the workgroup must call it.
+__device__ void b_flush_hot(const BatchArgs& a, int hs, double* s_hacc, int* fault) {
+  __syncthreads();
+  if (hs >= 0) {
+    for (int j = threadIdx.x; j < kHot; j += kBlock) {
+      const double sum = s_hacc[j];
+      if (sum != 0.0) {
+        s_hacc[j] = 0.0;
+        const int32_t w = a.hot_ids[j];
+        VRec* rec = a.vr + (int64_t)hs * a.n + w;
+        const double old = unsafeAtomicAdd(&rec->r, sum);
+        b_decide_direct(a, hs, w, rec->deg, old, sum, fault);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// edgeMap over all scheduled edges.  Each workgroup takes a contiguous range
+// of tiles; contributions to hot destinations of the slot that owns the
+// current tiles are summed in LDS and flushed when the range moves to
+// another slot, and at the end.
 __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int NF = c->nf_total;
@@ -307,8 +349,15 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   __shared__ int32_t s_slot[kEdgeTile + 1];
   __shared__ int s_cfn[kSlotRange], s_ctv[kSlotRange], s_bfn[kSlotRange], s_btv[kSlotRange];
   __shared__ unsigned long long s_efn[kSlotRange];
+  __shared__ double s_hacc[kHot];
+  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
+  int hs = -1;  // slot whose hot sums s_hacc holds
+  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int tb = blockIdx.x * per;
+  const int te = tb + per < ntiles ? tb + per : ntiles;
+  __syncthreads();
 
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = tb; tile < te; tile++) {
     const long long e0 = (long long)tile * kEdgeTile;
     const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
     const int i0 = a.tile_start[tile];
@@ -318,6 +367,11 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       continue;
     }
     const int cnt = i1 - i0 + 1;
+    const int tile_hs = a.eslot[i1];
+    if (tile_hs != hs) {
+      b_flush_hot(a, hs, s_hacc, &c->fault);
+      hs = tile_hs;
+    }
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
       s_start[j] = (int32_t)(a.estart[i0 + j] - e0);
       s_row[j] = a.rowp[i0 + j];
@@ -351,16 +405,23 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
         q[k] = s_slot[lo];
       }
     }
-    int32_t dw[kEdgesPerThread];
+    int2 dr[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      dr[k] = make_int2(0, 0);
+      if (w[k] >= 0) dr[k] = *reinterpret_cast<const int2*>(&a.vr[(int64_t)q[k] * n + w[k]].deg);
+    }
     double old[kEdgesPerThread];
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
-      dw[k] = 0;
       old[k] = 0.0;
-      if (w[k] >= 0) {
-        VRec* rec = a.vr + (int64_t)q[k] * n + w[k];
-        dw[k] = rec->deg;
-        old[k] = unsafeAtomicAdd(&rec->r, cf[k]);
+      if (w[k] < 0) continue;
+      const int hj = -dr[k].y - 1;
+      if (q[k] == hs && hj >= 0 && hj < kHot) {
+        atomicAdd(&s_hacc[hj], cf[k]);  // hot destination of the current slot
+        w[k] = -1;
+      } else {
+        old[k] = unsafeAtomicAdd(&a.vr[(int64_t)q[k] * n + w[k]].r, cf[k]);
       }
     }
     // decisions: rank within (slot, list) from LDS counters, or a direct
@@ -371,29 +432,16 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       rfn[k] = -1;
       rtv[k] = -1;
       if (w[k] < 0) continue;
-      const double thr = a.slots[q[k]].eps * (double)dw[k];
-      const bool cross = old[k] < thr && old[k] + cf[k] >= thr;
-      const bool first = __double_as_longlong(old[k]) == 0;
       const int j = q[k] - qlo;
-      Slot& S = a.slots[q[k]];
-      const int nxt = S.par ^ 1;
-      const int64_t base = (int64_t)q[k] * n;
       if (j < kSlotRange) {
-        if (cross) {
+        const double thr = a.slots[q[k]].eps * (double)dr[k].x;
+        if (old[k] < thr && old[k] + cf[k] >= thr) {
           rfn[k] = atomicAdd(&s_cfn[j], 1);
-          atomicAdd(&s_efn[j], (unsigned long long)dw[k]);
+          atomicAdd(&s_efn[j], (unsigned long long)dr[k].x);
         }
-        if (first) rtv[k] = atomicAdd(&s_ctv[j], 1);
+        if (__double_as_longlong(old[k]) == 0) rtv[k] = atomicAdd(&s_ctv[j], 1);
       } else {
-        if (cross) {
-          long long pos = atomicAdd(&S.cnt[nxt], 1);
-          atomicAdd((unsigned long long*)&S.edge_next[nxt], (unsigned long long)dw[k]);
-          if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = w[k]; else c->fault = 1;
-        }
-        if (first) {
-          long long pos = atomicAdd(&S.touched_cnt, 1);
-          if (pos < n) a.touched[base + pos] = w[k]; else c->fault = 1;
-        }
+        b_decide_direct(a, q[k], w[k], dr[k].x, old[k], cf[k], &c->fault);
       }
     }
     __syncthreads();
@@ -427,6 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
     }
     __syncthreads();
   }
+  b_flush_hot(a, hs, s_hacc, &c->fault);
 }
 
 __global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
@@ -600,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
     }
 #pragma unroll
     for (int kk = 0; kk < kEdgesPerThread; kk++)
-      if (own[kk] >= 0 && rw[kk] != 0 && rw[kk] < s_own[own[kk]]) atomicAdd(&s_cnt[own[kk]], 1);
+      if (own[kk] >= 0 && rw[kk] > 0 && rw[kk] < s_own[own[kk]]) atomicAdd(&s_cnt[own[kk]], 1);
     __syncthreads();
     for (int j = threadIdx.x; j < cnt; j += kBlock)
       if (s_cnt[j] != 0) atomicAdd(&a.scnt[i0 + j], s_cnt[j]);
@@ -685,9 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
       v = a.touched[base + (x - s_toff[s])];
       VRec* rec = a.vr + base + v;
       rv = rec->r;
-      rec->r = 0.0;
-      rec->rank = 0;
-      a.p[base + v] = 0.0;
+      rec->r = 0.0;  // p and rank are non-zero on the support only (k_sw_reset)
       if (rv != 0.0) rk = atomicAdd(&s_cnt[s - slo], 1);  // s - slo < kBlock
     }
     __syncthreads();
@@ -704,6 +751,21 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
       else if (sg.out_rid) { sg.out_rid[pos] = v; sg.out_rval[pos] = rv; }
     }
     __syncthreads();
+  }
+}
+
+// Reset p and the sweep rank of every swept support vertex (after the
+// boundary counts and the argmin no longer need them).
+__global__ __launch_bounds__(kBlock) void k_sw_reset(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const long long total = c->sw_total;
+  const SortElem* el = a.sbuf[c->sort_flip & 1];
+  for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
+       k += (long long)gridDim.x * kBlock) {
+    const SortElem e = el[k];
+    const int64_t base = (int64_t)a.segs[e.seg].slot * a.n;
+    a.vr[base + e.id].rank = a.hotcode[e.id];
+    a.p[base + e.id] = 0.0;
   }
 }
 
@@ -759,6 +821,7 @@ hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64
   hipLaunchKernelGGL(k_sw_scan<true>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_argmin, dim3(nseg), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_finish, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -105,6 +105,8 @@ struct BatchArgs {
   int32_t* scnt;            // [s_cap]
   int64_t* scut;            // [s_cap]
   int64_t s_cap;
+  const int32_t* hot_ids;   // [kHot] vertex of hot index j (graph-wide)
+  const int32_t* hotcode;   // [n] -(j+1) for hot vertex j, else 0
 };
 
 // Admission record (host-written).

@@ -40,7 +40,7 @@ __global__ void k_graph_init(PlainArgs a) {
     VRec rec;
     rec.r = 0.0;
     rec.deg = (int32_t)(a.off[v + 1] - a.off[v]);
-    rec.rank = 0;
+    rec.rank = a.hotcode[v];
     a.vr[v] = rec;
     a.p[v] = 0.0;
   }
@@ -194,7 +194,19 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
   }
 }
 
-// edgeMap(G, Frontier, UpdateNgh) with the filter folded in.
+// Threshold decision for one addition of c to r[w] that returned `old`:
+// crossing appends w to the next frontier, first touch to the touched list.
+__device__ __forceinline__ void decide(double old, double c, double thr, int32_t w, int32_t* s_fn,
+                                       int* s_nfn, int32_t* s_tv, int* s_ntv) {
+  if (old < thr && old + c >= thr) s_fn[atomicAdd(s_nfn, 1)] = w;
+  if (__double_as_longlong(old) == 0) s_tv[atomicAdd(s_ntv, 1)] = w;
+}
+
+// edgeMap(G, Frontier, UpdateNgh) with the filter folded in.  Each
+// workgroup takes a contiguous range of edge tiles.  Contributions to hot
+// destinations (the highest-degree vertices, which many frontier edges hit)
+// are summed in LDS and added to r once per workgroup; every other edge is
+// one device-scope FP64 atomic.
 __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   Ctl* c = a.ctl;
   int t, nf;
@@ -205,15 +217,21 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   __shared__ double s_coef[kEdgeTile + 1];
   __shared__ int32_t s_fn[kEdgeTile];
   __shared__ int32_t s_tv[kEdgeTile];
+  __shared__ double s_hacc[kHot];
   __shared__ int s_nfn, s_ntv, s_base, s_last;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->etotal;
   const double eps = c->eps;
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
+  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
   if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
+  __syncthreads();
+  const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const int tb = blockIdx.x * per;
+  const int te = tb + per < ntiles ? tb + per : ntiles;
 
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = tb; tile < te; tile++) {
     const long long e0 = (long long)tile * kEdgeTile;
     const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
     const int i0 = a.tile_start[tile];
@@ -230,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
     }
     __syncthreads();
     // Four independent edges per thread: all neighbour loads, then all
-    // atomics, then the decisions, so the memory latencies overlap.
+    // record loads and atomics, then the decisions, so latencies overlap.
     int32_t w[kEdgesPerThread];
     double cf[kEdgesPerThread];
 #pragma unroll
@@ -248,23 +266,41 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
         cf[k] = s_coef[lo];
       }
     }
-    int32_t dw[kEdgesPerThread];
+    int2 dr[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      dr[k] = make_int2(0, 0);
+      if (w[k] >= 0) dr[k] = *reinterpret_cast<const int2*>(&a.vr[w[k]].deg);
+    }
     double old[kEdgesPerThread];
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
-      dw[k] = 0;
       old[k] = 0.0;
-      if (w[k] >= 0) {
-        dw[k] = a.vr[w[k]].deg;
+      if (w[k] < 0) continue;
+      const int hj = -dr[k].y - 1;
+      if (hj >= 0 && hj < kHot) {
+        atomicAdd(&s_hacc[hj], cf[k]);  // hot: combined in LDS
+        w[k] = -1;
+      } else {
         old[k] = unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]);
       }
     }
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) {
-      if (w[k] >= 0) {
-        const double thr = eps * (double)dw[k];
-        if (old[k] < thr && old[k] + cf[k] >= thr) s_fn[atomicAdd(&s_nfn, 1)] = w[k];
-        if (__double_as_longlong(old[k]) == 0) s_tv[atomicAdd(&s_ntv, 1)] = w[k];
+    for (int k = 0; k < kEdgesPerThread; k++)
+      if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dr[k].x, w[k], s_fn, &s_nfn, s_tv, &s_ntv);
+    block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
+    block_flush(&c->touched_cnt, a.touched, a.n, s_tv, &s_ntv, &s_base, &c->fault);
+  }
+  // flush the hot sums: one atomic per hot destination this workgroup hit,
+  // kEdgeTile entries at a time (the size of the LDS append lists)
+  __syncthreads();
+  for (int j0 = 0; j0 < kHot; j0 += kEdgeTile) {
+    for (int j = j0 + threadIdx.x; j < j0 + kEdgeTile; j += kBlock) {
+      const double sum = s_hacc[j];
+      if (sum != 0.0) {
+        const int32_t w = a.hot_ids[j];
+        const double old = unsafeAtomicAdd(&a.vr[w].r, sum);
+        decide(old, sum, eps * (double)a.vr[w].deg, w, s_fn, &s_nfn, s_tv, &s_ntv);
       }
     }
     block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
@@ -428,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_count(PlainArgs a) {
     }
 #pragma unroll
     for (int kk = 0; kk < kEdgesPerThread; kk++) {
-      if (own[kk] >= 0 && rw[kk] != 0 && rw[kk] < i0 + own[kk] + 1) atomicAdd(&s_cnt[own[kk]], 1);
+      if (own[kk] >= 0 && rw[kk] > 0 && rw[kk] < i0 + own[kk] + 1) atomicAdd(&s_cnt[own[kk]], 1);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < cnt; j += kBlock)
@@ -584,14 +620,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   }
 }
 
-// Reset the dense per-vertex state of every touched vertex.
+// Reset the dense per-vertex state: r of every touched vertex; p and the
+// sweep rank (back to the hot code) of every support vertex.
 __global__ __launch_bounds__(kBlock) void k_cleanup(PlainArgs a) {
   Ctl* c = a.ctl;
   const int T = (int64_t)c->touched_cnt > a.n ? (int)a.n : c->touched_cnt;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < T; i += gridDim.x * kBlock) {
-    int32_t v = a.touched[i];
-    a.vr[v].r = 0.0;
-    a.vr[v].rank = 0;
+  const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < T; i += gridDim.x * kBlock)
+    a.vr[a.touched[i]].r = 0.0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    int32_t v = a.support[i];
+    a.vr[v].rank = a.hotcode[v];
     a.p[v] = 0.0;
   }
 }

@@ -89,6 +89,7 @@ struct plc_graph {
   size_t bytes = 0;
   std::vector<void*> blocks;
   std::vector<int32_t> deg;  // host copy of degrees, for query validation
+  std::vector<int32_t> hotcode_h;  // staging for the hot codes at load
   PlainArgs args{};
   BatchEngine* batch = nullptr;
 };
@@ -308,6 +309,10 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.rid = static_cast<int32_t*>(take(4 * N));
   a.rval = static_cast<double*>(take(8 * N));
   a.bbest = static_cast<long long*>(take(24 * nscan));
+  int32_t* hot_ids = static_cast<int32_t*>(take(4 * (size_t)plc::kHot));
+  int32_t* hotcode = static_cast<int32_t*>(take(4 * N));
+  a.hot_ids = hot_ids;
+  a.hotcode = hotcode;
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -326,6 +331,30 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
       hipMemcpyAsync((void*)a.nbr, nbrs, 4 * (size_t)num_arcs, hipMemcpyHostToDevice, s) !=
           hipSuccess)
     return fail();
+  // Hot destinations: the kHot highest-degree vertices (degree >= 32, ties by
+  // id).  Their hot index lives in the idle rank field of the state record.
+  {
+    std::vector<int32_t> order(N);
+    for (size_t v = 0; v < N; v++) order[v] = (int32_t)v;
+    const size_t H = std::min<size_t>(N, (size_t)plc::kHot);
+    auto by_deg = [&](int32_t x, int32_t y) {
+      return g->deg[x] != g->deg[y] ? g->deg[x] > g->deg[y] : x < y;
+    };
+    std::partial_sort(order.begin(), order.begin() + H, order.end(), by_deg);
+    g->hotcode_h.assign(N, 0);
+    std::vector<int32_t> ids(plc::kHot, 0);
+    for (size_t j = 0; j < H && g->deg[order[j]] >= 32; j++) {
+      ids[j] = order[j];
+      g->hotcode_h[order[j]] = -(int32_t)(j + 1);
+    }
+    if (hipMemcpyAsync(hot_ids, ids.data(), 4 * (size_t)plc::kHot, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(hotcode, g->hotcode_h.data(), 4 * N, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail();
+    if (hipStreamSynchronize(s) != hipSuccess) return fail();
+    g->hotcode_h.clear();
+    g->hotcode_h.shrink_to_fit();
+  }
   if (hipMemsetAsync(a.ctl, 0, sizeof(Ctl), s) != hipSuccess) return fail();
   for (int k = 0; k < plc::NUM_SCANS; k++)
     if (hipMemsetAsync(a.desc[k], 0, 2 * 8 * nscan, s) != hipSuccess) return fail();
@@ -677,6 +706,8 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   a.vol_total = g->arcs;
   a.off = g->args.off;
   a.nbr = g->args.nbr;
+  a.hot_ids = g->args.hot_ids;
+  a.hotcode = g->args.hotcode;
   a.B = B;
   a.slots = static_cast<plc::Slot*>(take(sizeof(plc::Slot) * B));
   a.vr = static_cast<plc::VRec*>(take(sizeof(plc::VRec) * n * B));

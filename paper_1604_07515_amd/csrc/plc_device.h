@@ -24,7 +24,8 @@ namespace plc {
 struct __align__(16) VRec {
   double r;      // residual; +0.0 = never touched by this query, -0.0 = pushed (optimized rule)
   int32_t deg;   // d(v), constant for the graph
-  int32_t rank;  // sweep rank 1..N while a sweep runs, 0 otherwise
+  int32_t rank;  // sweep rank 1..N while a sweep runs; otherwise the hot code:
+                 // -(j+1) for hot vertex j (see hot_ids), 0 for the others
 };
 
 // Query status in the control block.  ST_PUSH: rounds in progress (done when
@@ -100,6 +101,9 @@ struct PlainArgs {
   int32_t* rid;        // r nonzero ids
   double* rval;        // r nonzero values
   long long* bbest;    // per-block argmin candidates (cut, den, k)
+  // hot destinations: the highest-degree vertices, combined in LDS by the scatter
+  const int32_t* hot_ids;  // [kHot] vertex of hot index j
+  const int32_t* hotcode;  // [n] -(j+1) or 0, restored into VRec::rank after a sweep
 };
 
 // Launch configuration.
@@ -108,6 +112,8 @@ constexpr int kScanItems = 4;                    // items per thread in scan-typ
 constexpr int kScanBlock = kBlock * kScanItems;  // items per scan block
 constexpr int kEdgeTile = 1024;                  // edges per scatter / cut tile
 constexpr int kEdgesPerThread = kEdgeTile / kBlock;
+constexpr int kHot = 2048;                       // hot destinations combined in LDS
+static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
