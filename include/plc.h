@@ -177,7 +177,9 @@ plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uint64_t
 /* *done = 1 if query `id` has finished (its result is ready), else 0. */
 plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);
 
-/* Submit `count` queries and step g's batch engine until all have finished. */
+/* Submit `count` queries and step g's batch engine until all have finished.
+ * Throughput mode: queries that finish pushing while others still push are
+ * swept together later (unless queued queries wait for their slots). */
 plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
                            uint64_t* ids, plc_result_info* infos);
 

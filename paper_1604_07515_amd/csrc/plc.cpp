@@ -819,8 +819,11 @@ extern "C" plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q,
   return first;
 }
 
+// One global step.  defer_sweep: while other queries are still pushing and
+// none waits for a slot, leave finished queries unswept so that they are
+// swept together later (fewer, larger sweeps: throughput mode).
 static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uint64_t* done_ids,
-                             int32_t done_cap, int32_t* n_done) {
+                             int32_t done_cap, int32_t* n_done, bool defer_sweep) {
   BatchEngine& E = *g->batch;
   plc::BatchArgs& a = E.args;
   hipStream_t s = ctx->stream;
@@ -866,7 +869,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   int nseg = 0;
   long long total = 0, touch_total = 0, vol_bound = 0;
   E.sweeping.clear();
-  for (int q = 0; q < E.B; q++) {
+  const bool hold = defer_sweep && any_run && E.queue.empty();
+  for (int q = 0; q < E.B && !hold; q++) {
     if (E.state[q] != HS_PUSHED) continue;
     const plc::Slot& S = E.slots_h[q];
     const long long N = S.support_cnt, T = S.touched_cnt;
@@ -985,7 +989,7 @@ extern "C" plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_fligh
   if (ctx->broken) return PLC_E_HIP;
   if (!g->batch) return PLC_E_INVALID;
   (void)hipSetDevice(ctx->device);
-  return batch_step(ctx, g, in_flight, done_ids, done_cap, n_done);
+  return batch_step(ctx, g, in_flight, done_ids, done_cap, n_done, false);
 }
 
 extern "C" plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done) {
@@ -1006,7 +1010,7 @@ extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_quer
   (void)hipSetDevice(ctx->device);
   int32_t left = 1;
   while (left > 0) {
-    plc_status st = batch_step(ctx, g, &left, nullptr, 0, nullptr);
+    plc_status st = batch_step(ctx, g, &left, nullptr, 0, nullptr, true);
     if (st != PLC_OK) return st;
   }
   for (int32_t i = 0; i < count; i++) {
