@@ -98,6 +98,9 @@ def bench_plain(plc, synth, g, steps, warmup):
     seeds = synth.uniform_seeds(g, 16, seed=2)
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
+    tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
+    log("  plain launch shapes: self %d, scatter %d, sweep %d workgroups (%d tried)" % (
+        tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"], tune["candidates"]))
 
     def step(lat, acc):
         for s in seeds:
@@ -115,6 +118,7 @@ def bench_plain(plc, synth, g, steps, warmup):
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "what": "per query"},
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
         "kernels": tm, "roofline": roofline(tm),
+        "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep")},
     }
 
 
@@ -124,6 +128,9 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256):
                       + plc.batch_arena_bytes(g.n, g.arcs, slots) + (512 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
+    tune = ctx.autotune(hg, qs.seeds, qs.alpha, qs.eps, plc.PLC_TUNE_BATCH)
+    log("  batched launch shapes: self %d, scatter %d workgroups (%d tried)" % (
+        tune["batch_self"], tune["batch_scatter"], tune["candidates"]))
 
     def step(lat, acc):
         q0 = time.perf_counter()
@@ -143,6 +150,7 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256):
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
         "eps": [float(qs.eps.min()), float(qs.eps.max())], "alpha": [0.01, 0.05],
         "kernels": tm, "roofline": roofline(tm),
+        "launch_shapes": {k: tune[k] for k in ("batch_self", "batch_scatter", "batch_sweep")},
     }
 
 
@@ -159,6 +167,7 @@ def bench_serving(plc, synth, scale, nq, slots=64):
                       + plc.batch_arena_bytes(g.n, g.arcs, slots) + (1 << 30))
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
+    ctx.autotune(hg, seeds[:128], 0.01, eps[:128], plc.PLC_TUNE_BATCH)
     serve.saturation(ctx, hg, seeds[:256], 0.01, eps[:256])  # warm-up
     sat = serve.saturation(ctx, hg, seeds, 0.01, eps)
     out = {"workload": "rmat%d_ef16_serving_poisson" % scale, "n": g.n, "arcs": g.arcs,

@@ -183,6 +183,30 @@ plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);
 plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
                            uint64_t* ids, plc_result_info* infos);
 
+/*
+ * Launch-shape autotuner.  Runs the `count` sample queries (their results are
+ * discarded) under candidate launch shapes and keeps, for graph g, the
+ * fastest by wall time: for the plain path (which = PLC_TUNE_PLAIN) the
+ * workgroup counts of the vertexMap, edgeMap and sweep kernels; for the
+ * batched path (PLC_TUNE_BATCH, needs plc_batch_reserve first) the
+ * workgroup counts of its vertexMap and edgeMap kernels.  The edgeMap
+ * kernels give each workgroup a contiguous range of 1024-edge tiles, so the
+ * workgroup count sets the frontier tiling.  out (may be NULL) receives the
+ * chosen shapes.
+ */
+#define PLC_TUNE_PLAIN 1
+#define PLC_TUNE_BATCH 2
+typedef struct {
+  int32_t plain_self, plain_scatter, plain_sweep;   /* workgroups per launch */
+  int32_t batch_self, batch_scatter, batch_sweep;
+  double plain_ms, batch_ms;                        /* best sample wall time */
+  int32_t candidates;                               /* shapes tried */
+  int32_t reserved;
+} plc_tune;
+
+plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* sample, int32_t count,
+                        int32_t which, plc_tune* out);
+
 /* Summary of a finished query. PLC_E_NOTFOUND for unknown ids,
  * PLC_E_NOTREADY for queries still in flight. */
 plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);

@@ -33,7 +33,8 @@ PLC_GRAPH_VALIDATE = 1
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
            "plc_graph_info_get", "plc_run", "plc_result_info_get", "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
-           "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_run_batched")
+           "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_run_batched",
+           "plc_autotune")
 
 
 class PlcError(RuntimeError):
@@ -65,6 +66,21 @@ class plc_result_info(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PLC_TUNE_PLAIN = 1
+PLC_TUNE_BATCH = 2
+
+
+class plc_tune(C.Structure):
+    _fields_ = [("plain_self", C.c_int32), ("plain_scatter", C.c_int32),
+                ("plain_sweep", C.c_int32), ("batch_self", C.c_int32),
+                ("batch_scatter", C.c_int32), ("batch_sweep", C.c_int32),
+                ("plain_ms", C.c_double), ("batch_ms", C.c_double),
+                ("candidates", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class plc_kernel_time(C.Structure):
@@ -112,6 +128,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "plc_poll": ([P, U64, C.POINTER(I32)], I32),
         "plc_run_batched": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
                              C.POINTER(plc_result_info)], I32),
+        "plc_autotune": ([P, P, C.POINTER(plc_query), I32, I32, C.POINTER(plc_tune)], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -289,6 +306,14 @@ class Context:
         if check and rc != PLC_OK:
             raise PlcError(rc, "plc_run_batched")
         return list(ids), [x.as_dict() for x in infos]
+
+    def autotune(self, g: Graph, seeds, alpha, eps, which: int, rule=PLC_RULE_OPT) -> dict:
+        """Pick launch shapes for graph g from a sample of queries (results discarded)."""
+        qa = self.queries(seeds, alpha, eps, rule)
+        out = plc_tune()
+        _check(self.lib.plc_autotune(self.handle, g.handle, qa, len(qa), which, C.byref(out)),
+               "plc_autotune")
+        return out.as_dict()
 
     def result_info(self, qid: int) -> dict:
         info = plc_result_info()

@@ -91,6 +91,9 @@ struct plc_graph {
   std::vector<int32_t> deg;  // host copy of degrees, for query validation
   std::vector<int32_t> hotcode_h;  // staging for the hot codes at load
   PlainArgs args{};
+  // launch shapes (workgroups per launch); 0 = context default
+  int plain_self = 0, plain_scatter = 0, plain_sweep = 0;
+  int batch_self = 0, batch_scatter = 0, batch_sweep = 0;
   BatchEngine* batch = nullptr;
 };
 
@@ -404,8 +407,13 @@ static hipError_t ev_pair(EventPair& e) {
 }
 
 // Queue `rounds` rounds; with timing on, bracket each kernel with events.
-static hipError_t queue_rounds(plc_ctx* ctx, const PlainArgs& a, int first, int rounds) {
+static int shape(int tuned, int dflt) { return tuned > 0 ? tuned : dflt; }
+
+static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int first, int rounds) {
+  const PlainArgs& a = g->args;
   hipStream_t s = ctx->stream;
+  const int gs = shape(g->plain_self, ctx->grid_self);
+  const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   for (int i = 0; i < rounds; i++) {
     hipError_t r;
     if (ctx->timing) {
@@ -415,14 +423,14 @@ static hipError_t queue_rounds(plc_ctx* ctx, const PlainArgs& a, int first, int 
       if ((r = ev_pair(ctx->ev_self[k])) != hipSuccess) return r;
       if ((r = ev_pair(ctx->ev_scatter[k])) != hipSuccess) return r;
       (void)hipEventRecord(ctx->ev_self[k].a, s);
-      if ((r = plc::launch_self(s, a, ctx->grid_self)) != hipSuccess) return r;
+      if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
       (void)hipEventRecord(ctx->ev_self[k].b, s);
       (void)hipEventRecord(ctx->ev_scatter[k].a, s);
-      if ((r = plc::launch_scatter(s, a, ctx->grid_scatter)) != hipSuccess) return r;
+      if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
       (void)hipEventRecord(ctx->ev_scatter[k].b, s);
     } else {
-      if ((r = plc::launch_self(s, a, ctx->grid_self)) != hipSuccess) return r;
-      if ((r = plc::launch_scatter(s, a, ctx->grid_scatter)) != hipSuccess) return r;
+      if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
+      if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
     }
   }
   return hipSuccess;
@@ -438,13 +446,13 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   int chunk = std::max(2, ctx->chunk_rounds);
   Ctl& h = *ctx->ctl_host;
   for (;;) {
-    HIPCHK(ctx, queue_rounds(ctx, a, queued, chunk));
+    HIPCHK(ctx, queue_rounds(ctx, g, queued, chunk));
     queued += chunk;
     if (ctx->timing) {
       HIPCHK(ctx, ev_pair(ctx->ev_sweep));
       HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
     }
-    HIPCHK(ctx, plc::launch_sweep(s, a, ctx->grid_sweep));
+    HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
@@ -520,7 +528,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       HIPCHK(ctx, hipMemcpyAsync(res.rval, a.rval, 8 * R, hipMemcpyDeviceToDevice, s));
     }
   }
-  HIPCHK(ctx, plc::launch_cleanup(s, a, ctx->grid_sweep));
+  HIPCHK(ctx, plc::launch_cleanup(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
   uint64_t id = ctx->next_id++;
   ctx->results[id] = res;
   if (id_out) *id_out = id;
@@ -855,13 +863,13 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   bool any_run = false;
   for (int q = 0; q < E.B; q++) any_run |= E.state[q] == HS_RUN;
   if (any_run) {
-    HIPCHK(ctx, plc::launch_batch_plan_self(s, a, ctx->grid_self));
+    HIPCHK(ctx, plc::launch_batch_plan_self(s, a, shape(g->batch_self, ctx->grid_self)));
     if (ctx->timing) {
       if (ctx->ev_scatter.empty()) ctx->ev_scatter.emplace_back();
       HIPCHK(ctx, ev_pair(ctx->ev_scatter[0]));
       HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].a, s));
     }
-    HIPCHK(ctx, plc::launch_batch_scatter(s, a, ctx->grid_scatter));
+    HIPCHK(ctx, plc::launch_batch_scatter(s, a, shape(g->batch_scatter, ctx->grid_scatter)));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].b, s));
     HIPCHK(ctx, plc::launch_batch_round_end(s, a));
   }
@@ -917,7 +925,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       HIPCHK(ctx, ev_pair(ctx->ev_sweep));
       HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
     }
-    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, total, ctx->grid_sweep));
+    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, total, shape(g->batch_sweep, ctx->grid_sweep)));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
   }
   // 4. read back and wait
@@ -1027,4 +1035,94 @@ extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_quer
     }
   }
   return first;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+#include <chrono>
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Run the sample once under the graph's current shapes; wall time in ms.
+static plc_status tune_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,
+                           bool batched, double* ms) {
+  std::vector<uint64_t> ids(count);
+  const double t0 = now_ms();
+  plc_status st = batched ? plc_run_batched(ctx, g, q, count, ids.data(), nullptr)
+                          : plc_run(ctx, g, q, count, ids.data(), nullptr);
+  *ms = now_ms() - t0;
+  for (uint64_t id : ids)
+    if (id) (void)plc_release(ctx, id);
+  return st == PLC_E_HIP ? st : PLC_OK;
+}
+
+extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* sample,
+                                   int32_t count, int32_t which, plc_tune* out) {
+  if (!ctx || !g || !ctx->graphs.count(g) || !sample || count <= 0) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  if ((which & PLC_TUNE_BATCH) && !g->batch) return PLC_E_INVALID;
+  const int cu = ctx->num_cu;
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  int tried = 0;
+  double best_plain = 0, best_batch = 0;
+  if (which & PLC_TUNE_PLAIN) {
+    const int selfs[] = {cu / 2, cu, 2 * cu};
+    const int scats[] = {cu / 2, cu, 2 * cu, 4 * cu};
+    const int sweeps[] = {cu, 2 * cu};
+    double ms = 0;
+    g->plain_self = cu; g->plain_scatter = 4 * cu; g->plain_sweep = 2 * cu;
+    plc_status st = tune_run(ctx, g, sample, count, false, &ms);  // warm-up
+    if (st != PLC_OK) { ctx->timing = timing; return st; }
+    int bs = cu, bc = 4 * cu, bw = 2 * cu;
+    double best = 1e300;
+    for (int gs : selfs)
+      for (int gc : scats)
+        for (int gw : sweeps) {
+          g->plain_self = gs; g->plain_scatter = gc; g->plain_sweep = gw;
+          st = tune_run(ctx, g, sample, count, false, &ms);
+          if (st != PLC_OK) { ctx->timing = timing; return st; }
+          tried++;
+          if (ms < best) { best = ms; bs = gs; bc = gc; bw = gw; }
+        }
+    g->plain_self = bs; g->plain_scatter = bc; g->plain_sweep = bw;
+    best_plain = best;
+  }
+  if (which & PLC_TUNE_BATCH) {
+    const int selfs[] = {cu, 2 * cu};
+    const int scats[] = {2 * cu, 4 * cu, 8 * cu, 16 * cu};
+    double ms = 0;
+    g->batch_self = cu; g->batch_scatter = 4 * cu; g->batch_sweep = 2 * cu;
+    plc_status st = tune_run(ctx, g, sample, count, true, &ms);  // warm-up
+    if (st != PLC_OK) { ctx->timing = timing; return st; }
+    int bs = cu, bc = 4 * cu;
+    double best = 1e300;
+    for (int gs : selfs)
+      for (int gc : scats) {
+        g->batch_self = gs; g->batch_scatter = gc;
+        st = tune_run(ctx, g, sample, count, true, &ms);
+        if (st != PLC_OK) { ctx->timing = timing; return st; }
+        tried++;
+        if (ms < best) { best = ms; bs = gs; bc = gc; }
+      }
+    g->batch_self = bs; g->batch_scatter = bc;
+    best_batch = best;
+  }
+  ctx->timing = timing;
+  if (out) {
+    out->plain_self = shape(g->plain_self, ctx->grid_self);
+    out->plain_scatter = shape(g->plain_scatter, ctx->grid_scatter);
+    out->plain_sweep = shape(g->plain_sweep, ctx->grid_sweep);
+    out->batch_self = shape(g->batch_self, ctx->grid_self);
+    out->batch_scatter = shape(g->batch_scatter, ctx->grid_scatter);
+    out->batch_sweep = shape(g->batch_sweep, ctx->grid_sweep);
+    out->plain_ms = best_plain;
+    out->batch_ms = best_batch;
+    out->candidates = tried;
+    out->reserved = 0;
+  }
+  return PLC_OK;
 }

@@ -124,3 +124,21 @@ def test_reserve_limited_by_arena(plc):
         assert all(x["status"] == 0 for x in infos)
         for i in ids:
             ctx.release(i)
+
+
+def test_autotune_keeps_results(setup, plc):
+    g, ctx, hg = setup
+    seeds, alpha, eps, rules = mixed_queries(g, 24, seed=77)
+    tune = ctx.autotune(hg, seeds[:8], alpha[:8], eps[:8],
+                        plc.PLC_TUNE_PLAIN | plc.PLC_TUNE_BATCH)
+    assert tune["candidates"] == 24 + 8
+    for key in ("plain_self", "plain_scatter", "plain_sweep", "batch_self", "batch_scatter"):
+        assert tune[key] > 0
+    ids, _ = ctx.run_batched(hg, seeds, alpha, eps, rules)
+    for i, qid in enumerate(ids):
+        check_query(g, ctx.result(qid, release=True), int(seeds[i]), float(alpha[i]),
+                    float(eps[i]), int(rules[i]))
+    ids, _ = ctx.run(hg, seeds[:6], alpha[:6], eps[:6], rules[:6])
+    for i, qid in enumerate(ids):
+        check_query(g, ctx.result(qid, release=True), int(seeds[i]), float(alpha[i]),
+                    float(eps[i]), int(rules[i]))
