@@ -55,6 +55,15 @@ def tie_blocks(order, p, deg, p_other=None):
     return start
 
 
+def cluster_arcs(g, cl):
+    """Neighbour ids of every arc leaving the vertices of cl (CSR rows concatenated)."""
+    cl = np.asarray(cl, np.int64)
+    start = g.off[cl].astype(np.int64)
+    cnt = (g.off[cl + 1] - g.off[cl]).astype(np.int64)
+    base = np.repeat(start - np.concatenate(([0], np.cumsum(cnt)[:-1])), cnt)
+    return g.nbr[base + np.arange(int(cnt.sum()), dtype=np.int64)]
+
+
 def check_query(g, res, seed, alpha, eps, rule, orc=None, osw=None) -> dict:
     """Assert GPU result `res` (paper_1604_07515_amd.Result) matches the oracle."""
     n = g.n
@@ -113,8 +122,7 @@ def check_query(g, res, seed, alpha, eps, rule, orc=None, osw=None) -> dict:
     inset = np.zeros(n, bool)
     inset[cl] = True
     vol = int(deg[cl].sum())
-    src = np.repeat(np.arange(n), deg)
-    cut = int(np.count_nonzero(inset[src] & ~inset[g.nbr]))
+    cut = int(np.count_nonzero(~inset[cluster_arcs(g, cl)]))
     assert (cut, vol) == (info["cut"], info["vol"])
     den = min(vol, g.arcs - vol)
     assert Fraction(cut, den) == Fraction(info["cut"], den)

@@ -21,3 +21,18 @@ def test_tie_blocks_other_side():
     q = np.array([2.0, 2.0 * (1 + 1e-15), 1.0])  # a few ulps apart on the other
     assert tie_blocks(np.arange(3), p, deg).tolist() == [0, 1, 2]
     assert tie_blocks(np.arange(3), p, deg, q).tolist() == [0, 0, 2]
+
+
+def test_cluster_arcs_counts_the_cut():
+    import synth
+    from parity import cluster_arcs
+    g = synth.rmat(9, 8, seed=5)
+    rng = np.random.default_rng(0)
+    for k in (1, 7, 100, g.n):
+        cl = np.sort(rng.choice(g.n, k, replace=False))
+        inset = np.zeros(g.n, bool)
+        inset[cl] = True
+        want = sum(1 for v in cl for w in g.nbr[g.off[v]:g.off[v + 1]] if not inset[w])
+        arcs = cluster_arcs(g, cl)
+        assert len(arcs) == int(g.deg[cl].sum())
+        assert int(np.count_nonzero(~inset[arcs])) == want
