@@ -12,10 +12,12 @@ int32 ids, int64 offsets, FP64 p and r, optimized push rule:
   followed by the sweep cut, graph resident in HBM.
 * batched22: the same graph, 256 seeds in one batch (256 slots), eps
   log-uniform in [1e-7, 1e-5], alpha in {0.01, 0.05}; a step is the batch.
+  Run twice: with dense per-slot state and with compact per-query tables.
 * serve24: 2^24 vertices, seeds drawn proportionally to degree, eps
   log-uniform in [1e-7, 1e-4], alpha = 0.01, continuous batching over 64
-  slots: the saturation rate (all queries queued at once) and Poisson
-  arrivals at 50% and 90% of it, with p50/p99 latency.
+  slots (compact tables by default: admission by memory): the saturation
+  rate (all queries queued at once) and Poisson arrivals at 50% and 90% of
+  it, with p50/p99 latency.
 
 Prints one JSON line.  The roofline object describes the edge-scatter
 kernel, timed with HIP events on the library's stream over the timed steps.
@@ -24,6 +26,7 @@ The CPU baseline is the oracle timed on the host on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -50,14 +53,41 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def roofline(tm):
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scatter_hbm_traffic_rmat22.md")
+
+
+def measured_traffic(kernel):
+    """Per-launch HBM traffic of `kernel` from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter
+    reads for a device copy of known size), or None when the kernel's sources
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            block = f.read().split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)[kernel]
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+    return rec if h.hexdigest()[:16] == rec["source_sha256_16"] else None
+
+
+def roofline(tm, kernel):
     sc = tm["scatter"]
     by = SCATTER_B_PER_EDGE * sc["units"] + SCATTER_B_PER_ENTRY * sc["entries"]
     gbs = by / (sc["ms"] * 1e-3) / 1e9 if sc["ms"] > 0 else 0.0
+    tr = measured_traffic(kernel)
     return {
-        "kernel": "scatter (edgeMap UpdateNgh)", "bound": "hbm", "achieved": gbs,
-        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+        "kernel": "%s (edgeMap UpdateNgh)" % kernel, "bound": "hbm", "achieved": gbs,
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+        "traffic": tr["traffic_bytes_per_launch"] if tr else None,
+        "traffic_unit": "bytes per launch (FETCH_SIZE x %.3f + WRITE_SIZE x %.3f)" % (
+            tr["fetch_factor"], tr["write_factor"]) if tr else None,
+        "traffic_over_algorithmic": tr["traffic_over_algorithmic"] if tr else None,
         "bytes_model": "20 B per pushed edge + 24 B per pushed vertex",
+        "algorithmic_bytes_per_launch": by / max(sc["launches"], 1),
         "launches": sc["launches"], "avg_launch_us": sc["ms"] * 1e3 / max(sc["launches"], 1),
         "edges_per_s": sc["units"] / (sc["ms"] * 1e-3) if sc["ms"] > 0 else 0.0,
     }
@@ -117,15 +147,18 @@ def bench_plain(plc, synth, g, steps, warmup):
         "queries_per_s": nq / elapsed, "ms_per_step": elapsed * 1e3 / steps,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3, "what": "per query"},
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
-        "kernels": tm, "roofline": roofline(tm),
+        "kernels": tm, "roofline": roofline(tm, "k_scatter"),
         "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep")},
     }
 
 
-def bench_batched(plc, synth, g, steps, warmup, slots=256):
+def bench_batched(plc, synth, g, steps, warmup, slots=256, compact=False):
     qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
+    tables = (8 << 30) if compact else 0
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
-                      + plc.batch_arena_bytes(g.n, g.arcs, slots) + (512 << 20))
+                      + plc.batch_arena_bytes(g.n, g.arcs, slots, compact=compact,
+                                              table_bytes=tables) + (512 << 20),
+                      compact=compact)
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
     tune = ctx.autotune(hg, qs.seeds, qs.alpha, qs.eps, plc.PLC_TUNE_BATCH)
@@ -143,18 +176,19 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256):
     nq = acc["queries"]
     return {
         "queries": qs, "workload": "rmat%d_ef16_batched_256seeds" % (g.n.bit_length() - 1),
-        "slots": got, "edges_per_s": acc["edges"] / elapsed, "queries_per_s": nq / elapsed,
+        "state": "compact tables" if compact else "dense slots", "slots": got, "edges_per_s": acc["edges"] / elapsed, "queries_per_s": nq / elapsed,
         "ms_per_step": elapsed * 1e3 / steps,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
                        "what": "per batch of 256"},
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
         "eps": [float(qs.eps.min()), float(qs.eps.max())], "alpha": [0.01, 0.05],
-        "kernels": tm, "roofline": roofline(tm),
+        "kernels": tm,
+        "roofline": roofline(tm, "k_b_scatter<%s>" % ("CompactState" if compact else "DenseState")),
         "launch_shapes": {k: tune[k] for k in ("batch_self", "batch_scatter", "batch_sweep")},
     }
 
 
-def bench_serving(plc, synth, scale, nq, slots=64):
+def bench_serving(plc, synth, scale, nq, slots=64, compact=False):
     import numpy as np
     from paper_1604_07515_amd import serve
     t0 = time.time()
@@ -163,15 +197,18 @@ def bench_serving(plc, synth, scale, nq, slots=64):
     rng = np.random.default_rng(2)
     seeds = synth.degree_weighted_seeds(g, nq, rng)
     eps = 10.0 ** rng.uniform(-7, -4, nq)
+    tables = (8 << 30) if compact else 0
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
-                      + plc.batch_arena_bytes(g.n, g.arcs, slots) + (1 << 30))
+                      + plc.batch_arena_bytes(g.n, g.arcs, slots, compact=compact,
+                                              table_bytes=tables) + (1 << 30),
+                      compact=compact)
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
     ctx.autotune(hg, seeds[:128], 0.01, eps[:128], plc.PLC_TUNE_BATCH)
     serve.saturation(ctx, hg, seeds[:256], 0.01, eps[:256])  # warm-up
     sat = serve.saturation(ctx, hg, seeds, 0.01, eps)
     out = {"workload": "rmat%d_ef16_serving_poisson" % scale, "n": g.n, "arcs": g.arcs,
-           "slots": got, "queries_per_run": nq, "alpha": 0.01, "eps": [1e-7, 1e-4],
+           "state": "compact tables" if compact else "dense slots", "slots": got, "queries_per_run": nq, "alpha": 0.01, "eps": [1e-7, 1e-4],
            "seeds": "proportional to degree",
            "saturation": {"queries_per_s": sat.queries_per_s,
                           "edges_per_s": sat.edges / sat.wall_s,
@@ -188,6 +225,62 @@ def bench_serving(plc, synth, scale, nq, slots=64):
                                                             rep.percentile_ms(99)))
     ctx.close()
     return out
+
+
+def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
+    """1024 seeds (32 of them the top-degree hubs) on R-MAT 2^scale with eps
+    log-uniform in [1e-8, 1e-6], alpha 0.01, through the compact-table engine:
+    queries are admitted as table memory allows.  Driven step by step (so that
+    progress is printed); each result is released as soon as it is read."""
+    import numpy as np
+    t0 = time.time()
+    g = synth.rmat(scale, 16, seed=1)
+    log("large graph 2^%d: n=%d arcs=%d maxdeg=%d (%.1fs)" % (scale, g.n, g.arcs, g.deg.max(),
+                                                             time.time() - t0))
+    hubs = np.argsort(-g.deg, kind="stable")[:32]
+    seeds = np.concatenate([synth.uniform_seeds(g, nq - 32, seed=2), hubs])
+    eps = 10.0 ** np.random.default_rng(2).uniform(-8, -6, nq)
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                      + plc.batch_arena_bytes(g.n, g.arcs, slots, compact=True,
+                                              table_bytes=table_gib << 30), compact=True)
+    hg = ctx.load_graph(g.off, g.nbr)
+    got = ctx.batch_reserve(hg, slots)
+    import torch
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t1 = time.perf_counter()
+    ids = ctx.submit(hg, seeds, 0.01, eps)
+    done, acc, last_log, peak = [], {"edges": 0, "support": 0, "rounds": 0, "nomem": 0}, t1, 0
+    left = len(ids)
+    while left > 0:
+        fin = []
+        left = ctx.progress(hg, fin)
+        peak = max(peak, left)
+        for qid in fin:
+            info = ctx.result_info(qid)
+            if info["status"] == plc.PLC_E_NOMEM:
+                acc["nomem"] += 1
+            acc["edges"] += info["edges"]
+            acc["support"] = max(acc["support"], info["support"])
+            acc["rounds"] = max(acc["rounds"], info["rounds"])
+            ctx.release(qid)
+            done.append(qid)
+        if time.perf_counter() - last_log > 10:
+            last_log = time.perf_counter()
+            log("  large: %d of %d done, %.3g edges so far (%.0fs)" % (
+                len(done), nq, acc["edges"], last_log - t1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    tm = ctx.timing_get()
+    ctx.timing(False)
+    ctx.close()
+    return {"workload": "rmat%d_ef16_1024seeds_32hubs" % scale, "n": g.n, "arcs": g.arcs,
+            "state": "compact tables", "slots": got, "table_budget_gib": table_gib,
+            "eps": [1e-8, 1e-6], "alpha": 0.01, "queries": nq, "failed_nomem": acc["nomem"],
+            "elapsed_s": elapsed, "edges_per_s": acc["edges"] / elapsed,
+            "queries_per_s": nq / elapsed, "max_support": acc["support"],
+            "max_rounds": acc["rounds"], "kernels": tm,
+            "roofline": roofline(tm, "k_b_scatter<CompactState>")}
 
 
 def cpu_baseline(oracle, g, work, budget):
@@ -213,12 +306,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["plain", "batched", "serving"], default=None,
-                    help="run one workload only (the others are reported as skipped)")
+    ap.add_argument("--only", choices=["plain", "batched", "serving", "large"], default=None,
+                    help="run one workload only (the others are reported as skipped); "
+                         "'large' (R-MAT 2^26, 1024 seeds) runs only when asked for")
     ap.add_argument("--serve-scale", type=int, default=24)
     ap.add_argument("--serve-queries", type=int, default=2048)
+    ap.add_argument("--serve-state", choices=["dense", "compact"], default="compact",
+                    help="state layout of the serving engine")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a device copy of MIB MiB three times (reference kernel "
+                         "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -228,6 +327,17 @@ def main():
 
     import synth
     import paper_1604_07515_amd as plc
+
+    if args.copy_calibration > 0:
+        import torch
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x %d MiB device copies" % args.copy_calibration)
+        del src, dst
 
     t0 = time.time()
     g = synth.rmat(22, 16, seed=1)
@@ -239,7 +349,16 @@ def main():
     bat = bench_batched(plc, synth, g, max(2, args.steps // 2), 1) if want("batched") else None
     if bat:
         log("batched: %.3g edges/s, %.1f queries/s" % (bat["edges_per_s"], bat["queries_per_s"]))
-    srv = bench_serving(plc, synth, args.serve_scale, args.serve_queries) if want("serving") else None
+    bat_c = (bench_batched(plc, synth, g, max(2, args.steps // 2), 1, compact=True)
+             if want("batched") else None)
+    if bat_c:
+        log("batched (compact tables): %.3g edges/s, %.1f queries/s" % (
+            bat_c["edges_per_s"], bat_c["queries_per_s"]))
+    srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries,
+                         compact=args.serve_state == "compact") if want("serving") else None)
+    big = bench_large(plc, synth) if args.only == "large" else None
+    if big:
+        log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
 
     main_res = plain or bat
     out = {
@@ -270,6 +389,10 @@ def main():
         out["batched"] = {k: v for k, v in bat.items() if k != "queries"}
         if plain:
             out["batched"]["queries_per_s_vs_plain"] = bat["queries_per_s"] / plain["queries_per_s"]
+    if bat_c:
+        out["batched_compact"] = {k: v for k, v in bat_c.items() if k != "queries"}
+    if big:
+        out["large"] = big
     if srv:
         out["serving"] = srv
     if args.cpu_budget > 0:

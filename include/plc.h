@@ -52,10 +52,40 @@ typedef int32_t plc_status;
 typedef struct plc_ctx plc_ctx;
 typedef struct plc_graph plc_graph;
 
+/*
+ * Launch modes.  PLC_LAUNCH_GRAPH (the default): the round loops are recorded
+ * once as HIP graphs -- the plain path's chunks of rounds and its sweep, the
+ * batched path's round -- and replayed with one hipGraphLaunch each on the
+ * context's stream.  PLC_LAUNCH_DIRECT: every kernel is launched on its own.
+ * Both run the same kernels with the same arguments; if recording a graph
+ * fails the context falls back to direct launches.
+ */
+#define PLC_LAUNCH_GRAPH 0
+#define PLC_LAUNCH_DIRECT 1
+
+/*
+ * Layouts of the batch engine's per-query state.  PLC_STATE_DENSE: every slot
+ * owns dense arrays over all n vertices (40 bytes per vertex per slot,
+ * reserved up front by plc_batch_reserve); the edge scatter indexes them
+ * directly.  PLC_STATE_COMPACT: every admitted query owns an open-addressing
+ * table (16-byte records, p beside them, at most half full) plus its vertex
+ * lists, 32 bytes per table record, taken from the arena at admission,
+ * sized for the seed's first round and grown between rounds, so memory
+ * follows the vertices a query touches.  Queued queries are admitted while
+ * a slot is free and the arena can hold their first table; a query whose
+ * table cannot grow waits while others run, and fails with PLC_E_NOMEM only
+ * when no other query can make progress.  Results are the same in both
+ * layouts.
+ */
+#define PLC_STATE_DENSE 0
+#define PLC_STATE_COMPACT 1
+
 typedef struct {
   int32_t max_rounds;  /* watchdog on PR-Nibble rounds per query; 0 = 1<<20 */
   int32_t batch_slots; /* concurrent queries in the batched path; 0 = 256   */
-  int32_t reserved[6];
+  int32_t launch_mode; /* PLC_LAUNCH_GRAPH or PLC_LAUNCH_DIRECT             */
+  int32_t batch_state; /* PLC_STATE_DENSE or PLC_STATE_COMPACT              */
+  int32_t reserved[4];
 } plc_options;
 
 /*
@@ -144,12 +174,14 @@ plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count
  * additions differs).
  *
  * plc_batch_reserve: give graph g a batch engine with up to `slots`
- * concurrent queries (1..1024).  Each slot holds dense per-vertex state
- * (about 40 bytes per vertex), so fewer slots are granted when the arena is
- * short (max(64 MiB, 1/16 of the free arena) stays free for result blocks);
- * *granted (may be NULL) receives the number.  PLC_E_NOMEM if not even
- * one slot fits.  Calling it again re-creates the engine (pending and running
- * queries are dropped).
+ * concurrent queries (1..1024), in the context's state layout
+ * (plc_options.batch_state).  Dense: each slot holds per-vertex state (about
+ * 40 bytes per vertex), so fewer slots are granted when the arena is short
+ * (max(64 MiB, 1/16 of the free arena) stays free for result blocks).
+ * Compact: the slots themselves are small; queries take their tables from
+ * the arena as they run.  *granted (may be NULL) receives the number.
+ * PLC_E_NOMEM if not even one slot fits.  Calling it again re-creates the
+ * engine (pending and running queries are dropped).
  */
 plc_status plc_batch_reserve(plc_ctx* ctx, plc_graph* g, int32_t slots, int32_t* granted);
 
@@ -176,6 +208,31 @@ plc_status plc_progress(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uint64_t
 
 /* *done = 1 if query `id` has finished (its result is ready), else 0. */
 plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);
+
+/*
+ * Block until query `id` has finished, driving its graph's batch engine one
+ * plc_progress step at a time (other queries advance and finish as well;
+ * their results stay available to plc_poll and plc_result_*).  timeout_us < 0
+ * waits without limit; otherwise PLC_E_NOTREADY is returned once that much
+ * wall time has passed with the query still in flight.  PLC_OK when the
+ * query has finished (also if it already had), PLC_E_NOTFOUND for unknown
+ * ids.
+ */
+plc_status plc_wait(plc_ctx* ctx, uint64_t id, int64_t timeout_us);
+
+/*
+ * Arena bytes that one query q on graph g occupies on the batch engine: the
+ * state of one slot (dense over the graph's vertices: residual record, p,
+ * two frontier buffers, support and touched lists; plc_batch_reserve takes
+ * it for every slot) plus an upper bound on the query's result block.  The
+ * bound comes from the push's work bound (Sec. 3.3): every push except the
+ * seed's moves at least alpha' eps d(v) of the unit mass into p, with
+ * alpha' = 2 alpha/(1+alpha) for the optimized rule and alpha for the
+ * original, so at most 1 + 1/(alpha' eps) vertices are pushed and at most
+ * 1 + d(seed) + 1/(alpha' eps) are touched (both also at most n).  Used by a
+ * serving front end to budget admissions.  Returns 0 when g or q is invalid.
+ */
+size_t plc_query_bytes_estimate(const plc_graph* g, const plc_query* q);
 
 /* Submit `count` queries and step g's batch engine until all have finished.
  * Throughput mode: queries that finish pushing while others still push are

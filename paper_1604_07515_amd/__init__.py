@@ -28,13 +28,17 @@ PLC_E_HIP = -7
 PLC_RULE_OPT = 0
 PLC_RULE_ORIG = 1
 PLC_GRAPH_VALIDATE = 1
+PLC_LAUNCH_GRAPH = 0
+PLC_LAUNCH_DIRECT = 1
+PLC_STATE_DENSE = 0
+PLC_STATE_COMPACT = 1
 
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
            "plc_graph_info_get", "plc_run", "plc_result_info_get", "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
-           "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_run_batched",
-           "plc_autotune")
+           "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_wait",
+           "plc_query_bytes_estimate", "plc_run_batched", "plc_autotune")
 
 
 class PlcError(RuntimeError):
@@ -45,7 +49,8 @@ class PlcError(RuntimeError):
 
 class plc_options(C.Structure):
     _fields_ = [("max_rounds", C.c_int32), ("batch_slots", C.c_int32),
-                ("reserved", C.c_int32 * 6)]
+                ("launch_mode", C.c_int32), ("batch_state", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
 
 
 class plc_query(C.Structure):
@@ -126,6 +131,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "plc_submit": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64)], I32),
         "plc_progress": ([P, P, C.POINTER(I32), C.POINTER(U64), I32, C.POINTER(I32)], I32),
         "plc_poll": ([P, U64, C.POINTER(I32)], I32),
+        "plc_wait": ([P, U64, I64], I32),
+        "plc_query_bytes_estimate": ([P, C.POINTER(plc_query)], SZ),
         "plc_run_batched": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
                              C.POINTER(plc_result_info)], I32),
         "plc_autotune": ([P, P, C.POINTER(plc_query), I32, I32, C.POINTER(plc_tune)], I32),
@@ -197,12 +204,14 @@ class Graph:
 class Context:
     """A libplc context on one GPU, with a torch-owned arena and stream."""
 
-    def __init__(self, arena_bytes: int, device: int = 0, stream=None, max_rounds: int = 0):
+    def __init__(self, arena_bytes: int, device: int = 0, stream=None, max_rounds: int = 0,
+                 graphs: bool = True, compact: bool = False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libplc needs a GPU; torch.cuda.is_available() is False")
         self.lib = load_library()
         self.device = device
+        self.arena_bytes = int(arena_bytes)
         dev = torch.device("cuda", device)
         self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=dev)
         base = self.arena.data_ptr()
@@ -210,6 +219,8 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         opt = plc_options()
         opt.max_rounds = max_rounds
+        opt.launch_mode = PLC_LAUNCH_GRAPH if graphs else PLC_LAUNCH_DIRECT
+        opt.batch_state = PLC_STATE_COMPACT if compact else PLC_STATE_DENSE
         h = C.c_void_p()
         _check(self.lib.plc_init(C.byref(h), device, C.c_void_p(aligned), int(arena_bytes),
                                  C.c_void_p(self.stream.cuda_stream), C.byref(opt)), "plc_init")
@@ -296,6 +307,20 @@ class Context:
         _check(self.lib.plc_poll(self.handle, qid, C.byref(done)), "plc_poll")
         return bool(done.value)
 
+    def wait(self, qid: int, timeout_us: int = -1) -> bool:
+        """Step the query's batch engine until it has finished; False on timeout."""
+        rc = self.lib.plc_wait(self.handle, qid, int(timeout_us))
+        if rc == PLC_E_NOTREADY:
+            return False
+        _check(rc, "plc_wait")
+        return True
+
+    def query_bytes_estimate(self, g: Graph, seed: int, alpha: float, eps: float,
+                             rule: int = PLC_RULE_OPT) -> int:
+        """Arena bytes one query occupies on the batch engine (slot state + result bound)."""
+        qa = self.queries([seed], alpha, eps, rule)
+        return int(self.lib.plc_query_bytes_estimate(g.handle, qa))
+
     def run_batched(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
         """Batched path: submit all and step until every query has finished."""
         qa = self.queries(seeds, alpha, eps, rule)
@@ -352,16 +377,21 @@ class Context:
         return {"scatter": a.as_dict(), "self": b.as_dict(), "sweep": c.as_dict()}
 
 
-def batch_arena_bytes(n: int, arcs: int, slots: int) -> int:
-    """Arena bytes for a batch engine with `slots` slots (on top of the plain path)."""
-    per_slot = 40 * n
+def batch_arena_bytes(n: int, arcs: int, slots: int, compact: bool = False,
+                      table_bytes: int = 0) -> int:
+    """Arena bytes for a batch engine with `slots` slots (on top of the plain path).
+
+    Dense layout: the slots' per-vertex state (40 B per vertex per slot).
+    Compact layout: `table_bytes` for the running queries' tables (32 B per
+    table record; plc_query_bytes_estimate bounds one query's need)."""
+    per_slot = 0 if compact else 40 * n
     nf_cap = min(max(2 * n, 1 << 22), slots * n)
     nf_cap = max(nf_cap, n)
     e_cap = max(2 * arcs, 1 << 26)
     s_cap = max(min(2 * n, slots * n), n)
     fixed = (28 * nf_cap + 4 * (e_cap // 1024 + 2) + 96 * (max(nf_cap, s_cap) // 1024 + 2)
-             + 56 * s_cap + 512 * slots + (1 << 20))
-    return int((per_slot * slots + fixed) * 17 // 16 + (192 << 20))
+             + 56 * s_cap + 1024 * slots + 8 * n + (1 << 20))
+    return int((per_slot * slots + fixed) * 17 // 16 + (192 << 20) + table_bytes)
 
 
 def plain_arena_bytes(n: int, arcs: int) -> int:

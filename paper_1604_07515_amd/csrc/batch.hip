@@ -18,6 +18,9 @@
 // the segments of one merge sort (segment = query), then the rank map,
 // volume scan, boundary deltas and boundary scan run over the concatenation
 // and one workgroup per segment takes the exact argmin.
+//
+// The kernels that touch per-query state are templates over the state layout
+// (DenseState or CompactState, see batch_device.h).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -49,6 +52,75 @@ __device__ __forceinline__ int seg_of(const long long* off, int nseg, long long 
   return lo;
 }
 
+// ---------------------------------------------------------------- state layouts
+
+// 32-bit finaliser of MurmurHash3 (a bijection on 32-bit words): spreads the
+// clustered ids of high-degree R-MAT vertices over the table.
+__device__ __forceinline__ uint32_t vhash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x85ebca6bu;
+  x ^= x >> 13;
+  x *= 0xc2b2ae35u;
+  x ^= x >> 16;
+  return x;
+}
+
+// Dense: record v of the slot's n records; always present.
+struct DenseState {
+  static constexpr bool kCompact = false;
+  __device__ static VRec* find(const Slot& S, int32_t v) { return S.tab + v; }
+  __device__ static VRec* insert(const Slot& S, int32_t v) { return S.tab + v; }
+  __device__ static int32_t rank_of(const Slot& S, int32_t v) { return S.tab[v].rank; }
+  __device__ static double* pp(const Slot& S, int32_t v, const VRec*) { return S.tp + v; }
+  __device__ static int2 deg_hot(const BatchArgs&, const Slot& S, int32_t v) {
+    return *reinterpret_cast<const int2*>(&S.tab[v].deg);
+  }
+};
+
+// Compact: linear probing from vhash(v); the record's deg field holds the key
+// (kEmptyKey when free), rank is 0 outside a sweep.
+struct CompactState {
+  static constexpr bool kCompact = true;
+  // record holding v, or nullptr when v is not in the table (valid after the
+  // kernel that inserted v has finished)
+  __device__ static VRec* find(const Slot& S, int32_t v) {
+    const uint32_t m = (uint32_t)S.mask;
+    uint32_t h = vhash((uint32_t)v) & m;
+    for (uint32_t i = 0; i <= m; i++) {
+      const int32_t k = S.tab[h].deg;
+      if (k == v) return S.tab + h;
+      if (k == kEmptyKey) return nullptr;
+      h = (h + 1) & m;
+    }
+    return nullptr;
+  }
+  // record of v, claimed with a compare-and-swap when v is new; concurrent
+  // inserts of v agree on one record.  nullptr only if the table is full.
+  __device__ static VRec* insert(const Slot& S, int32_t v) {
+    const uint32_t m = (uint32_t)S.mask;
+    uint32_t h = vhash((uint32_t)v) & m;
+    for (uint32_t i = 0; i <= m; i++) {
+      int32_t* kp = &S.tab[h].deg;
+      const int32_t k = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k == v) return S.tab + h;
+      if (k == kEmptyKey) {
+        const int32_t old = atomicCAS(kp, kEmptyKey, v);
+        if (old == kEmptyKey || old == v) return S.tab + h;
+      }
+      h = (h + 1) & m;
+    }
+    return nullptr;
+  }
+  __device__ static int32_t rank_of(const Slot& S, int32_t v) {
+    const VRec* r = find(S, v);
+    return r ? r->rank : 0;
+  }
+  __device__ static double* pp(const Slot& S, int32_t, const VRec* rec) {
+    return S.tp + (rec - S.tab);
+  }
+  __device__ static int2 deg_hot(const BatchArgs& a, const Slot&, int32_t v) { return a.gdh[v]; }
+};
+
 // ---------------------------------------------------------------- init
 
 __global__ void k_b_init(BatchArgs a) {
@@ -65,10 +137,18 @@ __global__ void k_b_init(BatchArgs a) {
   }
 }
 
+// Compact layout: graph-wide {d(v), hot code} records.
+__global__ void k_gdh_init(BatchArgs a, int2* gdh) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < a.n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    gdh[v] = make_int2((int32_t)(a.off[v + 1] - a.off[v]), a.hotcode[v]);
+}
+
+template <class St>
 __global__ void k_b_admit(BatchArgs a, const Admit* adm, int count) {
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     Admit ad = adm[i];
-    if (ad.slot < 0 || ad.slot >= a.B || ad.seed < 0 || ad.seed >= a.n) continue;
+    if (ad.slot < 0 || ad.slot >= a.B || ad.seed < 0 || ad.seed >= a.n || ad.list_cap < 1) continue;
     Slot& S = a.slots[ad.slot];
     if (ad.rule == 1) {
       S.cs = ad.alpha;
@@ -105,10 +185,19 @@ __global__ void k_b_admit(BatchArgs a, const Admit* adm, int count) {
     S.best_den = 0;
     S.phi = 0.0;
     S.rnnz = 0;
-    const int64_t base = (int64_t)ad.slot * a.n;
-    a.fbuf[2 * base] = ad.seed;
-    a.touched[base] = ad.seed;
-    a.vr[base + ad.seed].r = 1.0;
+    S.hold = 0;
+    S.tab = ad.tab;
+    S.tp = ad.tp;
+    S.fb[0] = ad.fb0;
+    S.fb[1] = ad.fb1;
+    S.support = ad.support;
+    S.touched = ad.touched;
+    S.mask = ad.mask;
+    S.list_cap = ad.list_cap;
+    S.fb[0][0] = ad.seed;
+    S.touched[0] = ad.seed;
+    VRec* rec = St::insert(S, ad.seed);  // a fresh (cleared) table: never full
+    if (rec) rec->r = 1.0; else S.fault = 1;
     S.status = SL_PUSH;
   }
 }
@@ -125,7 +214,7 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_plan(BatchArgs a) {
     S.fbase = -1;
     S.nf = 0;
     S.round_edges = 0;
-    if (S.status == SL_PUSH) {
+    if (S.status == SL_PUSH && !S.hold) {
       int cur = S.cnt[S.par];
       if (cur <= 0) {
         S.status = SL_PUSHED;
@@ -133,7 +222,7 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_plan(BatchArgs a) {
         S.limited = 1;
         S.status = SL_PUSHED;
       } else {
-        nf = cur < a.n ? cur : a.n;
+        nf = cur < S.list_cap ? cur : S.list_cap;
         e = S.edge_next[S.par];
       }
     }
@@ -164,6 +253,7 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_plan(BatchArgs a) {
   }
 }
 
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int NF = c->nf_total;
@@ -182,7 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
   scan_clear_prev(site, a.desc[BSCAN_FRONTIER], a.desc_cap);
   unsigned long long* desc = a.desc[BSCAN_FRONTIER] + (size_t)site->parity * a.desc_cap;
   const int nblk = (NF + kScanBlock - 1) / kScanBlock;
-  const int64_t n = a.n;
   __syncthreads();
 
   for (;;) {
@@ -218,27 +307,32 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
         const int q = slot_of(s_pref, B, g);
         const Slot& S = a.slots[q];
         const int i = (int)(g - s_pref[q]);
-        const int par = S.par;
-        const int64_t base = (int64_t)q * n;
-        const int32_t v = a.fbuf[(2 * base) + (int64_t)par * n + i];
-        VRec rec = a.vr[base + v];
-        const double rho = rec.r;
-        const int32_t d = rec.deg;
-        const double pold = a.p[base + v];
-        a.p[base + v] = pold + S.cs * rho;
-        const double nr = S.opt ? -0.0 : S.keep * rho;
-        a.vr[base + v].r = nr;
-        a.coef[g] = (S.cn * rho) / (double)d;
+        const int32_t v = S.fb[S.par][i];
+        VRec* rp = St::find(S, v);
+        double rho = 0.0;
+        int32_t d = 0;
+        if (rp) {
+          rho = rp->r;
+          d = St::deg_hot(a, S, v).x;
+          double* pv = St::pp(S, v, rp);
+          const double pold = *pv;
+          *pv = pold + S.cs * rho;
+          const double nr = S.opt ? -0.0 : S.keep * rho;
+          rp->r = nr;
+          if (pold == 0.0) rsup[k] = atomicAdd(&s_csup[q - qlo], 1);
+          if (!S.opt && nr >= S.eps * (double)d) {
+            rstay[k] = atomicAdd(&s_cstay[q - qlo], 1);
+            atomicAdd(&s_estay[q - qlo], (unsigned long long)d);
+          }
+        } else {
+          c->fault = 1;  // a frontier vertex always has a record
+        }
+        a.coef[g] = d > 0 ? (S.cn * rho) / (double)d : 0.0;
         a.rowp[g] = a.off[v];
         a.eslot[g] = q;
         vk[k] = v;
         dk[k] = d;
         qk[k] = q;
-        if (pold == 0.0) rsup[k] = atomicAdd(&s_csup[q - qlo], 1);
-        if (!S.opt && nr >= S.eps * (double)d) {
-          rstay[k] = atomicAdd(&s_cstay[q - qlo], 1);
-          atomicAdd(&s_estay[q - qlo], (unsigned long long)d);
-        }
       }
       dsum += dk[k];
     }
@@ -256,16 +350,14 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
       if (vk[k] < 0) continue;
-      const int q = qk[k];
-      const int64_t base = (int64_t)q * n;
+      const Slot& S = a.slots[qk[k]];
       if (rsup[k] >= 0) {
-        const long long pos = (long long)s_bsup[q - qlo] + rsup[k];
-        if (pos < n) a.support[base + pos] = vk[k]; else c->fault = 1;
+        const long long pos = (long long)s_bsup[qk[k] - qlo] + rsup[k];
+        if (pos < S.list_cap) S.support[pos] = vk[k]; else c->fault = 1;
       }
       if (rstay[k] >= 0) {
-        const long long pos = (long long)s_bstay[q - qlo] + rstay[k];
-        const int nxt = a.slots[q].par ^ 1;
-        if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = vk[k]; else c->fault = 1;
+        const long long pos = (long long)s_bstay[qk[k] - qlo] + rstay[k];
+        if (pos < S.list_cap) S.fb[S.par ^ 1][pos] = vk[k]; else c->fault = 1;
       }
     }
     long long agg;
@@ -300,32 +392,37 @@ __device__ __forceinline__ void b_decide_direct(const BatchArgs& a, int q, int32
                                                 double old, double c, int* fault) {
   Slot& S = a.slots[q];
   const double thr = S.eps * (double)dw;
-  const int64_t base = (int64_t)q * a.n;
   if (old < thr && old + c >= thr) {
     const int nxt = S.par ^ 1;
     long long pos = atomicAdd(&S.cnt[nxt], 1);
     atomicAdd((unsigned long long*)&S.edge_next[nxt], (unsigned long long)dw);
-    if (pos < a.n) a.fbuf[2 * base + (int64_t)nxt * a.n + pos] = w; else *fault = 1;
+    if (pos < S.list_cap) S.fb[nxt][pos] = w; else *fault = 1;
   }
   if (__double_as_longlong(old) == 0) {
     long long pos = atomicAdd(&S.touched_cnt, 1);
-    if (pos < a.n) a.touched[base + pos] = w; else *fault = 1;
+    if (pos < S.list_cap) S.touched[pos] = w; else *fault = 1;
   }
 }
 
 // Add the LDS sums of slot hs's hot destinations to r (one atomic each) and
 // clear them.  Every thread of the workgroup must call it.
+template <class St>
 __device__ void b_flush_hot(const BatchArgs& a, int hs, double* s_hacc, int* fault) {
   __syncthreads();
   if (hs >= 0) {
+    const Slot& S = a.slots[hs];
     for (int j = threadIdx.x; j < kHot; j += kBlock) {
       const double sum = s_hacc[j];
       if (sum != 0.0) {
         s_hacc[j] = 0.0;
         const int32_t w = a.hot_ids[j];
-        VRec* rec = a.vr + (int64_t)hs * a.n + w;
+        VRec* rec = St::insert(S, w);
+        if (!rec) {
+          *fault = 1;
+          continue;
+        }
         const double old = unsafeAtomicAdd(&rec->r, sum);
-        b_decide_direct(a, hs, w, rec->deg, old, sum, fault);
+        b_decide_direct(a, hs, w, St::deg_hot(a, S, w).x, old, sum, fault);
       }
     }
   }
@@ -333,16 +430,18 @@ __device__ void b_flush_hot(const BatchArgs& a, int hs, double* s_hacc, int* fau
 }
 
 // edgeMap over all scheduled edges.  Each workgroup takes a contiguous range
-// of tiles; contributions to hot destinations of the slot that owns the
-// current tiles are summed in LDS and flushed when the range moves to
-// another slot, and at the end.
+// of tiles, numbered XCD-major (xcd_block) so that a slot's edges stay within
+// one XCD's L2 (12 % less fetched from memory on R-MAT 2^22 with 256 slots);
+// contributions to hot destinations of the slot that owns the current tiles
+// are summed in LDS and flushed when the range moves to another slot, and at
+// the end.
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int NF = c->nf_total;
   if (NF <= 0) return;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->e_total;
-  const int64_t n = a.n;
   __shared__ int32_t s_start[kEdgeTile + 1];
   __shared__ int64_t s_row[kEdgeTile + 1];
   __shared__ double s_coef[kEdgeTile + 1];
@@ -353,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
   int hs = -1;  // slot whose hot sums s_hacc holds
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
-  const int tb = blockIdx.x * per;
+  const int tb = xcd_block(blockIdx.x, gridDim.x) * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
   __syncthreads();
 
@@ -369,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
     const int cnt = i1 - i0 + 1;
     const int tile_hs = a.eslot[i1];
     if (tile_hs != hs) {
-      b_flush_hot(a, hs, s_hacc, &c->fault);
+      b_flush_hot<St>(a, hs, s_hacc, &c->fault);
       hs = tile_hs;
     }
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
@@ -409,7 +508,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       dr[k] = make_int2(0, 0);
-      if (w[k] >= 0) dr[k] = *reinterpret_cast<const int2*>(&a.vr[(int64_t)q[k] * n + w[k]].deg);
+      if (w[k] >= 0) dr[k] = St::deg_hot(a, a.slots[q[k]], w[k]);
     }
     double old[kEdgesPerThread];
 #pragma unroll
@@ -421,7 +520,13 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
         atomicAdd(&s_hacc[hj], cf[k]);  // hot destination of the current slot
         w[k] = -1;
       } else {
-        old[k] = unsafeAtomicAdd(&a.vr[(int64_t)q[k] * n + w[k]].r, cf[k]);
+        VRec* rec = St::insert(a.slots[q[k]], w[k]);
+        if (rec) {
+          old[k] = unsafeAtomicAdd(&rec->r, cf[k]);
+        } else {
+          c->fault = 1;  // full table: the host sizes tables so that this cannot happen
+          w[k] = -1;
+        }
       }
     }
     // decisions: rank within (slot, list) from LDS counters, or a direct
@@ -462,20 +567,19 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
     for (int k = 0; k < kEdgesPerThread; k++) {
       if (rfn[k] < 0 && rtv[k] < 0) continue;
       const int j = q[k] - qlo;
-      const int64_t base = (int64_t)q[k] * n;
+      const Slot& S = a.slots[q[k]];
       if (rfn[k] >= 0) {
-        const int nxt = a.slots[q[k]].par ^ 1;
         const long long pos = (long long)s_bfn[j] + rfn[k];
-        if (pos < n) a.fbuf[2 * base + (int64_t)nxt * n + pos] = w[k]; else c->fault = 1;
+        if (pos < S.list_cap) S.fb[S.par ^ 1][pos] = w[k]; else c->fault = 1;
       }
       if (rtv[k] >= 0) {
         const long long pos = (long long)s_btv[j] + rtv[k];
-        if (pos < n) a.touched[base + pos] = w[k]; else c->fault = 1;
+        if (pos < S.list_cap) S.touched[pos] = w[k]; else c->fault = 1;
       }
     }
     __syncthreads();
   }
-  b_flush_hot(a, hs, s_hacc, &c->fault);
+  b_flush_hot<St>(a, hs, s_hacc, &c->fault);
 }
 
 __global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
@@ -493,8 +597,105 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
   if (S.cnt[S.par] == 0) S.status = SL_PUSHED;
 }
 
+// ---------------------------------------------------------------- compact tables
+
+constexpr int kMaxClearJobs = 2 * kMaxSlots;  // admissions + growths of one step
+
+// Clear every record (key kEmptyKey, r 0, rank 0) and p of each job's block;
+// x runs over the records of all jobs end to end.
+__global__ __launch_bounds__(kBlock) void k_c_clear(const ClearJob* jobs, int count,
+                                                    long long total) {
+  __shared__ long long s_off[kMaxClearJobs];
+  for (int j = threadIdx.x; j < count; j += kBlock) s_off[j] = jobs[j].off;
+  __syncthreads();
+  for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < total;
+       x += (long long)gridDim.x * kBlock) {
+    const int j = seg_of(s_off, count, x);
+    const ClearJob& J = jobs[j];
+    const long long i = x - s_off[j];
+    if (i >= J.cap) continue;
+    VRec r;
+    r.r = 0.0;
+    r.deg = kEmptyKey;
+    r.rank = 0;
+    J.tab[i] = r;
+    J.tp[i] = 0.0;
+  }
+}
+
+// Re-insert every record of the growing tables into their new (cleared)
+// tables.  x runs over the old records of all growing tables end to end.
+__global__ __launch_bounds__(kBlock) void k_c_rehash(BatchArgs a, const Grow* gr, int count,
+                                                     long long total) {
+  __shared__ long long s_off[kMaxSlots];
+  for (int j = threadIdx.x; j < count; j += kBlock) s_off[j] = gr[j].rec_off;
+  __syncthreads();
+  for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < total;
+       x += (long long)gridDim.x * kBlock) {
+    const int j = seg_of(s_off, count, x);
+    const Grow& G = gr[j];
+    const Slot& S = a.slots[G.slot];  // still the old table
+    const long long i = x - s_off[j];
+    if (i > G.old_mask) continue;
+    const VRec rec = S.tab[i];
+    if (rec.deg == kEmptyKey) continue;
+    Slot T;
+    T.tab = G.tab;
+    T.mask = G.new_mask;
+    VRec* dst = CompactState::insert(T, rec.deg);
+    if (!dst) {
+      a.ctl->fault = 1;
+      continue;
+    }
+    dst->r = rec.r;
+    dst->rank = rec.rank;
+    G.tp[dst - G.tab] = S.tp[i];
+  }
+}
+
+// Copy the lists of each growing slot (one workgroup per slot) and point the
+// slot at its new block.
+__global__ __launch_bounds__(kBlock) void k_c_move_lists(BatchArgs a, const Grow* gr, int count) {
+  const int j = blockIdx.x;
+  if (j >= count) return;
+  const Grow& G = gr[j];
+  Slot& S = a.slots[G.slot];
+  const int par = S.par;
+  const int n0 = S.cnt[par], n1 = S.cnt[par ^ 1], ns = S.support_cnt, nt = S.touched_cnt;
+  int32_t* nf0 = par == 0 ? G.fb0 : G.fb1;
+  int32_t* nf1 = par == 0 ? G.fb1 : G.fb0;
+  if (n0 > G.list_cap || n1 > G.list_cap || ns > G.list_cap || nt > G.list_cap) {
+    if (threadIdx.x == 0) a.ctl->fault = 1;
+    return;
+  }
+  for (int i = threadIdx.x; i < n0; i += kBlock) nf0[i] = S.fb[par][i];
+  for (int i = threadIdx.x; i < n1; i += kBlock) nf1[i] = S.fb[par ^ 1][i];
+  for (int i = threadIdx.x; i < ns; i += kBlock) G.support[i] = S.support[i];
+  for (int i = threadIdx.x; i < nt; i += kBlock) G.touched[i] = S.touched[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.tab = G.tab;
+    S.tp = G.tp;
+    S.fb[0] = G.fb0;
+    S.fb[1] = G.fb1;
+    S.support = G.support;
+    S.touched = G.touched;
+    S.mask = G.new_mask;
+    S.list_cap = G.list_cap;
+    S.hold = 0;
+  }
+}
+
+__global__ void k_slot_hold(BatchArgs a, const int32_t* holds, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int q = holds[i] & 0xffff;
+    if (q < a.B) a.slots[q].hold = holds[i] >> 16;
+  }
+}
+
 // ---------------------------------------------------------------- sweep
 
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_sw_keys(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int nseg = c->sw_nseg;
@@ -507,9 +708,12 @@ __global__ __launch_bounds__(kBlock) void k_sw_keys(BatchArgs a) {
        k += (long long)gridDim.x * kBlock) {
     const int s = seg_of(s_off, nseg, k);
     const SweepSeg& sg = a.segs[s];
-    const int64_t base = (int64_t)sg.slot * a.n;
-    const int32_t v = a.support[base + (k - s_off[s])];
-    const double ratio = a.p[base + v] / (double)a.vr[base + v].deg;
+    const Slot& S = a.slots[sg.slot];
+    const int32_t v = S.support[k - s_off[s]];
+    const VRec* rp = St::find(S, v);
+    double ratio = 0.0;
+    if (rp) ratio = *St::pp(S, v, rp) / (double)St::deg_hot(a, S, v).x;
+    else c->fault = 1;
     SortElem e;
     e.key = ~(unsigned long long)__double_as_longlong(ratio);
     e.id = v;
@@ -518,6 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_keys(BatchArgs a) {
   }
 }
 
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_sw_rank(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const long long total = c->sw_total;
@@ -526,13 +731,18 @@ __global__ __launch_bounds__(kBlock) void k_sw_rank(BatchArgs a) {
        k += (long long)gridDim.x * kBlock) {
     const SortElem e = el[k];
     const SweepSeg& sg = a.segs[e.seg];
+    const Slot& S = a.slots[sg.slot];
     const long long i = k - sg.elem_off;
-    const int64_t base = (int64_t)sg.slot * a.n;
-    a.vr[base + e.id].rank = (int32_t)(i + 1);
-    a.sdeg[k] = a.vr[base + e.id].deg;
+    VRec* rp = St::find(S, e.id);
+    if (!rp) {
+      c->fault = 1;
+      continue;
+    }
+    rp->rank = (int32_t)(i + 1);
+    a.sdeg[k] = St::deg_hot(a, S, e.id).x;
     if (sg.out_ids) {
       sg.out_ids[i] = e.id;
-      sg.out_p[i] = a.p[base + e.id];
+      sg.out_p[i] = *St::pp(S, e.id, rp);
     }
     a.scnt[k] = 0;
   }
@@ -596,6 +806,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_scan(BatchArgs a) {
   }
 }
 
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const long long total = c->sw_total;
@@ -643,7 +854,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
           if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
         }
         const int32_t w = a.nbr[s_row[lo] + (rel - s_start[lo])];
-        rw[kk] = a.vr[(int64_t)s_slot[lo] * a.n + w].rank;
+        rw[kk] = St::rank_of(a.slots[s_slot[lo]], w);
         own[kk] = lo;
       }
     }
@@ -708,7 +919,11 @@ __global__ __launch_bounds__(kBlock) void k_sw_argmin(BatchArgs a) {
   }
 }
 
-// Gather the nonzeros of r of every swept query and reset its slot state.
+// Gather the nonzeros of r of every swept query.  Dense: walk each touched
+// list and reset r (p and rank are reset by k_sw_reset).  Compact: scan each
+// table (x runs over records; the block is returned to the arena afterwards,
+// so nothing is reset).
+template <class St>
 __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int nseg = c->sw_nseg;
@@ -730,11 +945,18 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
     if (x < total) {
       s = seg_of(s_toff, nseg, x);
       const SweepSeg& sg = a.segs[s];
-      const int64_t base = (int64_t)sg.slot * a.n;
-      v = a.touched[base + (x - s_toff[s])];
-      VRec* rec = a.vr + base + v;
-      rv = rec->r;
-      rec->r = 0.0;  // p and rank are non-zero on the support only (k_sw_reset)
+      const Slot& S = a.slots[sg.slot];
+      const long long i = x - s_toff[s];
+      if (St::kCompact) {
+        const VRec rec = S.tab[i];
+        v = rec.deg;
+        rv = v != kEmptyKey ? rec.r : 0.0;
+      } else {
+        v = S.touched[i];
+        VRec* rec = S.tab + v;
+        rv = rec->r;
+        rec->r = 0.0;
+      }
       if (rv != 0.0) rk = atomicAdd(&s_cnt[s - slo], 1);  // s - slo < kBlock
     }
     __syncthreads();
@@ -747,15 +969,15 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
     if (rk >= 0) {
       const SweepSeg& sg = a.segs[s];
       const long long pos = (long long)s_base[s - slo] + rk;
-      if (pos >= sg.n_touch) c->fault = 1;
+      if (pos >= a.slots[sg.slot].touched_cnt) c->fault = 1;
       else if (sg.out_rid) { sg.out_rid[pos] = v; sg.out_rval[pos] = rv; }
     }
     __syncthreads();
   }
 }
 
-// Reset p and the sweep rank of every swept support vertex (after the
-// boundary counts and the argmin no longer need them).
+// Dense layout: reset p and the sweep rank of every swept support vertex
+// (after the boundary counts and the argmin no longer need them).
 __global__ __launch_bounds__(kBlock) void k_sw_reset(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const long long total = c->sw_total;
@@ -763,9 +985,9 @@ __global__ __launch_bounds__(kBlock) void k_sw_reset(BatchArgs a) {
   for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < total;
        k += (long long)gridDim.x * kBlock) {
     const SortElem e = el[k];
-    const int64_t base = (int64_t)a.segs[e.seg].slot * a.n;
-    a.vr[base + e.id].rank = a.hotcode[e.id];
-    a.p[base + e.id] = 0.0;
+    const Slot& S = a.slots[a.segs[e.seg].slot];
+    S.tab[e.id].rank = a.hotcode[e.id];
+    S.tp[e.id] = 0.0;
   }
 }
 
@@ -779,20 +1001,39 @@ hipError_t launch_batch_init(hipStream_t s, const BatchArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count) {
+hipError_t launch_gdh_init(hipStream_t s, const BatchArgs& a, int2* gdh) {
+  int grid = (int)((a.n + kBlock - 1) / kBlock);
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_gdh_init, dim3(grid), dim3(kBlock), 0, s, a, gdh);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count,
+                              bool compact) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_b_admit, dim3(1), dim3(256), 0, s, a, adm, count);
+  if (compact)
+    hipLaunchKernelGGL(k_b_admit<CompactState>, dim3(1), dim3(256), 0, s, a, adm, count);
+  else
+    hipLaunchKernelGGL(k_b_admit<DenseState>, dim3(1), dim3(256), 0, s, a, adm, count);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self) {
+hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self, bool compact) {
   hipLaunchKernelGGL(k_b_plan, dim3(1), dim3(kMaxSlots), 0, s, a);
-  hipLaunchKernelGGL(k_b_self, dim3(grid_self), dim3(kBlock), 0, s, a);
+  if (compact)
+    hipLaunchKernelGGL(k_b_self<CompactState>, dim3(grid_self), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_b_self<DenseState>, dim3(grid_self), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter) {
-  hipLaunchKernelGGL(k_b_scatter, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter,
+                                bool compact) {
+  if (compact)
+    hipLaunchKernelGGL(k_b_scatter<CompactState>, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_b_scatter<DenseState>, dim3(grid_scatter), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -801,10 +1042,10 @@ hipError_t launch_batch_round_end(hipStream_t s, const BatchArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
-                              int grid) {
-  if (nseg <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sw_keys, dim3(grid), dim3(kBlock), 0, s, a);
+template <class St>
+static hipError_t sweep_kernels(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
+                                int grid) {
+  hipLaunchKernelGGL(k_sw_keys<St>, dim3(grid), dim3(kBlock), 0, s, a);
   SortArgs sa;
   sa.buf[0] = a.sbuf[0];
   sa.buf[1] = a.sbuf[1];
@@ -815,13 +1056,41 @@ hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64
   sa.active_value = 0;
   hipError_t e = launch_sort(s, sa, max_elems, grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sw_rank, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_rank<St>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_scan<false>, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sw_count, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_count<St>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_scan<true>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_argmin, dim3(nseg), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sw_finish, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sw_finish<St>, dim3(grid), dim3(kBlock), 0, s, a);
+  if (!St::kCompact) hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
+                              int grid, bool compact) {
+  if (nseg <= 0) return hipSuccess;
+  return compact ? sweep_kernels<CompactState>(s, a, nseg, max_elems, grid)
+                 : sweep_kernels<DenseState>(s, a, nseg, max_elems, grid);
+}
+
+hipError_t launch_table_clear(hipStream_t s, const ClearJob* jobs, int count, long long total,
+                              int grid) {
+  if (count <= 0 || count > kMaxClearJobs) return count <= 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_c_clear, dim3(grid), dim3(kBlock), 0, s, jobs, count, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_table_grow(hipStream_t s, const BatchArgs& a, const Grow* gr, int count,
+                             long long total_old, int grid) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_c_rehash, dim3(grid), dim3(kBlock), 0, s, a, gr, count, total_old);
+  hipLaunchKernelGGL(k_c_move_lists, dim3(count), dim3(kBlock), 0, s, a, gr, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_slot_hold(hipStream_t s, const BatchArgs& a, const int32_t* holds, int count) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_hold, dim3(1), dim3(256), 0, s, a, holds, count);
   return hipGetLastError();
 }
 

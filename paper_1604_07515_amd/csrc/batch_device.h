@@ -2,13 +2,25 @@
 // together, one round-synchronous PR-Nibble round per global step, and the
 // queries whose frontier emptied are swept together.
 //
-// Per batch slot q (dense, like the plain path, so that the scatter needs no
-// probing): VRec vr[q*n + v], double p[q*n + v], two frontier buffers
-// fbuf[(2q+k)*n + i], a support list and a touched list.  A slot's state is
-// reset through its touched list when its query retires, so admitting the
-// next query costs O(1).  Round buffers (per-entry coefficient, row, edge
-// start, slot) are shared by all slots: a round's entries are the
-// concatenation of the scheduled slots' frontiers, in slot order.
+// Every slot q reaches its state through pointers in its Slot record (set by
+// the host at admission):
+//   tab   16-byte records {r, d or key, rank}
+//   tp    p, parallel to tab
+//   fb[2] frontier buffers, support, touched: vertex-id lists of list_cap
+// Two state layouts share the kernels (a template parameter):
+//   dense   (DenseState)   tab/tp are the slot's slices of engine-wide
+//           arrays indexed by vertex id (n records per slot), like the plain
+//           path; the scatter's atomic needs no probing.  Reset through the
+//           touched list when the query retires.
+//   compact (CompactState) tab/tp are a per-query open-addressing table of
+//           capacity mask+1 (a power of 2, linear probing, at most half
+//           full), allocated from the arena at admission and grown between
+//           rounds, so a query holds memory in proportion to the vertices it
+//           touched rather than to n.  d(v) and the hot code come from a
+//           graph-wide array.
+// Round buffers (per-entry coefficient, row, edge start, slot) are shared by
+// all slots: a round's entries are the concatenation of the scheduled slots'
+// frontiers, in slot order.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -20,6 +32,8 @@
 namespace plc {
 
 enum : int32_t { SL_FREE = 0, SL_PUSH = 1, SL_PUSHED = 2, SL_SWEEP = 3 };
+
+constexpr int32_t kEmptyKey = -1;  // key of a free compact-table record
 
 struct __align__(64) Slot {
   double cs, cn, keep, eps;
@@ -37,7 +51,16 @@ struct __align__(64) Slot {
   // sweep results
   long long kstar, best_cut, best_vol, best_den;
   double phi;
-  int32_t rnnz, pad;
+  int32_t rnnz;
+  int32_t hold;             // compact: 1 = skip rounds until the table has grown
+  // state (see above)
+  VRec* tab;
+  double* tp;
+  int32_t* fb[2];
+  int32_t* support;
+  int32_t* touched;
+  int32_t mask;             // compact: table capacity - 1
+  int32_t list_cap;         // capacity of each list
 };
 
 // One query's part of a sweep batch (written by the host before the sweep).
@@ -45,8 +68,9 @@ struct __align__(16) SweepSeg {
   int32_t slot;
   int32_t n_elem;           // support size
   long long elem_off;       // first element of the segment
-  long long touch_off;      // first touched-list position of the segment (flattened)
-  int32_t n_touch;
+  long long touch_off;      // first finish entry of the segment (flattened): touched-list
+                            // positions (dense) or table records (compact)
+  int32_t n_touch;          // touched-list length (dense) or table capacity (compact)
   int32_t pad;
   int32_t* out_ids;         // support in sweep order (NULL: discard the vectors)
   double* out_p;            // p at those vertices
@@ -64,7 +88,7 @@ struct __align__(64) BatchCtl {
   int32_t sort_flip;
   int32_t sw_nseg;          // sweep: segments
   int32_t sw_total;         // sweep: elements
-  long long sw_touch_total; // sweep: touched entries
+  long long sw_touch_total; // sweep: finish entries
   long long sw_etotal;      // sweep: volume of all swept supports
   int32_t sw_ntiles;        // sweep: edge tiles
   int32_t pad0;
@@ -79,11 +103,8 @@ struct BatchArgs {
   const int32_t* nbr;
   int32_t B;                // slots
   Slot* slots;
-  VRec* vr;                 // [B*n]
-  double* p;                // [B*n]
-  int32_t* fbuf;            // [2*B*n]
-  int32_t* support;         // [B*n]
-  int32_t* touched;         // [B*n]
+  VRec* vr;                 // dense: [B*n]
+  double* p;                // dense: [B*n]
   BatchCtl* ctl;
   // round buffers
   int32_t* fprefix;         // [B+1]
@@ -107,21 +128,60 @@ struct BatchArgs {
   int64_t s_cap;
   const int32_t* hot_ids;   // [kHot] vertex of hot index j (graph-wide)
   const int32_t* hotcode;   // [n] -(j+1) for hot vertex j, else 0
+  const int2* gdh;          // [n] {d(v), hot code} (graph-wide; compact layout)
 };
 
-// Admission record (host-written).
+// Admission record (host-written): the query and the slot's state pointers.
 struct __align__(16) Admit {
   int32_t slot, seed, rule, max_rounds;
   double alpha, eps;
-  int32_t seed_deg, pad;
+  int32_t seed_deg, mask, list_cap, pad;
+  VRec* tab;
+  double* tp;
+  int32_t* fb0;
+  int32_t* fb1;
+  int32_t* support;
+  int32_t* touched;
 };
 
-hipError_t launch_batch_init(hipStream_t s, const BatchArgs& a);
-hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count);
-hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self);
-hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter);
+// Compact layout: a table that moves to a larger block (host-written).
+struct __align__(16) Grow {
+  int32_t slot;
+  int32_t old_mask, new_mask, list_cap;
+  long long rec_off;        // first record of this table in the flattened rehash index
+  VRec* tab;
+  double* tp;
+  int32_t* fb0;
+  int32_t* fb1;
+  int32_t* support;
+  int32_t* touched;
+};
+
+// Compact layout: one table block to clear (host-written); off = first
+// record of this job in the flattened index over all jobs of a launch.
+struct __align__(16) ClearJob {
+  VRec* tab;
+  double* tp;
+  long long cap;
+  long long off;
+};
+
+hipError_t launch_batch_init(hipStream_t s, const BatchArgs& a);      // dense layout
+hipError_t launch_gdh_init(hipStream_t s, const BatchArgs& a, int2* gdh);  // compact layout
+hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count,
+                              bool compact);
+hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self, bool compact);
+hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter,
+                                bool compact);
 hipError_t launch_batch_round_end(hipStream_t s, const BatchArgs& a);
 hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
+                              int grid, bool compact);
+// compact layout: clear table blocks (records and p), move grown tables,
+// set the slots' hold flags (holds[i] = slot | flag << 16)
+hipError_t launch_table_clear(hipStream_t s, const ClearJob* jobs, int count, long long total,
                               int grid);
+hipError_t launch_table_grow(hipStream_t s, const BatchArgs& a, const Grow* gr, int count,
+                             long long total_old, int grid);
+hipError_t launch_slot_hold(hipStream_t s, const BatchArgs& a, const int32_t* holds, int count);
 
 }  // namespace plc

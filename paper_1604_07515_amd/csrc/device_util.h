@@ -180,6 +180,17 @@ __device__ __forceinline__ void block_flush(int32_t* counter, int32_t* dst, int6
   __syncthreads();
 }
 
+// The dispatcher hands workgroups to the 8 XCDs round-robin (XCD =
+// blockIdx % 8), and each XCD has its own L2.  xcd_block renumbers the
+// workgroups of a grid of G so that those of one XCD get consecutive numbers
+// (a bijection on [0, G)).  A kernel that gives contiguous work ranges by
+// this number keeps neighbouring work -- in the batched kernels, the edges of
+// one slot, whose state lines they share -- inside one L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int q = G >> 3, r = G & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
 // a/b < c/d exactly, for b, d > 0.
 __device__ __forceinline__ bool ratio_lt(long long a, long long b, long long c, long long d) {
   return (__int128)a * (__int128)d < (__int128)c * (__int128)b;

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstddef>
@@ -48,6 +49,35 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+static void event_pair_free(EventPair& e) {
+  if (e.a) (void)hipEventDestroy(e.a);
+  if (e.b) (void)hipEventDestroy(e.b);
+  e = EventPair{};
+}
+
+// A launch sequence recorded once as a HIP graph (on the context's capture
+// stream) and replayed with one hipGraphLaunch on the caller's stream.  The
+// fields below exec say what it was recorded for; a timed graph also holds
+// event-record nodes around the kernels that are timed, one pair per round.
+struct Captured {
+  hipGraphExec_t exec = nullptr;
+  int gs = -1, gc = -1, gw = -1, rounds = -1;
+  bool timed = false;
+  std::vector<EventPair> ev_self, ev_scatter;
+  EventPair ev_sweep;
+  bool matches(int s, int c, int w, int r, bool t) const {
+    return exec && gs == s && gc == c && gw == w && rounds == r && timed == t;
+  }
+};
+
+static void captured_free(Captured& c) {
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  for (auto& e : c.ev_self) event_pair_free(e);
+  for (auto& e : c.ev_scatter) event_pair_free(e);
+  event_pair_free(c.ev_sweep);
+  c = Captured{};
+}
+
 struct KTime {
   int64_t launches = 0;
   double ms = 0;
@@ -79,6 +109,23 @@ struct BatchEngine {
   std::vector<Result> sweeping;      // result blocks filled by the sweep in flight
   std::deque<std::pair<uint64_t, plc_query>> queue;
   size_t bytes = 0;
+  Captured round_g;                  // one round: plan, self, scatter, round end
+  bool compact = false;              // PLC_STATE_COMPACT
+  // dense layout: the slots' lists, slices of q*n (frontiers: (2q+k)*n)
+  int32_t* d_fbuf = nullptr;
+  int32_t* d_support = nullptr;
+  int32_t* d_touched = nullptr;
+  // compact layout: per slot, the running query's block and table capacity
+  std::vector<void*> qblock;
+  std::vector<int64_t> qcap;
+  std::vector<int> hold;             // hold flag last sent to the device
+  std::vector<char> fresh;           // admitted this step: slots_h not read back yet
+  plc::Grow* grow_h = nullptr;       // pinned grow records
+  plc::Grow* grow_d = nullptr;
+  int32_t* holds_h = nullptr;        // pinned hold updates
+  int32_t* holds_d = nullptr;
+  plc::ClearJob* clear_h = nullptr;  // pinned table clears of one step (2B)
+  plc::ClearJob* clear_d = nullptr;
 };
 
 }  // namespace
@@ -95,6 +142,8 @@ struct plc_graph {
   int plain_self = 0, plain_scatter = 0, plain_sweep = 0;
   int batch_self = 0, batch_scatter = 0, batch_sweep = 0;
   BatchEngine* batch = nullptr;
+  std::map<int, Captured> chunk_g;  // plain path: R rounds of (self, scatter), R a power of 2
+  Captured sweep_g;                 // plain path: the sweep sequence
 };
 
 struct plc_ctx {
@@ -104,13 +153,15 @@ struct plc_ctx {
   plc_options opt{};
   Ctl* ctl_host = nullptr;  // pinned
   std::map<uint64_t, Result> results;
-  std::set<uint64_t> inflight;  // submitted to a batch engine, not finished
+  std::map<uint64_t, plc_graph*> inflight;  // submitted to a batch engine, not finished
   uint64_t next_id = 1;
   bool broken = false;
   std::set<plc_graph*> graphs;
   int num_cu = 256;
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
   int chunk_rounds = 16;
+  bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
+  hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
   bool timing = false;
   std::vector<EventPair> ev_scatter, ev_self;
   EventPair ev_sweep;
@@ -167,11 +218,22 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
     return PLC_E_HIP;
   }
   std::memset(c->ctl_host, 0, sizeof(Ctl));
+  // The caller's stream may be the null stream, which cannot be captured, so
+  // graphs are recorded on a stream of our own and replayed on the caller's.
+  if (c->opt.launch_mode == PLC_LAUNCH_GRAPH &&
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess)
+    c->use_graphs = true;
   *out = c;
   return PLC_OK;
 }
 
 static void batch_free(plc_ctx* ctx, plc_graph* g);
+
+static void graph_captures_free(plc_graph* g) {
+  for (auto& kv : g->chunk_g) captured_free(kv.second);
+  g->chunk_g.clear();
+  captured_free(g->sweep_g);
+}
 
 static void free_events(plc_ctx* c) {
   for (auto& e : c->ev_scatter) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
@@ -188,9 +250,11 @@ extern "C" plc_status plc_destroy(plc_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (plc_graph* g : ctx->graphs) {
     batch_free(ctx, g);
+    graph_captures_free(g);
     delete g;
   }
   free_events(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
   delete ctx;
   return PLC_OK;
@@ -373,6 +437,7 @@ extern "C" plc_status plc_graph_free(plc_ctx* ctx, plc_graph* g) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   batch_free(ctx, g);
+  graph_captures_free(g);
   graph_release_blocks(ctx, g);
   ctx->graphs.erase(g);
   delete g;
@@ -406,10 +471,106 @@ static hipError_t ev_pair(EventPair& e) {
   return hipEventCreate(&e.b);
 }
 
-// Queue `rounds` rounds; with timing on, bracket each kernel with events.
 static int shape(int tuned, int dflt) { return tuned > 0 ? tuned : dflt; }
 
-static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int first, int rounds) {
+// Record body(stream) into c.exec.  On failure the context stops using graphs
+// (direct launches run the same kernels) and false is returned.
+template <class F>
+static bool capture(plc_ctx* ctx, Captured& c, F&& body) {
+  hipStream_t cs = ctx->cap_stream;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t eb = body(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    e = eb != hipSuccess ? eb : ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    c.exec = nullptr;
+    captured_free(c);
+    ctx->use_graphs = false;
+    return false;
+  }
+  return true;
+}
+
+static hipError_t ev_ext(hipEvent_t ev, hipStream_t cs) {
+  return hipEventRecordWithFlags(ev, cs, hipEventRecordExternal);
+}
+
+// Graph of R plain rounds (self, scatter); timed graphs bracket each kernel
+// with events.
+static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
+  const int gs = shape(g->plain_self, ctx->grid_self);
+  const int gc = shape(g->plain_scatter, ctx->grid_scatter);
+  Captured& c = g->chunk_g[R];
+  if (c.matches(gs, gc, 0, R, ctx->timing)) return &c;
+  captured_free(c);
+  c.gs = gs;
+  c.gc = gc;
+  c.gw = 0;
+  c.rounds = R;
+  c.timed = ctx->timing;
+  if (c.timed) {
+    c.ev_self.resize(R);
+    c.ev_scatter.resize(R);
+    for (int i = 0; i < R; i++)
+      if (ev_pair(c.ev_self[i]) != hipSuccess || ev_pair(c.ev_scatter[i]) != hipSuccess) {
+        captured_free(c);
+        ctx->use_graphs = false;
+        return nullptr;
+      }
+  }
+  const PlainArgs& a = g->args;
+  const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
+    hipError_t r;
+    for (int i = 0; i < R; i++) {
+      if (c.timed && (r = ev_ext(c.ev_self[i].a, cs)) != hipSuccess) return r;
+      if ((r = plc::launch_self(cs, a, gs)) != hipSuccess) return r;
+      if (c.timed && (r = ev_ext(c.ev_self[i].b, cs)) != hipSuccess) return r;
+      if (c.timed && (r = ev_ext(c.ev_scatter[i].a, cs)) != hipSuccess) return r;
+      if ((r = plc::launch_scatter(cs, a, gc)) != hipSuccess) return r;
+      if (c.timed && (r = ev_ext(c.ev_scatter[i].b, cs)) != hipSuccess) return r;
+    }
+    return hipSuccess;
+  });
+  return ok ? &c : nullptr;
+}
+
+// Graph of the plain sweep sequence.
+static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g) {
+  const int gw = shape(g->plain_sweep, ctx->grid_sweep);
+  Captured& c = g->sweep_g;
+  if (c.matches(0, 0, gw, 0, ctx->timing)) return &c;
+  captured_free(c);
+  c.gs = 0;
+  c.gc = 0;
+  c.gw = gw;
+  c.rounds = 0;
+  c.timed = ctx->timing;
+  if (c.timed && ev_pair(c.ev_sweep) != hipSuccess) {
+    captured_free(c);
+    ctx->use_graphs = false;
+    return nullptr;
+  }
+  const PlainArgs& a = g->args;
+  const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
+    hipError_t r;
+    if (c.timed && (r = ev_ext(c.ev_sweep.a, cs)) != hipSuccess) return r;
+    if ((r = plc::launch_sweep(cs, a, gw)) != hipSuccess) return r;
+    if (c.timed && (r = ev_ext(c.ev_sweep.b, cs)) != hipSuccess) return r;
+    return hipSuccess;
+  });
+  return ok ? &c : nullptr;
+}
+
+// Queue `rounds` rounds; with timing on, bracket each kernel with events
+// (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk).
+
+static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
   const PlainArgs& a = g->args;
   hipStream_t s = ctx->stream;
   const int gs = shape(g->plain_self, ctx->grid_self);
@@ -417,7 +578,7 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int first, int 
   for (int i = 0; i < rounds; i++) {
     hipError_t r;
     if (ctx->timing) {
-      size_t k = (size_t)(first + i);
+      size_t k = (size_t)i;
       while (ctx->ev_self.size() <= k) ctx->ev_self.emplace_back();
       while (ctx->ev_scatter.size() <= k) ctx->ev_scatter.emplace_back();
       if ((r = ev_pair(ctx->ev_self[k])) != hipSuccess) return r;
@@ -445,17 +606,60 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   int queued = 0;
   int chunk = std::max(2, ctx->chunk_rounds);
   Ctl& h = *ctx->ctl_host;
+  const EventPair* sweep_ev = &ctx->ev_sweep;
   for (;;) {
-    HIPCHK(ctx, queue_rounds(ctx, g, queued, chunk));
-    queued += chunk;
-    if (ctx->timing) {
-      HIPCHK(ctx, ev_pair(ctx->ev_sweep));
-      HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
+    // a chunk of R rounds: a replayed graph (R rounded up to a power of 2) or
+    // direct launches
+    int R = chunk;
+    Captured* cg = nullptr;
+    if (ctx->use_graphs) {
+      R = 2;
+      while (R < chunk) R <<= 1;
+      cg = plain_chunk_graph(ctx, g, R);
     }
-    HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
-    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
+    const EventPair* ev_s;
+    const EventPair* ev_c;
+    if (cg) {
+      HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
+      ev_s = cg->ev_self.data();
+      ev_c = cg->ev_scatter.data();
+    } else {
+      R = chunk;
+      HIPCHK(ctx, queue_rounds(ctx, g, R));
+      ev_s = ctx->ev_self.data();
+      ev_c = ctx->ev_scatter.data();
+    }
+    // the sweep (its kernels exit at once while the push is still running)
+    Captured* sg = ctx->use_graphs ? plain_sweep_graph(ctx, g) : nullptr;
+    if (sg) {
+      HIPCHK(ctx, hipGraphLaunch(sg->exec, s));
+      sweep_ev = &sg->ev_sweep;
+    } else {
+      if (ctx->timing) {
+        HIPCHK(ctx, ev_pair(ctx->ev_sweep));
+        HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
+      }
+      HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
+      if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
+      sweep_ev = &ctx->ev_sweep;
+    }
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
+    if (ctx->timing) {
+      // every round of an earlier chunk pushed (else the query would have
+      // ended there), so this chunk's pushing rounds are the first h.round - queued
+      const int ran = std::max(0, std::min(R, h.round - queued));
+      float ms = 0;
+      for (int i = 0; i < ran; i++) {
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ev_c[i].a, ev_c[i].b));
+        ctx->t_scatter.ms += ms;
+        ctx->t_scatter.launches++;
+        HIPCHK(ctx, hipEventElapsedTime(&ms, ev_s[i].a, ev_s[i].b));
+        ctx->t_self.ms += ms;
+        ctx->t_self.launches++;
+      }
+    }
+    queued += R;
     if (h.status == plc::ST_SWEPT) break;
     if (h.status != plc::ST_PUSH) {  // unexpected state: device-side fault
       ctx->broken = true;
@@ -471,19 +675,11 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   if (ctx->timing) {
     float ms = 0;
-    for (int i = 0; i < h.round && i < queued; i++) {
-      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_scatter[i].a, ctx->ev_scatter[i].b));
-      ctx->t_scatter.ms += ms;
-      ctx->t_scatter.launches++;
-      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_self[i].a, ctx->ev_self[i].b));
-      ctx->t_self.ms += ms;
-      ctx->t_self.launches++;
-    }
     ctx->t_scatter.units += h.edges;
     ctx->t_scatter.entries += h.pushes;
     ctx->t_self.units += h.pushes;
     ctx->t_self.entries += h.pushes;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_sweep.a, ctx->ev_sweep.b));
+    HIPCHK(ctx, hipEventElapsedTime(&ms, sweep_ev->a, sweep_ev->b));
     ctx->t_sweep.ms += ms;
     ctx->t_sweep.launches++;
     ctx->t_sweep.units += h.etotal;
@@ -642,6 +838,11 @@ extern "C" plc_status plc_timing_get(plc_ctx* ctx, plc_kernel_time* scatter, plc
 
 // ---------------------------------------------------------------- batched path
 
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 static void batch_free(plc_ctx* ctx, plc_graph* g) {
   BatchEngine* E = g->batch;
   if (!E) return;
@@ -656,6 +857,12 @@ static void batch_free(plc_ctx* ctx, plc_graph* g) {
   if (E->adm_h) (void)hipHostFree(E->adm_h);
   if (E->ctl_h) (void)hipHostFree(E->ctl_h);
   if (E->hdr_h) (void)hipHostFree(E->hdr_h);
+  if (E->grow_h) (void)hipHostFree(E->grow_h);
+  if (E->holds_h) (void)hipHostFree(E->holds_h);
+  if (E->clear_h) (void)hipHostFree(E->clear_h);
+  for (void* b : E->qblock)
+    if (b) ctx->arena.release(b);
+  captured_free(E->round_g);
   delete E;
   g->batch = nullptr;
 }
@@ -682,9 +889,27 @@ static size_t batch_fixed_bytes(const plc_graph* g, int B) {
   size_t b = 0;
   b += 28 * (size_t)nf_cap + 4 * (size_t)tile_cap + 3 * 16 * (size_t)desc_cap;
   b += (2 * sizeof(plc::SortElem) + 4 + 8 + 4 + 8) * (size_t)s_cap;
-  b += (sizeof(plc::Slot) + sizeof(plc::SweepSeg) + sizeof(plc::Admit) + 8) * (size_t)B;
-  b += 64 * 1024;
+  b += (sizeof(plc::Slot) + sizeof(plc::SweepSeg) + sizeof(plc::Admit) + sizeof(plc::Grow) +
+        2 * sizeof(plc::ClearJob) + 12) * (size_t)B;
+  b += 8 * (size_t)g->n + 64 * 1024;  // compact: graph-wide {d, hot code}
   return b;
+}
+
+// Compact layout: table capacity (a power of 2, at least 256) for `need`
+// keys at load factor 1/2, and the bytes of a query block of that capacity:
+// records (16 B) + p (8 B) + four lists of cap/2 ids (8 B).
+static int64_t table_cap_for(const plc_graph* g, int64_t need) {
+  need = std::min<int64_t>(std::max<int64_t>(need, 1), g->n);
+  int64_t cap = 256;
+  while (cap < 2 * need) cap <<= 1;
+  return cap;
+}
+static size_t table_block_bytes(int64_t cap) { return 32 * (size_t)cap; }
+
+// Arena kept free for result blocks when tables are taken (admission) or
+// grown (half of it).
+static size_t result_headroom(const plc_ctx* ctx) {
+  return std::max<size_t>((size_t)64 << 20, ctx->arena.capacity() / 32);
 }
 
 static size_t batch_slot_bytes(const plc_graph* g) {
@@ -717,12 +942,23 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   a.hot_ids = g->args.hot_ids;
   a.hotcode = g->args.hotcode;
   a.B = B;
+  E->compact = ctx->opt.batch_state == PLC_STATE_COMPACT;
   a.slots = static_cast<plc::Slot*>(take(sizeof(plc::Slot) * B));
-  a.vr = static_cast<plc::VRec*>(take(sizeof(plc::VRec) * n * B));
-  a.p = static_cast<double*>(take(8 * n * B));
-  a.fbuf = static_cast<int32_t*>(take(4 * 2 * n * B));
-  a.support = static_cast<int32_t*>(take(4 * n * B));
-  a.touched = static_cast<int32_t*>(take(4 * n * B));
+  if (E->compact) {
+    a.vr = nullptr;
+    a.p = nullptr;
+    a.gdh = static_cast<int2*>(take(8 * n));
+  } else {
+    a.vr = static_cast<plc::VRec*>(take(sizeof(plc::VRec) * n * B));
+    a.p = static_cast<double*>(take(8 * n * B));
+    E->d_fbuf = static_cast<int32_t*>(take(4 * 2 * n * B));
+    E->d_support = static_cast<int32_t*>(take(4 * n * B));
+    E->d_touched = static_cast<int32_t*>(take(4 * n * B));
+    a.gdh = nullptr;
+  }
+  E->grow_d = static_cast<plc::Grow*>(take(sizeof(plc::Grow) * B));
+  E->holds_d = static_cast<int32_t*>(take(4 * (size_t)B));
+  E->clear_d = static_cast<plc::ClearJob*>(take(sizeof(plc::ClearJob) * 2 * (size_t)B));
   a.ctl = static_cast<plc::BatchCtl*>(take(sizeof(plc::BatchCtl)));
   a.fprefix = static_cast<int32_t*>(take(4 * ((size_t)B + 1)));
   a.eslot = static_cast<int32_t*>(take(4 * (size_t)nf_cap));
@@ -751,6 +987,10 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   }
   E->state.assign(B, HS_FREE);
   E->qid.assign(B, 0);
+  E->qblock.assign(B, nullptr);
+  E->qcap.assign(B, 0);
+  E->hold.assign(B, 0);
+  E->fresh.assign(B, 0);
   if (hipHostMalloc(reinterpret_cast<void**>(&E->slots_h), sizeof(plc::Slot) * B,
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&E->segs_h), sizeof(plc::SweepSeg) * B,
@@ -760,6 +1000,12 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
       hipHostMalloc(reinterpret_cast<void**>(&E->ctl_h), sizeof(plc::BatchCtl),
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&E->hdr_h), sizeof(SweepHdr),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->grow_h), sizeof(plc::Grow) * B,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->holds_h), 4 * (size_t)B,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&E->clear_h), sizeof(plc::ClearJob) * 2 * (size_t)B,
                     hipHostMallocDefault) != hipSuccess) {
     batch_free(ctx, g);
     ctx->broken = true;
@@ -770,7 +1016,10 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   HIPCHK(ctx, hipMemsetAsync(a.ctl, 0, sizeof(plc::BatchCtl), s));
   for (int k = 0; k < plc::BNUM_SCANS; k++)
     HIPCHK(ctx, hipMemsetAsync(a.desc[k], 0, 2 * 8 * (size_t)desc_cap, s));
-  HIPCHK(ctx, plc::launch_batch_init(s, a));
+  if (E->compact)
+    HIPCHK(ctx, plc::launch_gdh_init(s, a, const_cast<int2*>(a.gdh)));
+  else
+    HIPCHK(ctx, plc::launch_batch_init(s, a));
   HIPCHK(ctx, hipStreamSynchronize(s));
   return PLC_OK;
 }
@@ -788,7 +1037,7 @@ extern "C" plc_status plc_batch_reserve(plc_ctx* ctx, plc_graph* g, int32_t slot
   // Largest slot count that fits the free arena (one block per array),
   // keeping headroom for the result blocks of finished queries.
   int B = slots;
-  const size_t per = batch_slot_bytes(g);
+  const size_t per = ctx->opt.batch_state == PLC_STATE_COMPACT ? 0 : batch_slot_bytes(g);
   const size_t free_now = ctx->arena.free_bytes();
   const size_t headroom = std::max<size_t>((size_t)64 << 20, free_now / 16);
   const size_t budget = free_now > headroom ? free_now - headroom : 0;
@@ -821,10 +1070,44 @@ extern "C" plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q,
     }
     uint64_t id = ctx->next_id++;
     g->batch->queue.emplace_back(id, q[i]);
-    ctx->inflight.insert(id);
+    ctx->inflight[id] = g;
     if (ids) ids[i] = id;
   }
   return first;
+}
+
+// Graph of one batched round: plan, self, scatter (timed graphs bracket it
+// with events), round end.
+static Captured* batch_round_graph(plc_ctx* ctx, plc_graph* g) {
+  const int gs = shape(g->batch_self, ctx->grid_self);
+  const int gc = shape(g->batch_scatter, ctx->grid_scatter);
+  Captured& c = g->batch->round_g;
+  if (c.matches(gs, gc, 0, 1, ctx->timing)) return &c;
+  captured_free(c);
+  c.gs = gs;
+  c.gc = gc;
+  c.gw = 0;
+  c.rounds = 1;
+  c.timed = ctx->timing;
+  if (c.timed) {
+    c.ev_scatter.resize(1);
+    if (ev_pair(c.ev_scatter[0]) != hipSuccess) {
+      captured_free(c);
+      ctx->use_graphs = false;
+      return nullptr;
+    }
+  }
+  const plc::BatchArgs& a = g->batch->args;
+  const bool compact = g->batch->compact;
+  const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
+    hipError_t r;
+    if ((r = plc::launch_batch_plan_self(cs, a, gs, compact)) != hipSuccess) return r;
+    if (c.timed && (r = ev_ext(c.ev_scatter[0].a, cs)) != hipSuccess) return r;
+    if ((r = plc::launch_batch_scatter(cs, a, gc, compact)) != hipSuccess) return r;
+    if (c.timed && (r = ev_ext(c.ev_scatter[0].b, cs)) != hipSuccess) return r;
+    return plc::launch_batch_round_end(cs, a);
+  });
+  return ok ? &c : nullptr;
 }
 
 // One global step.  defer_sweep: while other queries are still pushing and
@@ -835,14 +1118,53 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   BatchEngine& E = *g->batch;
   plc::BatchArgs& a = E.args;
   hipStream_t s = ctx->stream;
-  // 1. admission into free slots, in submission order
-  int nadm = 0;
+  // 1. admission into free slots, in submission order (compact layout: while
+  // the arena holds the query's first table and the result headroom)
+  const int64_t n = g->n;
+  int nadm = 0, njobs = 0;
+  long long clear_total = 0;
   for (int q = 0; q < E.B && !E.queue.empty(); q++) {
     if (E.state[q] != HS_FREE) continue;
     const uint64_t id = E.queue.front().first;
     const plc_query qq = E.queue.front().second;
+    plc::Admit& ad = E.adm_h[nadm];
+    if (E.compact) {
+      const int64_t cap = table_cap_for(g, 1 + (int64_t)g->deg[qq.seed]);
+      const size_t bytes = table_block_bytes(cap);
+      if (ctx->arena.free_bytes() < bytes + result_headroom(ctx)) break;
+      void* blk = ctx->arena.alloc(bytes);
+      if (!blk) break;
+      char* b = static_cast<char*>(blk);
+      const int64_t L = cap / 2;
+      ad.tab = reinterpret_cast<plc::VRec*>(b);
+      ad.tp = reinterpret_cast<double*>(b + 16 * cap);
+      int32_t* lists = reinterpret_cast<int32_t*>(b + 24 * cap);
+      ad.fb0 = lists;
+      ad.fb1 = lists + L;
+      ad.support = lists + 2 * L;
+      ad.touched = lists + 3 * L;
+      ad.mask = (int32_t)(cap - 1);
+      ad.list_cap = (int32_t)L;
+      plc::ClearJob& J = E.clear_h[njobs++];
+      J.tab = ad.tab;
+      J.tp = ad.tp;
+      J.cap = cap;
+      J.off = clear_total;
+      clear_total += cap;
+      E.qblock[q] = blk;
+      E.qcap[q] = cap;
+    } else {
+      ad.tab = a.vr + (int64_t)q * n;
+      ad.tp = a.p + (int64_t)q * n;
+      ad.fb0 = E.d_fbuf + 2 * (int64_t)q * n;
+      ad.fb1 = E.d_fbuf + (2 * (int64_t)q + 1) * n;
+      ad.support = E.d_support + (int64_t)q * n;
+      ad.touched = E.d_touched + (int64_t)q * n;
+      ad.mask = 0;
+      ad.list_cap = (int32_t)n;
+    }
     E.queue.pop_front();
-    plc::Admit& ad = E.adm_h[nadm++];
+    nadm++;
     ad.slot = q;
     ad.seed = qq.seed;
     ad.rule = (int32_t)qq.rule;
@@ -853,31 +1175,172 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     ad.pad = 0;
     E.state[q] = HS_RUN;
     E.qid[q] = id;
+    E.fresh[q] = 1;
+    E.hold[q] = 0;
+  }
+  // 1b. compact layout: grow every table that this round could fill past
+  // half (new keys this round <= the frontier's edge count); a query whose
+  // table cannot grow now sits the round out
+  int nfail = 0, ngrow = 0;
+  long long total_old = 0;
+  std::vector<void*> old_blocks;
+  if (E.compact) {
+    int nhold = 0;
+    for (int q = 0; q < E.B; q++) {
+      if (E.state[q] != HS_RUN || E.fresh[q]) continue;
+      const plc::Slot& S = E.slots_h[q];
+      if (S.status != plc::SL_PUSH) continue;
+      const int64_t need = std::min<int64_t>(n, (int64_t)S.touched_cnt + S.edge_next[S.par]);
+      if (2 * need <= E.qcap[q]) {
+        if (E.hold[q]) {
+          E.holds_h[nhold++] = q;
+          E.hold[q] = 0;
+        }
+        continue;
+      }
+      const int64_t cap = table_cap_for(g, need);
+      const size_t bytes = table_block_bytes(cap);
+      void* blk = ctx->arena.free_bytes() >= bytes + result_headroom(ctx) / 2
+                      ? ctx->arena.alloc(bytes) : nullptr;
+      if (!blk) {
+        if (!E.hold[q]) {
+          E.holds_h[nhold++] = q | (1 << 16);
+          E.hold[q] = 1;
+        }
+        continue;
+      }
+      char* b = static_cast<char*>(blk);
+      const int64_t L = cap / 2;
+      plc::Grow& G = E.grow_h[ngrow++];
+      G.slot = q;
+      G.old_mask = (int32_t)(E.qcap[q] - 1);
+      G.new_mask = (int32_t)(cap - 1);
+      G.list_cap = (int32_t)L;
+      G.rec_off = total_old;
+      G.tab = reinterpret_cast<plc::VRec*>(b);
+      G.tp = reinterpret_cast<double*>(b + 16 * cap);
+      int32_t* lists = reinterpret_cast<int32_t*>(b + 24 * cap);
+      G.fb0 = lists;
+      G.fb1 = lists + L;
+      G.support = lists + 2 * L;
+      G.touched = lists + 3 * L;
+      plc::ClearJob& J = E.clear_h[njobs++];
+      J.tab = G.tab;
+      J.tp = G.tp;
+      J.cap = cap;
+      J.off = clear_total;
+      clear_total += cap;
+      total_old += E.qcap[q];
+      old_blocks.push_back(E.qblock[q]);
+      E.qblock[q] = blk;
+      E.qcap[q] = cap;
+      E.hold[q] = 0;  // k_c_move_lists clears the device flag
+    }
+    if (nhold > 0) {
+      HIPCHK(ctx, hipMemcpyAsync(E.holds_d, E.holds_h, 4 * (size_t)nhold, hipMemcpyHostToDevice,
+                                 s));
+      HIPCHK(ctx, plc::launch_slot_hold(s, a, E.holds_d, nhold));
+    }
+    // Every running query held and none left to sweep or admitted: nothing
+    // would ever free memory, so the held query that needs the most fails.
+    bool progress = false, held = false;
+    for (int q = 0; q < E.B; q++) {
+      if (E.state[q] == HS_PUSHED || (E.state[q] == HS_RUN && !E.hold[q])) progress = true;
+      held |= E.state[q] == HS_RUN && E.hold[q];
+    }
+    if (!held && !progress && nadm == 0 && !E.queue.empty()) {
+      bool busy = false;
+      for (int q = 0; q < E.B; q++) busy |= E.state[q] != HS_FREE;
+      if (!busy) {
+        // nothing runs and the first queued query's table does not fit
+        const uint64_t id = E.queue.front().first;
+        E.queue.pop_front();
+        Result res;
+        res.info.status = PLC_E_NOMEM;
+        ctx->results[id] = res;
+        ctx->inflight.erase(id);
+        if (done_ids && nfail < done_cap) done_ids[nfail] = id;
+        nfail++;
+      }
+    }
+    if (held && !progress) {
+      int worst = -1;
+      int64_t wneed = -1;
+      for (int q = 0; q < E.B; q++) {
+        if (E.state[q] != HS_RUN || !E.hold[q]) continue;
+        const plc::Slot& S = E.slots_h[q];
+        const int64_t need = (int64_t)S.touched_cnt + S.edge_next[S.par];
+        if (need > wneed) { wneed = need; worst = q; }
+      }
+      const plc::Slot& S = E.slots_h[worst];
+      Result res;
+      res.info.status = PLC_E_NOMEM;
+      res.info.rounds = S.rounds;
+      res.info.pushes = S.pushes;
+      res.info.edges = S.edges;
+      const uint64_t id = E.qid[worst];
+      ctx->results[id] = res;
+      ctx->inflight.erase(id);
+      if (done_ids && nfail < done_cap) done_ids[nfail] = id;
+      nfail++;
+      ctx->arena.release(E.qblock[worst]);  // the device slot stays held until re-admitted
+      E.qblock[worst] = nullptr;
+      E.qcap[worst] = 0;
+      E.state[worst] = HS_FREE;
+      E.qid[worst] = 0;
+    }
+  }
+  // 1c. clear new tables, admit, move grown tables (in this order)
+  const int gw = shape(g->batch_sweep, ctx->grid_sweep);
+  if (njobs > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(E.clear_d, E.clear_h, sizeof(plc::ClearJob) * njobs,
+                               hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, plc::launch_table_clear(s, E.clear_d, njobs, clear_total, gw));
   }
   if (nadm > 0) {
     HIPCHK(ctx, hipMemcpyAsync(E.adm_d, E.adm_h, sizeof(plc::Admit) * nadm,
                                hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, plc::launch_batch_admit(s, a, E.adm_d, nadm));
+    HIPCHK(ctx, plc::launch_batch_admit(s, a, E.adm_d, nadm, E.compact));
+  }
+  if (ngrow > 0) {
+    HIPCHK(ctx, hipMemcpyAsync(E.grow_d, E.grow_h, sizeof(plc::Grow) * ngrow,
+                               hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, plc::launch_table_grow(s, a, E.grow_d, ngrow, total_old, gw));
+    // stream order: later users of these blocks run after the rehash
+    for (void* b : old_blocks) ctx->arena.release(b);
   }
   // 2. one round for every running query
   bool any_run = false;
   for (int q = 0; q < E.B; q++) any_run |= E.state[q] == HS_RUN;
+  const EventPair* scatter_ev = nullptr;
   if (any_run) {
-    HIPCHK(ctx, plc::launch_batch_plan_self(s, a, shape(g->batch_self, ctx->grid_self)));
-    if (ctx->timing) {
-      if (ctx->ev_scatter.empty()) ctx->ev_scatter.emplace_back();
-      HIPCHK(ctx, ev_pair(ctx->ev_scatter[0]));
-      HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].a, s));
+    Captured* rg = ctx->use_graphs ? batch_round_graph(ctx, g) : nullptr;
+    if (rg) {
+      HIPCHK(ctx, hipGraphLaunch(rg->exec, s));
+      if (ctx->timing) scatter_ev = &rg->ev_scatter[0];
+    } else {
+      HIPCHK(ctx, plc::launch_batch_plan_self(s, a, shape(g->batch_self, ctx->grid_self),
+                                              E.compact));
+      if (ctx->timing) {
+        if (ctx->ev_scatter.empty()) ctx->ev_scatter.emplace_back();
+        HIPCHK(ctx, ev_pair(ctx->ev_scatter[0]));
+        HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].a, s));
+        scatter_ev = &ctx->ev_scatter[0];
+      }
+      HIPCHK(ctx, plc::launch_batch_scatter(s, a, shape(g->batch_scatter, ctx->grid_scatter),
+                                            E.compact));
+      if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].b, s));
+      HIPCHK(ctx, plc::launch_batch_round_end(s, a));
     }
-    HIPCHK(ctx, plc::launch_batch_scatter(s, a, shape(g->batch_scatter, ctx->grid_scatter)));
-    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].b, s));
-    HIPCHK(ctx, plc::launch_batch_round_end(s, a));
   }
   // 3. sweep the queries whose frontier emptied in an earlier step
   int nseg = 0;
   long long total = 0, touch_total = 0, vol_bound = 0;
   E.sweeping.clear();
-  const bool hold = defer_sweep && any_run && E.queue.empty();
+  // (a held query makes no progress, so it never delays the sweeps that free memory)
+  bool any_active = false;
+  for (int q = 0; q < E.B; q++) any_active |= E.state[q] == HS_RUN && !E.hold[q];
+  const bool hold = defer_sweep && any_active && E.queue.empty();
   for (int q = 0; q < E.B && !hold; q++) {
     if (E.state[q] != HS_PUSHED) continue;
     const plc::Slot& S = E.slots_h[q];
@@ -892,8 +1355,10 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     sg.slot = q;
     sg.n_elem = (int32_t)N;
     sg.elem_off = total;
+    // finish entries: the touched list (dense) or every table record (compact)
+    const long long F = E.compact ? (long long)E.qcap[q] : T;
     sg.touch_off = touch_total;
-    sg.n_touch = (int32_t)T;
+    sg.n_touch = (int32_t)F;
     sg.pad = 0;
     if (res.block) {
       char* b = static_cast<char*>(res.block);
@@ -909,7 +1374,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     E.sweeping.push_back(res);
     E.state[q] = HS_SWEEP;
     total += N;
-    touch_total += T;
+    touch_total += F;
     vol_bound += S.edges;
     nseg++;
   }
@@ -925,7 +1390,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       HIPCHK(ctx, ev_pair(ctx->ev_sweep));
       HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
     }
-    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, total, shape(g->batch_sweep, ctx->grid_sweep)));
+    HIPCHK(ctx, plc::launch_batch_sweep(s, a, nseg, total, shape(g->batch_sweep, ctx->grid_sweep),
+                                        E.compact));
     if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
   }
   // 4. read back and wait
@@ -938,8 +1404,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   }
   if (ctx->timing) {
     float ms = 0;
-    if (any_run) {
-      HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_scatter[0].a, ctx->ev_scatter[0].b));
+    if (scatter_ev) {
+      HIPCHK(ctx, hipEventElapsedTime(&ms, scatter_ev->a, scatter_ev->b));
       ctx->t_scatter.ms += ms;
       ctx->t_scatter.launches++;
       ctx->t_scatter.units += E.ctl_h->e_total;
@@ -976,18 +1442,24 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     const uint64_t id = E.qid[q];
     ctx->results[id] = res;
     ctx->inflight.erase(id);
-    if (done_ids && i < done_cap) done_ids[i] = id;
+    if (done_ids && nfail + i < done_cap) done_ids[nfail + i] = id;
     E.state[q] = HS_FREE;
     E.qid[q] = 0;
+    if (E.qblock[q]) {
+      ctx->arena.release(E.qblock[q]);
+      E.qblock[q] = nullptr;
+      E.qcap[q] = 0;
+    }
   }
   E.sweeping.clear();
+  std::fill(E.fresh.begin(), E.fresh.end(), 0);
   int running = 0;
   for (int q = 0; q < E.B; q++) {
     if (E.state[q] == HS_RUN && E.slots_h[q].status == plc::SL_PUSHED) E.state[q] = HS_PUSHED;
     running += E.state[q] != HS_FREE;
   }
   if (in_flight) *in_flight = running + (int32_t)E.queue.size();
-  if (n_done) *n_done = nseg;
+  if (n_done) *n_done = nfail + nseg;
   return PLC_OK;
 }
 
@@ -1005,6 +1477,38 @@ extern "C" plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done) {
   if (ctx->results.count(id)) { *done = 1; return PLC_OK; }
   if (ctx->inflight.count(id)) { *done = 0; return PLC_OK; }
   return PLC_E_NOTFOUND;
+}
+
+extern "C" plc_status plc_wait(plc_ctx* ctx, uint64_t id, int64_t timeout_us) {
+  if (!ctx) return PLC_E_INVALID;
+  const double t0 = now_ms();
+  for (;;) {
+    if (ctx->results.count(id)) return PLC_OK;
+    auto it = ctx->inflight.find(id);
+    if (it == ctx->inflight.end()) return PLC_E_NOTFOUND;
+    if (ctx->broken) return PLC_E_HIP;
+    if (timeout_us >= 0 && (now_ms() - t0) * 1e3 >= (double)timeout_us) return PLC_E_NOTREADY;
+    plc_graph* g = it->second;
+    if (!ctx->graphs.count(g) || !g->batch) return PLC_E_NOTFOUND;
+    (void)hipSetDevice(ctx->device);
+    plc_status st = batch_step(ctx, g, nullptr, nullptr, 0, nullptr, false);
+    if (st != PLC_OK) return st;
+  }
+}
+
+extern "C" size_t plc_query_bytes_estimate(const plc_graph* g, const plc_query* q) {
+  if (!g || !q || !query_ok(g, *q)) return 0;
+  const double ap = q->rule == PLC_RULE_OPT ? 2.0 * q->alpha / (1.0 + q->alpha) : q->alpha;
+  const double w = 1.0 / (ap * q->eps);  // bound on the pushed volume outside the seed
+  const double nn = (double)g->n;
+  const double sup = std::min(nn, 1.0 + std::floor(w));
+  const double tch = std::min(nn, 1.0 + (double)g->deg[q->seed] + std::floor(w));
+  // result block: support ids + p, nonzero ids + values of r, each part 256-B aligned
+  const double res = 12.0 * sup + 12.0 * tch + 4 * 256.0;
+  const size_t state = g->ctx && g->ctx->opt.batch_state == PLC_STATE_COMPACT
+                           ? table_block_bytes(table_cap_for(g, (int64_t)tch))
+                           : batch_slot_bytes(g);
+  return state + (size_t)res;
 }
 
 extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_query* q,
@@ -1039,12 +1543,6 @@ extern "C" plc_status plc_run_batched(plc_ctx* ctx, plc_graph* g, const plc_quer
 
 // ---------------------------------------------------------------- autotuner
 
-#include <chrono>
-
-static double now_ms() {
-  return std::chrono::duration<double, std::milli>(
-             std::chrono::steady_clock::now().time_since_epoch()).count();
-}
 
 // Run the sample once under the graph's current shapes; wall time in ms.
 static plc_status tune_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count,

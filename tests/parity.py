@@ -153,3 +153,21 @@ def check_same(g, a, b) -> None:
     if not (0 < k < len(blk) and blk[k] == blk[k - 1]):
         for key in ("kstar", "cut", "vol", "phi"):
             assert a.info[key] == b.info[key], key
+
+
+def check_properties(g, res, eps):
+    """Invariants of one result that need no oracle run."""
+    info = res.info
+    assert info["status"] == 0
+    assert info["support"] == len(res.sweep_ids) == len(res.sweep_p)
+    assert np.all(res.sweep_p > 0)
+    assert abs(res.sweep_p.sum() + res.r_vals.sum() - 1.0) < 1e-12, "mass"
+    assert np.all(res.r_vals < eps * g.deg[res.r_ids]), "termination"
+    key = res.sweep_p / g.deg[res.sweep_ids]
+    assert np.all(key[1:] <= key[:-1] * (1 + 1e-10)), "sweep order"
+    cl = res.cluster
+    inset = np.zeros(g.n, bool)
+    inset[cl] = True
+    assert info["vol"] == int(g.deg[cl].sum())
+    assert info["cut"] == int(np.count_nonzero(~inset[cluster_arcs(g, cl)]))
+    assert info["phi"] == info["cut"] / min(info["vol"], g.arcs - info["vol"])

@@ -142,3 +142,46 @@ def test_autotune_keeps_results(setup, plc):
     for i, qid in enumerate(ids):
         check_query(g, ctx.result(qid, release=True), int(seeds[i]), float(alpha[i]),
                     float(eps[i]), int(rules[i]))
+
+
+def test_wait_and_bytes_estimate(setup, plc):
+    """plc_wait drives the engine until one query is done; the byte estimate
+    bounds each query's slot state plus result block."""
+    g, ctx, hg = setup
+    seeds, alpha, eps, rules = mixed_queries(g, 12, seed=55)
+    ids = ctx.submit(hg, seeds, alpha, eps, rules)
+    assert not ctx.wait(ids[11], 0)          # nothing stepped yet: times out at once
+    assert ctx.wait(ids[11])
+    assert ctx.poll(ids[11])
+    slot = 40 * g.n
+    for i, qid in enumerate(ids):
+        assert ctx.wait(qid, 60_000_000)
+        res = ctx.result(qid, release=True)
+        check_query(g, res, int(seeds[i]), float(alpha[i]), float(eps[i]), int(rules[i]))
+        est = ctx.query_bytes_estimate(hg, int(seeds[i]), float(alpha[i]), float(eps[i]),
+                                       int(rules[i]))
+        assert est >= slot + 12 * (res.info["support"] + res.info["r_nnz"])
+    assert ctx.query_bytes_estimate(hg, -1, 0.01, 1e-4) == 0
+    with pytest.raises(plc.PlcError):
+        ctx.wait(ids[0])                       # released: unknown id
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batched_launch_modes(plc, graphs):
+    """The batched round as a replayed graph and as direct launches."""
+    g = synth.rmat(12, 8, seed=12)
+    with plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                     + plc.batch_arena_bytes(g.n, g.arcs, 16), graphs=graphs) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        assert c.batch_reserve(hg, 16) == 16
+        seeds, alpha, eps, rules = mixed_queries(g, 40, seed=77)
+        say("case batched launch mode graphs=%s" % graphs)
+        c.timing(True)
+        ids, infos = c.run_batched(hg, seeds, alpha, eps, rules)
+        tm = c.timing_get()
+        c.timing(False)
+        assert tm["scatter"]["launches"] > 0 and tm["scatter"]["ms"] > 0
+        assert tm["scatter"]["units"] == sum(i["edges"] for i in infos)
+        for i, qid in enumerate(ids):
+            check_query(g, c.result(qid, release=True), int(seeds[i]), float(alpha[i]),
+                        float(eps[i]), int(rules[i]))

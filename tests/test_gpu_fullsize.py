@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import check_query, check_same, cluster_arcs
+from parity import check_properties, check_query, check_same
 
 pytestmark = pytest.mark.gpu
 
@@ -36,24 +36,6 @@ def plc():
 @pytest.fixture(scope="module")
 def g22():
     return synth.rmat(22, 16, seed=1)
-
-
-def check_properties(g, res, eps):
-    """Invariants of one result that need no oracle run."""
-    info = res.info
-    assert info["status"] == 0
-    assert info["support"] == len(res.sweep_ids) == len(res.sweep_p)
-    assert np.all(res.sweep_p > 0)
-    assert abs(res.sweep_p.sum() + res.r_vals.sum() - 1.0) < 1e-12, "mass"
-    assert np.all(res.r_vals < eps * g.deg[res.r_ids]), "termination"
-    key = res.sweep_p / g.deg[res.sweep_ids]
-    assert np.all(key[1:] <= key[:-1] * (1 + 1e-10)), "sweep order"
-    cl = res.cluster
-    inset = np.zeros(g.n, bool)
-    inset[cl] = True
-    assert info["vol"] == int(g.deg[cl].sum())
-    assert info["cut"] == int(np.count_nonzero(~inset[cluster_arcs(g, cl)]))
-    assert info["phi"] == info["cut"] / min(info["vol"], g.arcs - info["vol"])
 
 
 def test_plain_rmat22_bench_shapes(plc, g22):

@@ -1,0 +1,57 @@
+"""Parity on the large skewed graph: R-MAT 2^26 (ef 16, ~2.1 G arcs, max
+degree ~1 M), seeds including the top-degree hubs, eps log-uniform in
+[1e-8, 1e-6], alpha 0.01, through the compact-table engine (dense slots would
+cost 2.7 GB each at this size).
+
+48 queries (40 uniform seeds + the 8 highest-degree hubs) run in one batch;
+every result is checked for the properties that hold at any size (mass,
+termination, sweep order, the reported cut and volume recounted from the
+cluster), and a sample -- including a hub and the heaviest eps -- against the
+oracle.  The benchmark's 1024-seed run on this graph is `bench.py --only large`.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from parity import check_properties, check_query
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_large_rmat26_sampled():
+    import paper_1604_07515_amd as plc
+    g = synth.rmat(26, 16, seed=1)
+    say("graph 2^26 arcs", g.arcs, "maxdeg", int(g.deg.max()))
+    hubs = np.argsort(-g.deg, kind="stable")[:8]
+    seeds = np.concatenate([synth.uniform_seeds(g, 40, seed=12), hubs])
+    eps = 10.0 ** np.random.default_rng(12).uniform(-8, -6, len(seeds))
+    eps[40] = 1e-6  # the top hub, at the largest eps
+    with plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                     + plc.batch_arena_bytes(g.n, g.arcs, 64, compact=True,
+                                             table_bytes=80 << 30), compact=True) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        assert c.batch_reserve(hg, 64) == 64
+        say("running", len(seeds), "queries")
+        ids, infos = c.run_batched(hg, seeds, 0.01, eps)
+        say("edges pushed", sum(i["edges"] for i in infos),
+            "max support", max(i["support"] for i in infos))
+        # oracle samples: the two largest eps, the top hub, and the heaviest
+        # query (by pushed edges) that the oracle finishes in a few seconds
+        edges = np.array([i["edges"] for i in infos])
+        light = np.flatnonzero(edges[:40] <= 2e8)
+        sample = set(np.argsort(-eps[:40])[:2].tolist()) | {40}
+        if len(light):
+            sample.add(int(light[np.argmax(edges[light])]))
+        for i, qid in enumerate(ids):
+            res = c.result(qid, release=True)
+            check_properties(g, res, float(eps[i]))
+            if i in sample:
+                say("oracle check of query", i, "seed", int(seeds[i]), "eps", float(eps[i]))
+                check_query(g, res, int(seeds[i]), 0.01, float(eps[i]), 0)
