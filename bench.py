@@ -385,6 +385,7 @@ def main():
         out["per_query"] = main_res["per_query"]
         out["roofline"] = main_res["roofline"]
         out["kernels"] = main_res["kernels"]
+        out["launch_shapes"] = main_res["launch_shapes"]
     if bat:
         out["batched"] = {k: v for k, v in bat.items() if k != "queries"}
         if plain:

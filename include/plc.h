@@ -68,10 +68,10 @@ typedef struct plc_graph plc_graph;
  * owns dense arrays over all n vertices (40 bytes per vertex per slot,
  * reserved up front by plc_batch_reserve); the edge scatter indexes them
  * directly.  PLC_STATE_COMPACT: every admitted query owns an open-addressing
- * table (16-byte records, p beside them, at most half full) plus its vertex
- * lists, 32 bytes per table record, taken from the arena at admission,
- * sized for the seed's first round and grown between rounds, so memory
- * follows the vertices a query touches.  Queued queries are admitted while
+ * table (16-byte records, p beside them) plus its vertex lists, 36 bytes per
+ * table record, taken from the arena at admission, sized for the seed's
+ * first round and grown between rounds (at most half full before a round,
+ * at most 3/4 after it), so memory follows the vertices a query touches.  Queued queries are admitted while
  * a slot is free and the arena can hold their first table; a query whose
  * table cannot grow waits while others run, and fails with PLC_E_NOMEM only
  * when no other query can make progress.  Results are the same in both

@@ -65,12 +65,28 @@ __device__ __forceinline__ uint32_t vhash(uint32_t x) {
   return x;
 }
 
+// The part of a slot's state the edge scatter needs (staged in LDS per tile).
+struct TabView {
+  VRec* tab;
+  double* tp;
+  int32_t mask;
+};
+
 // Dense: record v of the slot's n records; always present.
 struct DenseState {
   static constexpr bool kCompact = false;
+  __device__ static VRec* insert_v(const TabView& t, int32_t v) { return t.tab + v; }
+  __device__ static int32_t probe_start(const TabView&, int32_t, uint32_t*) { return 0; }
+  __device__ static VRec* probe_finish(const TabView& t, int32_t v, uint32_t, int32_t) {
+    return t.tab + v;
+  }
+  __device__ static int2 deg_hot_v(const BatchArgs&, const TabView& t, int32_t v) {
+    return *reinterpret_cast<const int2*>(&t.tab[v].deg);
+  }
   __device__ static VRec* find(const Slot& S, int32_t v) { return S.tab + v; }
   __device__ static VRec* insert(const Slot& S, int32_t v) { return S.tab + v; }
   __device__ static int32_t rank_of(const Slot& S, int32_t v) { return S.tab[v].rank; }
+  __device__ static int32_t rank_at(const VRec* tab, int32_t, int32_t v) { return tab[v].rank; }
   __device__ static double* pp(const Slot& S, int32_t v, const VRec*) { return S.tp + v; }
   __device__ static int2 deg_hot(const BatchArgs&, const Slot& S, int32_t v) {
     return *reinterpret_cast<const int2*>(&S.tab[v].deg);
@@ -96,24 +112,52 @@ struct CompactState {
   }
   // record of v, claimed with a compare-and-swap when v is new; concurrent
   // inserts of v agree on one record.  nullptr only if the table is full.
-  __device__ static VRec* insert(const Slot& S, int32_t v) {
-    const uint32_t m = (uint32_t)S.mask;
+  __device__ static VRec* insert_v(const TabView& t, int32_t v) {
+    const uint32_t m = (uint32_t)t.mask;
     uint32_t h = vhash((uint32_t)v) & m;
     for (uint32_t i = 0; i <= m; i++) {
-      int32_t* kp = &S.tab[h].deg;
+      int32_t* kp = &t.tab[h].deg;
       const int32_t k = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (k == v) return S.tab + h;
+      if (k == v) return t.tab + h;
       if (k == kEmptyKey) {
         const int32_t old = atomicCAS(kp, kEmptyKey, v);
-        if (old == kEmptyKey || old == v) return S.tab + h;
+        if (old == kEmptyKey || old == v) return t.tab + h;
       }
       h = (h + 1) & m;
     }
     return nullptr;
   }
-  __device__ static int32_t rank_of(const Slot& S, int32_t v) {
-    const VRec* r = find(S, v);
-    return r ? r->rank : 0;
+  __device__ static VRec* insert(const Slot& S, int32_t v) {
+    return insert_v(TabView{S.tab, S.tp, S.mask}, v);
+  }
+  // insert_v split in two so that a thread's first key loads overlap:
+  // probe_start loads the key at v's home position, probe_finish resolves it.
+  __device__ static int32_t probe_start(const TabView& t, int32_t v, uint32_t* h) {
+    *h = vhash((uint32_t)v) & (uint32_t)t.mask;
+    return __hip_atomic_load(&t.tab[*h].deg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ static VRec* probe_finish(const TabView& t, int32_t v, uint32_t h, int32_t k) {
+    if (k == v) return t.tab + h;
+    if (k == kEmptyKey) {
+      const int32_t old = atomicCAS(&t.tab[h].deg, kEmptyKey, v);
+      if (old == kEmptyKey || old == v) return t.tab + h;
+    }
+    return insert_v(t, v);  // collision: probe on from the home position
+  }
+  __device__ static int2 deg_hot_v(const BatchArgs& a, const TabView&, int32_t v) {
+    return a.gdh[v];
+  }
+  __device__ static int32_t rank_of(const Slot& S, int32_t v) { return rank_at(S.tab, S.mask, v); }
+  __device__ static int32_t rank_at(const VRec* tab, int32_t mask, int32_t v) {
+    const uint32_t m = (uint32_t)mask;
+    uint32_t h = vhash((uint32_t)v) & m;
+    for (uint32_t i = 0; i <= m; i++) {
+      const VRec* r = tab + h;
+      if (r->deg == v) return r->rank;
+      if (r->deg == kEmptyKey) return 0;
+      h = (h + 1) & m;
+    }
+    return 0;
   }
   __device__ static double* pp(const Slot& S, int32_t, const VRec* rec) {
     return S.tp + (rec - S.tab);
@@ -448,12 +492,15 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   __shared__ int32_t s_slot[kEdgeTile + 1];
   __shared__ int s_cfn[kSlotRange], s_ctv[kSlotRange], s_bfn[kSlotRange], s_btv[kSlotRange];
   __shared__ unsigned long long s_efn[kSlotRange];
+  __shared__ TabView s_view[kSlotRange];
+  __shared__ double s_eps[kSlotRange];
   __shared__ double s_hacc[kHot];
-  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
   int hs = -1;  // slot whose hot sums s_hacc holds
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = xcd_block(blockIdx.x, gridDim.x) * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
+  if (tb >= te) return;  // no tiles for this workgroup
+  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
   __syncthreads();
 
   for (int tile = tb; tile < te; tile++) {
@@ -471,6 +518,15 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       b_flush_hot<St>(a, hs, s_hacc, &c->fault);
       hs = tile_hs;
     }
+    // the tile's entries belong to slots qlo..tile_hs (ascending)
+    const int qlo = a.eslot[i0];
+    const int range = tile_hs - qlo + 1;
+    const int rr = range < kSlotRange ? range : kSlotRange;
+    for (int j = threadIdx.x; j < rr; j += kBlock) {
+      const Slot& S = a.slots[qlo + j];
+      s_view[j] = TabView{S.tab, S.tp, S.mask};
+      s_eps[j] = S.eps;
+    }
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
       s_start[j] = (int32_t)(a.estart[i0 + j] - e0);
       s_row[j] = a.rowp[i0 + j];
@@ -483,8 +539,6 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       s_efn[j] = 0ull;
     }
     __syncthreads();
-    const int qlo = s_slot[0];
-    const int range = s_slot[cnt - 1] - qlo + 1;
     int32_t w[kEdgesPerThread], q[kEdgesPerThread];
     double cf[kEdgesPerThread];
 #pragma unroll
@@ -508,26 +562,48 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       dr[k] = make_int2(0, 0);
-      if (w[k] >= 0) dr[k] = St::deg_hot(a, a.slots[q[k]], w[k]);
+      if (w[k] >= 0) {
+        const int j = q[k] - qlo;
+        const Slot& S = a.slots[q[k]];
+        const TabView v = j < kSlotRange ? s_view[j] : TabView{S.tab, S.tp, S.mask};
+        dr[k] = St::deg_hot_v(a, v, w[k]);
+      }
+    }
+    // hot destinations of the current slot: combined in LDS; the others:
+    // first probe of every edge, then resolution, then the atomics
+    TabView tv[kEdgesPerThread];
+    uint32_t hp[kEdgesPerThread];
+    int32_t k0[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      if (w[k] < 0) continue;
+      const int hj = -dr[k].y - 1;
+      if (q[k] == hs && hj >= 0 && hj < kHot) {
+        atomicAdd(&s_hacc[hj], cf[k]);
+        w[k] = -1;
+        continue;
+      }
+      const int j = q[k] - qlo;
+      const Slot& S = a.slots[q[k]];
+      tv[k] = j < kSlotRange ? s_view[j] : TabView{S.tab, S.tp, S.mask};
+      k0[k] = St::probe_start(tv[k], w[k], &hp[k]);
+    }
+    VRec* rec[kEdgesPerThread];
+#pragma unroll
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      rec[k] = nullptr;
+      if (w[k] < 0) continue;
+      rec[k] = St::probe_finish(tv[k], w[k], hp[k], k0[k]);
+      if (!rec[k]) {
+        c->fault = 1;  // full table: the host sizes tables so that this cannot happen
+        w[k] = -1;
+      }
     }
     double old[kEdgesPerThread];
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       old[k] = 0.0;
-      if (w[k] < 0) continue;
-      const int hj = -dr[k].y - 1;
-      if (q[k] == hs && hj >= 0 && hj < kHot) {
-        atomicAdd(&s_hacc[hj], cf[k]);  // hot destination of the current slot
-        w[k] = -1;
-      } else {
-        VRec* rec = St::insert(a.slots[q[k]], w[k]);
-        if (rec) {
-          old[k] = unsafeAtomicAdd(&rec->r, cf[k]);
-        } else {
-          c->fault = 1;  // full table: the host sizes tables so that this cannot happen
-          w[k] = -1;
-        }
-      }
+      if (w[k] >= 0) old[k] = unsafeAtomicAdd(&rec[k]->r, cf[k]);
     }
     // decisions: rank within (slot, list) from LDS counters, or a direct
     // global reservation when the tile spans more slots than the LDS range
@@ -539,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       if (w[k] < 0) continue;
       const int j = q[k] - qlo;
       if (j < kSlotRange) {
-        const double thr = a.slots[q[k]].eps * (double)dr[k].x;
+        const double thr = s_eps[j] * (double)dr[k].x;
         if (old[k] < thr && old[k] + cf[k] >= thr) {
           rfn[k] = atomicAdd(&s_cfn[j], 1);
           atomicAdd(&s_efn[j], (unsigned long long)dr[k].x);
@@ -550,7 +626,6 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       }
     }
     __syncthreads();
-    const int rr = range < kSlotRange ? range : kSlotRange;
     for (int j = threadIdx.x; j < rr; j += kBlock) {
       Slot& S = a.slots[qlo + j];
       const int nxt = S.par ^ 1;
@@ -601,8 +676,8 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
 
 constexpr int kMaxClearJobs = 2 * kMaxSlots;  // admissions + growths of one step
 
-// Clear every record (key kEmptyKey, r 0, rank 0) and p of each job's block;
-// x runs over the records of all jobs end to end.
+// Clear every record (key kEmptyKey, r 0, rank 0) and p of each job's
+// block; x runs over the records of all jobs end to end.
 __global__ __launch_bounds__(kBlock) void k_c_clear(const ClearJob* jobs, int count,
                                                     long long total) {
   __shared__ long long s_off[kMaxClearJobs];
@@ -639,10 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_c_rehash(BatchArgs a, const Grow* gr
     if (i > G.old_mask) continue;
     const VRec rec = S.tab[i];
     if (rec.deg == kEmptyKey) continue;
-    Slot T;
-    T.tab = G.tab;
-    T.mask = G.new_mask;
-    VRec* dst = CompactState::insert(T, rec.deg);
+    VRec* dst = CompactState::insert_v(TabView{G.tab, G.tp, G.new_mask}, rec.deg);
     if (!dst) {
       a.ctl->fault = 1;
       continue;
@@ -818,7 +890,8 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
   __shared__ int64_t s_row[kEdgeTile + 1];
   __shared__ int32_t s_cnt[kEdgeTile + 1];
   __shared__ int32_t s_own[kEdgeTile + 1];
-  __shared__ int32_t s_slot[kEdgeTile + 1];
+  __shared__ const VRec* s_tab[kEdgeTile + 1];
+  __shared__ int32_t s_mask[kEdgeTile + 1];
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long e0 = (long long)tile * kEdgeTile;
     const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
@@ -836,7 +909,9 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
       s_start[j] = (int32_t)(a.svol[k] - a.sdeg[k] - e0);
       s_row[j] = a.off[e.id];
       s_own[j] = (int32_t)(k - sg.elem_off + 1);
-      s_slot[j] = sg.slot;
+      const Slot& S = a.slots[sg.slot];
+      s_tab[j] = S.tab;
+      s_mask[j] = S.mask;
       s_cnt[j] = 0;
     }
     __syncthreads();
@@ -854,7 +929,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
           if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
         }
         const int32_t w = a.nbr[s_row[lo] + (rel - s_start[lo])];
-        rw[kk] = St::rank_of(a.slots[s_slot[lo]], w);
+        rw[kk] = St::rank_at(s_tab[lo], s_mask[lo], w);
         own[kk] = lo;
       }
     }
@@ -919,11 +994,8 @@ __global__ __launch_bounds__(kBlock) void k_sw_argmin(BatchArgs a) {
   }
 }
 
-// Gather the nonzeros of r of every swept query.  Dense: walk each touched
-// list and reset r (p and rank are reset by k_sw_reset).  Compact: scan each
-// table (x runs over records; the block is returned to the arena afterwards,
-// so nothing is reset).
-template <class St>
+// Dense layout: gather the nonzeros of r of every swept query by walking its
+// touched list, and reset r (p and rank are reset by k_sw_reset).
 __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int nseg = c->sw_nseg;
@@ -947,16 +1019,10 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
       const SweepSeg& sg = a.segs[s];
       const Slot& S = a.slots[sg.slot];
       const long long i = x - s_toff[s];
-      if (St::kCompact) {
-        const VRec rec = S.tab[i];
-        v = rec.deg;
-        rv = v != kEmptyKey ? rec.r : 0.0;
-      } else {
-        v = S.touched[i];
-        VRec* rec = S.tab + v;
-        rv = rec->r;
-        rec->r = 0.0;
-      }
+      v = S.touched[i];
+      VRec* rec = S.tab + v;
+      rv = rec->r;
+      rec->r = 0.0;
       if (rv != 0.0) rk = atomicAdd(&s_cnt[s - slo], 1);  // s - slo < kBlock
     }
     __syncthreads();
@@ -971,6 +1037,53 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
       const long long pos = (long long)s_base[s - slo] + rk;
       if (pos >= a.slots[sg.slot].touched_cnt) c->fault = 1;
       else if (sg.out_rid) { sg.out_rid[pos] = v; sg.out_rval[pos] = rv; }
+    }
+    __syncthreads();
+  }
+}
+
+// Compact layout: gather the nonzeros of r of every swept query by scanning
+// its table (the block returns to the arena afterwards, so nothing is
+// reset).  Tables are powers of two of at least kScanBlock records, so every
+// kScanBlock-record chunk of the concatenated tables lies in one table.
+__global__ __launch_bounds__(kBlock) void k_sw_gather(BatchArgs a) {
+  BatchCtl* c = a.ctl;
+  const int nseg = c->sw_nseg;
+  const long long nchunk = c->sw_touch_total / kScanBlock;
+  __shared__ long long s_toff[kMaxSlots];
+  __shared__ long long sh[kBlock / 64 + 1];
+  __shared__ long long s_base;
+  __shared__ int s_seg;
+  for (int j = threadIdx.x; j < nseg; j += kBlock) s_toff[j] = a.segs[j].touch_off;
+  __syncthreads();
+  for (long long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const long long x0 = ch * kScanBlock;
+    if (threadIdx.x == 0) s_seg = seg_of(s_toff, nseg, x0);
+    __syncthreads();
+    const SweepSeg& sg = a.segs[s_seg];
+    Slot& S = a.slots[sg.slot];
+    const long long i0 = x0 - s_toff[s_seg];
+    int32_t vk[kScanItems];
+    double rk[kScanItems];
+    long long cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const VRec rec = S.tab[i0 + k * kBlock + threadIdx.x];
+      vk[k] = rec.deg;
+      rk[k] = rec.deg != kEmptyKey ? rec.r : 0.0;
+      cnt += rk[k] != 0.0;
+    }
+    long long tot;
+    long long pos = block_excl_scan<kBlock>(cnt, &tot, sh);
+    if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&S.rnnz, (int)tot) : 0;
+    __syncthreads();
+    pos += s_base;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      if (rk[k] == 0.0) continue;
+      if (pos >= S.touched_cnt) c->fault = 1;
+      else if (sg.out_rid) { sg.out_rid[pos] = vk[k]; sg.out_rval[pos] = rk[k]; }
+      pos++;
     }
     __syncthreads();
   }
@@ -1061,8 +1174,12 @@ static hipError_t sweep_kernels(hipStream_t s, const BatchArgs& a, int nseg, int
   hipLaunchKernelGGL(k_sw_count<St>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_scan<true>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_argmin, dim3(nseg), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sw_finish<St>, dim3(grid), dim3(kBlock), 0, s, a);
-  if (!St::kCompact) hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
+  if (St::kCompact) {
+    hipLaunchKernelGGL(k_sw_gather, dim3(grid), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_sw_finish, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 

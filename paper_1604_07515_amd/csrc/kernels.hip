@@ -224,12 +224,17 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   const double eps = c->eps;
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
-  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
-  if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
-  __syncthreads();
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = blockIdx.x * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
+  // a workgroup without tiles (large grids, small rounds) only takes part in
+  // the round's closing count
+  const bool busy = tb < te;
+  if (busy) {
+    for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
+    if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
+    __syncthreads();
+  }
 
   for (int tile = tb; tile < te; tile++) {
     const long long e0 = (long long)tile * kEdgeTile;
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   // flush the hot sums: one atomic per hot destination this workgroup hit,
   // kEdgeTile entries at a time (the size of the LDS append lists)
   __syncthreads();
-  for (int j0 = 0; j0 < kHot; j0 += kEdgeTile) {
+  for (int j0 = 0; busy && j0 < kHot; j0 += kEdgeTile) {
     for (int j = j0 + threadIdx.x; j < j0 + kEdgeTile; j += kBlock) {
       const double sum = s_hacc[j];
       if (sum != 0.0) {

@@ -895,16 +895,25 @@ static size_t batch_fixed_bytes(const plc_graph* g, int B) {
   return b;
 }
 
-// Compact layout: table capacity (a power of 2, at least 256) for `need`
-// keys at load factor 1/2, and the bytes of a query block of that capacity:
-// records (16 B) + p (8 B) + four lists of cap/2 ids (8 B).
-static int64_t table_cap_for(const plc_graph* g, int64_t need) {
-  need = std::min<int64_t>(std::max<int64_t>(need, 1), g->n);
-  int64_t cap = 256;
-  while (cap < 2 * need) cap <<= 1;
+// Compact layout.  A table of capacity cap (a power of 2, at least 1024) is
+// sized so that before a round at most half of it is occupied and the
+// round's worst case (occupancy + one new key per edge of the frontier)
+// stays within 3/4 of it: linear probing then stays short even in the rare
+// round that adds as many new keys as it has edges, and a table never fills.
+// A query block holds the records (16 B), p (8 B) and four lists of
+// 3/4 cap vertex ids (12 B): 36 B per record.
+static int64_t table_cap_for(const plc_graph* g, int64_t occupied, int64_t worst) {
+  occupied = std::min<int64_t>(std::max<int64_t>(occupied, 1), g->n);
+  worst = std::min<int64_t>(std::max<int64_t>(worst, occupied), g->n);
+  int64_t cap = plc::kScanBlock;  // the r gather scans tables in kScanBlock chunks
+  while (cap < 2 * occupied || 4 * worst > 3 * cap) cap <<= 1;
   return cap;
 }
-static size_t table_block_bytes(int64_t cap) { return 32 * (size_t)cap; }
+static bool table_needs_growth(int64_t cap, int64_t occupied, int64_t worst) {
+  return 2 * occupied > cap || 4 * worst > 3 * cap;
+}
+static size_t table_block_bytes(int64_t cap) { return 36 * (size_t)cap; }
+static int64_t table_list_cap(int64_t cap) { return cap / 4 * 3; }
 
 // Arena kept free for result blocks when tables are taken (admission) or
 // grown (half of it).
@@ -1129,13 +1138,13 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     const plc_query qq = E.queue.front().second;
     plc::Admit& ad = E.adm_h[nadm];
     if (E.compact) {
-      const int64_t cap = table_cap_for(g, 1 + (int64_t)g->deg[qq.seed]);
+      const int64_t cap = table_cap_for(g, 1, 1 + (int64_t)g->deg[qq.seed]);
       const size_t bytes = table_block_bytes(cap);
       if (ctx->arena.free_bytes() < bytes + result_headroom(ctx)) break;
       void* blk = ctx->arena.alloc(bytes);
       if (!blk) break;
       char* b = static_cast<char*>(blk);
-      const int64_t L = cap / 2;
+      const int64_t L = table_list_cap(cap);
       ad.tab = reinterpret_cast<plc::VRec*>(b);
       ad.tp = reinterpret_cast<double*>(b + 16 * cap);
       int32_t* lists = reinterpret_cast<int32_t*>(b + 24 * cap);
@@ -1190,15 +1199,16 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       if (E.state[q] != HS_RUN || E.fresh[q]) continue;
       const plc::Slot& S = E.slots_h[q];
       if (S.status != plc::SL_PUSH) continue;
-      const int64_t need = std::min<int64_t>(n, (int64_t)S.touched_cnt + S.edge_next[S.par]);
-      if (2 * need <= E.qcap[q]) {
+      const int64_t occ = S.touched_cnt;
+      const int64_t worst = std::min<int64_t>(n, occ + S.edge_next[S.par]);
+      if (!table_needs_growth(E.qcap[q], occ, worst)) {
         if (E.hold[q]) {
           E.holds_h[nhold++] = q;
           E.hold[q] = 0;
         }
         continue;
       }
-      const int64_t cap = table_cap_for(g, need);
+      const int64_t cap = std::max<int64_t>(table_cap_for(g, occ, worst), 2 * E.qcap[q]);
       const size_t bytes = table_block_bytes(cap);
       void* blk = ctx->arena.free_bytes() >= bytes + result_headroom(ctx) / 2
                       ? ctx->arena.alloc(bytes) : nullptr;
@@ -1210,7 +1220,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
         continue;
       }
       char* b = static_cast<char*>(blk);
-      const int64_t L = cap / 2;
+      const int64_t L = table_list_cap(cap);
       plc::Grow& G = E.grow_h[ngrow++];
       G.slot = q;
       G.old_mask = (int32_t)(E.qcap[q] - 1);
@@ -1506,7 +1516,7 @@ extern "C" size_t plc_query_bytes_estimate(const plc_graph* g, const plc_query* 
   // result block: support ids + p, nonzero ids + values of r, each part 256-B aligned
   const double res = 12.0 * sup + 12.0 * tch + 4 * 256.0;
   const size_t state = g->ctx && g->ctx->opt.batch_state == PLC_STATE_COMPACT
-                           ? table_block_bytes(table_cap_for(g, (int64_t)tch))
+                           ? table_block_bytes(table_cap_for(g, (int64_t)tch, (int64_t)tch))
                            : batch_slot_bytes(g);
   return state + (size_t)res;
 }

@@ -158,7 +158,7 @@ def test_compact_first_table_does_not_fit(plc):
     cannot be admitted and, with nothing else running, fails at once with
     PLC_E_NOMEM."""
     g = synth.rmat(20, 8, seed=5)
-    c, hg = tight_context(plc, g, 4, 3)  # the hub's first table needs 4 MiB
+    c, hg = tight_context(plc, g, 4, 2)  # the hub's first table needs 2.25 MiB
     with c:
         seed = int(np.argmax(g.deg))
         ids, infos = c.run_batched(hg, [seed], 0.01, 1e-4, check=False)
