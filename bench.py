@@ -377,7 +377,8 @@ def main():
         "config": ({"workload": "rmat22_ef16_plain_16seeds", "n": g.n, "arcs": g.arcs,
                     "alpha": 0.01, "eps": 1e-7, "rule": "optimized", "queries_per_step": 16,
                     "path": "plain (one query at a time)"} if plain else
-                   {"workload": bat["workload"], "n": g.n, "arcs": g.arcs}),
+                   {"workload": bat["workload"], "n": g.n, "arcs": g.arcs} if bat else
+                   {"workload": (srv or big or {}).get("workload")}),
     }
     if main_res:
         out["queries_per_s"] = main_res["queries_per_s"]

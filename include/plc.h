@@ -12,8 +12,11 @@
  *    arena) at plc_init and keeps it alive until plc_destroy.  The library
  *    never allocates device memory itself; every graph, query state and
  *    result lives in the arena, so the arena size is the memory budget.
+ *    (It does allocate pinned host staging buffers with hipHostMalloc.)
  *  - Streams: all device work is issued on the hipStream_t given at plc_init
- *    (passed as void*; NULL means the default stream).
+ *    (passed as void*; NULL means the default stream).  In the default
+ *    launch mode the library also owns one non-blocking stream on which it
+ *    only records graphs; nothing executes on it.
  *  - Graphs are undirected and unweighted (Sec. 2, "Graph Notation"): CSR
  *    with row offsets off[0..n] and neighbour ids nbr[0..off[n]), every
  *    undirected edge stored as two arcs, d(v) = off[v+1] - off[v],
@@ -71,11 +74,11 @@ typedef struct plc_graph plc_graph;
  * table (16-byte records, p beside them) plus its vertex lists, 36 bytes per
  * table record, taken from the arena at admission, sized for the seed's
  * first round and grown between rounds (at most half full before a round,
- * at most 3/4 after it), so memory follows the vertices a query touches.  Queued queries are admitted while
- * a slot is free and the arena can hold their first table; a query whose
- * table cannot grow waits while others run, and fails with PLC_E_NOMEM only
- * when no other query can make progress.  Results are the same in both
- * layouts.
+ * at most 3/4 after it), so memory follows the vertices a query touches.
+ * Queued queries are admitted while a slot is free and the arena can hold
+ * their first table; a query whose table cannot grow waits while others
+ * run, and fails with PLC_E_NOMEM only when no other query can make
+ * progress.  Results are the same in both layouts.
  */
 #define PLC_STATE_DENSE 0
 #define PLC_STATE_COMPACT 1
@@ -150,7 +153,12 @@ plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs, const void*
                           int32_t offsets_bits, const int32_t* nbrs, uint32_t flags,
                           plc_graph** out);
 
+/* Wait for outstanding work, drop the graph's batch engine (queued and
+ * running queries are dropped; finished results stay valid) and return its
+ * arena memory.  PLC_E_INVALID if g does not belong to ctx. */
 plc_status plc_graph_free(plc_ctx* ctx, plc_graph* g);
+
+/* Sizes of a loaded graph (host-side bookkeeping, no device work). */
 plc_status plc_graph_info_get(const plc_graph* g, plc_graph_info* out);
 
 /*
@@ -174,7 +182,8 @@ plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count
  * additions differs).
  *
  * plc_batch_reserve: give graph g a batch engine with up to `slots`
- * concurrent queries (1..1024), in the context's state layout
+ * concurrent queries (1..1024; slots <= 0 takes plc_options.batch_slots),
+ * in the context's state layout
  * (plc_options.batch_state).  Dense: each slot holds per-vertex state (about
  * 40 bytes per vertex), so fewer slots are granted when the arena is short
  * (max(64 MiB, 1/16 of the free arena) stays free for result blocks).
@@ -221,12 +230,14 @@ plc_status plc_poll(plc_ctx* ctx, uint64_t id, int32_t* done);
 plc_status plc_wait(plc_ctx* ctx, uint64_t id, int64_t timeout_us);
 
 /*
- * Arena bytes that one query q on graph g occupies on the batch engine: the
- * state of one slot (dense over the graph's vertices: residual record, p,
- * two frontier buffers, support and touched lists; plc_batch_reserve takes
- * it for every slot) plus an upper bound on the query's result block.  The
- * bound comes from the push's work bound (Sec. 3.3): every push except the
- * seed's moves at least alpha' eps d(v) of the unit mass into p, with
+ * Upper bound on the arena bytes that one query q on graph g occupies on the
+ * batch engine, in the context's state layout, plus its result block.
+ * Dense: the state of one slot (residual record, p, two frontier buffers,
+ * support and touched lists over all n vertices; plc_batch_reserve takes it
+ * for every slot).  Compact: the largest table block the query can reach
+ * (36 B per record, capacity the power of two >= 2 x its touched bound).
+ * The bounds come from the push's work bound (Sec. 3.3): every push except
+ * the seed's moves at least alpha' eps d(v) of the unit mass into p, with
  * alpha' = 2 alpha/(1+alpha) for the optimized rule and alpha for the
  * original, so at most 1 + 1/(alpha' eps) vertices are pushed and at most
  * 1 + d(seed) + 1/(alpha' eps) are touched (both also at most n).  Used by a
@@ -273,7 +284,8 @@ plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);
  * one): sweep_ids[support] = the support in sweep order (non-increasing
  * p/d, ties by ascending id), sweep_p[support] = p at those vertices, so the
  * cluster is sweep_ids[0..kstar); r_ids[r_nnz], r_vals[r_nnz] = nonzeros of
- * the final residual in unspecified order.
+ * the final residual in unspecified order.  PLC_E_NOMEM for a query that
+ * failed with PLC_E_NOMEM (it has no vectors).
  */
 plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_ids, double* sweep_p,
                            int32_t* r_ids, double* r_vals);
@@ -285,9 +297,12 @@ plc_status plc_release(plc_ctx* ctx, uint64_t id);
 plc_status plc_arena_free_bytes(plc_ctx* ctx, size_t* total, size_t* largest);
 
 /*
- * Device-time accounting of the plain path, measured with HIP events recorded
- * on the context's stream around kernel launches (off by default).  Only
- * rounds that pushed something are counted for the scatter and self kernels.
+ * Device-time accounting, measured with HIP events on the context's stream
+ * around kernel launches (event-record nodes inside replayed graphs), off by
+ * default.  Plain path: only rounds that pushed something are counted for
+ * the scatter and self kernels.  Batch engine: one scatter launch per step
+ * (all scheduled queries' edges) and one sweep sequence per step that swept;
+ * self is not timed.
  *   scatter: the edgeMap kernel; units = pushed edges, entries = pushes
  *   self:    the vertexMap + frontier-scan kernel; units = pushes
  *   sweep:   the whole sweep-cut sequence; units = support volume vol(S_N),

@@ -152,9 +152,9 @@ struct CompactState {
     const uint32_t m = (uint32_t)mask;
     uint32_t h = vhash((uint32_t)v) & m;
     for (uint32_t i = 0; i <= m; i++) {
-      const VRec* r = tab + h;
-      if (r->deg == v) return r->rank;
-      if (r->deg == kEmptyKey) return 0;
+      const int2 kr = *reinterpret_cast<const int2*>(&tab[h].deg);  // {key, rank}
+      if (kr.x == v) return kr.y;
+      if (kr.x == kEmptyKey) return 0;
       h = (h + 1) & m;
     }
     return 0;
@@ -725,27 +725,41 @@ __global__ __launch_bounds__(kBlock) void k_c_rehash(BatchArgs a, const Grow* gr
   }
 }
 
-// Copy the lists of each growing slot (one workgroup per slot) and point the
-// slot at its new block.
-__global__ __launch_bounds__(kBlock) void k_c_move_lists(BatchArgs a, const Grow* gr, int count) {
-  const int j = blockIdx.x;
-  if (j >= count) return;
-  const Grow& G = gr[j];
-  Slot& S = a.slots[G.slot];
-  const int par = S.par;
-  const int n0 = S.cnt[par], n1 = S.cnt[par ^ 1], ns = S.support_cnt, nt = S.touched_cnt;
-  int32_t* nf0 = par == 0 ? G.fb0 : G.fb1;
-  int32_t* nf1 = par == 0 ? G.fb1 : G.fb0;
-  if (n0 > G.list_cap || n1 > G.list_cap || ns > G.list_cap || nt > G.list_cap) {
-    if (threadIdx.x == 0) a.ctl->fault = 1;
-    return;
-  }
-  for (int i = threadIdx.x; i < n0; i += kBlock) nf0[i] = S.fb[par][i];
-  for (int i = threadIdx.x; i < n1; i += kBlock) nf1[i] = S.fb[par ^ 1][i];
-  for (int i = threadIdx.x; i < ns; i += kBlock) G.support[i] = S.support[i];
-  for (int i = threadIdx.x; i < nt; i += kBlock) G.touched[i] = S.touched[i];
+// Copy the current frontier, support and touched lists of the growing slots
+// to their new blocks; x runs over those entries of all slots end to end.
+__global__ __launch_bounds__(kBlock) void k_c_move_lists(BatchArgs a, const Grow* gr, int count,
+                                                         long long total) {
+  __shared__ long long s_off[kMaxSlots];
+  for (int j = threadIdx.x; j < count; j += kBlock) s_off[j] = gr[j].list_off;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < total;
+       x += (long long)gridDim.x * kBlock) {
+    const int j = seg_of(s_off, count, x);
+    const Grow& G = gr[j];
+    const Slot& S = a.slots[G.slot];  // still the old block
+    long long i = x - s_off[j];
+    if (i < G.n_front) {
+      (G.par == 0 ? G.fb0 : G.fb1)[i] = S.fb[G.par][i];
+      continue;
+    }
+    i -= G.n_front;
+    if (i < G.n_sup) {
+      G.support[i] = S.support[i];
+      continue;
+    }
+    i -= G.n_sup;
+    if (i < G.n_touch) G.touched[i] = S.touched[i];
+  }
+}
+
+// Point each growing slot at its new block (after the rehash and the copy).
+__global__ void k_c_commit(BatchArgs a, const Grow* gr, int count) {
+  for (int j = threadIdx.x; j < count; j += blockDim.x) {
+    const Grow& G = gr[j];
+    Slot& S = a.slots[G.slot];
+    if (S.par != G.par || S.cnt[G.par] != G.n_front || S.cnt[G.par ^ 1] != 0 ||
+        S.support_cnt != G.n_sup || S.touched_cnt != G.n_touch || G.n_touch > G.list_cap)
+      a.ctl->fault = 1;  // the host's copy of the slot was stale
     S.tab = G.tab;
     S.tp = G.tp;
     S.fb[0] = G.fb0;
@@ -1198,10 +1212,11 @@ hipError_t launch_table_clear(hipStream_t s, const ClearJob* jobs, int count, lo
 }
 
 hipError_t launch_table_grow(hipStream_t s, const BatchArgs& a, const Grow* gr, int count,
-                             long long total_old, int grid) {
+                             long long total_old, long long total_list, int grid) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_c_rehash, dim3(grid), dim3(kBlock), 0, s, a, gr, count, total_old);
-  hipLaunchKernelGGL(k_c_move_lists, dim3(count), dim3(kBlock), 0, s, a, gr, count);
+  hipLaunchKernelGGL(k_c_move_lists, dim3(grid), dim3(kBlock), 0, s, a, gr, count, total_list);
+  hipLaunchKernelGGL(k_c_commit, dim3(1), dim3(256), 0, s, a, gr, count);
   return hipGetLastError();
 }
 

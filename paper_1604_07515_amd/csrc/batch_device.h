@@ -149,6 +149,9 @@ struct __align__(16) Grow {
   int32_t slot;
   int32_t old_mask, new_mask, list_cap;
   long long rec_off;        // first record of this table in the flattened rehash index
+  long long list_off;       // first list entry of this slot in the flattened copy index
+  int32_t par;              // current frontier buffer
+  int32_t n_front, n_sup, n_touch;  // list lengths to move (host copy of the slot)
   VRec* tab;
   double* tp;
   int32_t* fb0;
@@ -181,7 +184,7 @@ hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64
 hipError_t launch_table_clear(hipStream_t s, const ClearJob* jobs, int count, long long total,
                               int grid);
 hipError_t launch_table_grow(hipStream_t s, const BatchArgs& a, const Grow* gr, int count,
-                             long long total_old, int grid);
+                             long long total_old, long long total_list, int grid);
 hipError_t launch_slot_hold(hipStream_t s, const BatchArgs& a, const int32_t* holds, int count);
 
 }  // namespace plc

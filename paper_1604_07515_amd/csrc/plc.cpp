@@ -106,6 +106,7 @@ struct BatchEngine {
   SweepHdr* hdr_h = nullptr;         // pinned sweep header
   std::vector<int> state;            // HS_*
   std::vector<uint64_t> qid;
+  std::vector<int> qbucket;          // compact: hint bucket of the slot's query
   std::vector<Result> sweeping;      // result blocks filled by the sweep in flight
   std::deque<std::pair<uint64_t, plc_query>> queue;
   size_t bytes = 0;
@@ -126,7 +127,16 @@ struct BatchEngine {
   int32_t* holds_d = nullptr;
   plc::ClearJob* clear_h = nullptr;  // pinned table clears of one step (2B)
   plc::ClearJob* clear_d = nullptr;
+  // compact layout: running mean of the final touched count of finished
+  // queries, per quarter decade of the work-bound scale 1/(alpha' eps); a
+  // new query's first table is sized for it (fewer growth steps)
+  std::map<int, double> touched_hint;
 };
+
+static int hint_bucket(const plc_query& q) {
+  const double ap = q.rule == PLC_RULE_OPT ? 2.0 * q.alpha / (1.0 + q.alpha) : q.alpha;
+  return (int)std::floor(4.0 * std::log10(1.0 / (ap * q.eps)));
+}
 
 }  // namespace
 
@@ -205,7 +215,7 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
   c->arena.reset(dev_arena, arena_bytes);
   if (opt) c->opt = *opt;
   if (c->opt.max_rounds <= 0) c->opt.max_rounds = 1 << 20;
-  if (c->opt.batch_slots <= 0) c->opt.batch_slots = 256;
+  if (c->opt.batch_slots <= 0 || c->opt.batch_slots > 1024) c->opt.batch_slots = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->num_cu = prop.multiProcessorCount;
@@ -997,6 +1007,7 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   E->state.assign(B, HS_FREE);
   E->qid.assign(B, 0);
   E->qblock.assign(B, nullptr);
+  E->qbucket.assign(B, 0);
   E->qcap.assign(B, 0);
   E->hold.assign(B, 0);
   E->fresh.assign(B, 0);
@@ -1035,6 +1046,7 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
 
 extern "C" plc_status plc_batch_reserve(plc_ctx* ctx, plc_graph* g, int32_t slots,
                                         int32_t* granted) {
+  if (slots <= 0 && ctx) slots = ctx->opt.batch_slots;
   if (!ctx || !g || !ctx->graphs.count(g) || slots < 1 || slots > 1024) return PLC_E_INVALID;
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
@@ -1138,10 +1150,25 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     const plc_query qq = E.queue.front().second;
     plc::Admit& ad = E.adm_h[nadm];
     if (E.compact) {
-      const int64_t cap = table_cap_for(g, 1, 1 + (int64_t)g->deg[qq.seed]);
-      const size_t bytes = table_block_bytes(cap);
-      if (ctx->arena.free_bytes() < bytes + result_headroom(ctx)) break;
-      void* blk = ctx->arena.alloc(bytes);
+      int64_t expect = 1;
+      auto hint = E.touched_hint.find(hint_bucket(qq));
+      if (hint != E.touched_hint.end()) {
+        // never above this query's own touched bound (plc_query_bytes_estimate)
+        const double ap = qq.rule == PLC_RULE_OPT ? 2.0 * qq.alpha / (1.0 + qq.alpha) : qq.alpha;
+        const double bound = 1.0 + g->deg[qq.seed] + std::floor(1.0 / (ap * qq.eps));
+        expect = (int64_t)std::min(hint->second, std::min(bound, (double)n));
+      }
+      // the hinted size if the arena has room for it, else the seed's first
+      // round only (the table then grows like any other)
+      const int64_t first = table_cap_for(g, 1, 1 + (int64_t)g->deg[qq.seed]);
+      int64_t cap = table_cap_for(g, expect, std::max<int64_t>(expect, 1 + g->deg[qq.seed]));
+      void* blk = nullptr;
+      for (;;) {
+        const size_t bytes = table_block_bytes(cap);
+        if (ctx->arena.free_bytes() >= bytes + result_headroom(ctx)) blk = ctx->arena.alloc(bytes);
+        if (blk || cap == first) break;
+        cap = first;
+      }
       if (!blk) break;
       char* b = static_cast<char*>(blk);
       const int64_t L = table_list_cap(cap);
@@ -1162,6 +1189,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       clear_total += cap;
       E.qblock[q] = blk;
       E.qcap[q] = cap;
+      E.qbucket[q] = hint_bucket(qq);
     } else {
       ad.tab = a.vr + (int64_t)q * n;
       ad.tp = a.p + (int64_t)q * n;
@@ -1191,7 +1219,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   // half (new keys this round <= the frontier's edge count); a query whose
   // table cannot grow now sits the round out
   int nfail = 0, ngrow = 0;
-  long long total_old = 0;
+  long long total_old = 0, total_list = 0;
   std::vector<void*> old_blocks;
   if (E.compact) {
     int nhold = 0;
@@ -1227,6 +1255,12 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       G.new_mask = (int32_t)(cap - 1);
       G.list_cap = (int32_t)L;
       G.rec_off = total_old;
+      G.list_off = total_list;
+      G.par = S.par;
+      G.n_front = S.cnt[S.par];
+      G.n_sup = S.support_cnt;
+      G.n_touch = S.touched_cnt;
+      total_list += (long long)G.n_front + G.n_sup + G.n_touch;
       G.tab = reinterpret_cast<plc::VRec*>(b);
       G.tp = reinterpret_cast<double*>(b + 16 * cap);
       int32_t* lists = reinterpret_cast<int32_t*>(b + 24 * cap);
@@ -1315,7 +1349,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   if (ngrow > 0) {
     HIPCHK(ctx, hipMemcpyAsync(E.grow_d, E.grow_h, sizeof(plc::Grow) * ngrow,
                                hipMemcpyHostToDevice, s));
-    HIPCHK(ctx, plc::launch_table_grow(s, a, E.grow_d, ngrow, total_old, gw));
+    HIPCHK(ctx, plc::launch_table_grow(s, a, E.grow_d, ngrow, total_old, total_list, gw));
     // stream order: later users of these blocks run after the rehash
     for (void* b : old_blocks) ctx->arena.release(b);
   }
@@ -1459,6 +1493,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       ctx->arena.release(E.qblock[q]);
       E.qblock[q] = nullptr;
       E.qcap[q] = 0;
+      auto ins = E.touched_hint.emplace(E.qbucket[q], (double)S.touched_cnt);
+      if (!ins.second) ins.first->second = 0.75 * ins.first->second + 0.25 * S.touched_cnt;
     }
   }
   E.sweeping.clear();
