@@ -354,29 +354,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_keys(PlainArgs a) {
   }
 }
 
-// Rank map (rank[v_k] = k, outside = 0) and per-position degree, p and id.
-__global__ __launch_bounds__(kBlock) void k_sweep_rank(PlainArgs a) {
-  Ctl* c = a.ctl;
-  if (c->status != ST_SWEEPING) return;
-  const int N = c->N;
-  const SortElem* el = a.sbuf[c->sort_flip & 1];
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < N; k += gridDim.x * kBlock) {
-    int32_t v = el[k].id;
-    a.vr[v].rank = k + 1;
-    a.sdeg[k] = a.vr[v].deg;
-    a.sp[k] = a.p[v];
-    a.sid[k] = v;
-    a.scnt[k] = 0;
-  }
-}
-
-// Inclusive volume prefix vol(S_k) and the edge-tile map over the support's
-// edges in sweep order (the offsets of the Z array in Theorem 1's proof).
+// Rank map (rank[v_k] = k, outside = 0) with per-position degree, p and id,
+// and the inclusive volume prefix vol(S_k) with the edge-tile map over the
+// support's edges in sweep order (the offsets of the Z array in Theorem 1's
+// proof).
 __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
   const int N = c->N;
   if (N <= 0) return;
+  const SortElem* el = a.sbuf[c->sort_flip & 1];
   __shared__ long long sh[kBlock / 64 + 1];
   __shared__ long long s_excl;
   __shared__ int s_tk[2];
@@ -392,7 +379,16 @@ __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
     long long dsum = 0;
     for (int k = 0; k < kScanItems; k++) {
       int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
-      dk[k] = i < N ? a.sdeg[i] : 0;
+      dk[k] = 0;
+      if (i < N) {
+        const int32_t v = el[i].id;
+        a.vr[v].rank = i + 1;
+        dk[k] = a.vr[v].deg;
+        a.sdeg[i] = dk[k];
+        a.sp[i] = a.p[v];
+        a.sid[i] = v;
+        a.scnt[i] = 0;
+      }
       dsum += dk[k];
     }
     long long agg;
@@ -505,7 +501,7 @@ __device__ void block_argmin(long long* s_bc, long long* s_bd, long long* s_bk) 
 // Inclusive prefix of the boundary deltas gives |boundary(S_k)|; with vol_k
 // the conductance of every prefix follows.  Each block publishes its best
 // prefix (smallest cut/den by exact comparison, first k on ties, den = 0
-// excluded); k_cut_final reduces the candidates.
+// excluded); k_sweep_finish reduces the candidates.
 __global__ __launch_bounds__(kBlock) void k_cut_scan(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
@@ -562,11 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_scan(PlainArgs a) {
 }
 
 // Reduce the per-block candidates of k_cut_scan (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_cut_final(PlainArgs a) {
-  Ctl* c = a.ctl;
-  if (c->status != ST_SWEEPING) return;
-  const int N = c->N;
-  if (N <= 0) return;
+__device__ void cut_final(const PlainArgs& a, Ctl* c, int N) {
   const int nblk = (N + kScanBlock - 1) / kScanBlock;
   __shared__ long long s_bc[kBlock], s_bd[kBlock], s_bk[kBlock];
   long long mc = -1, md = 1, mk = 0;
@@ -587,10 +579,13 @@ __global__ __launch_bounds__(kBlock) void k_cut_final(PlainArgs a) {
   }
 }
 
-// Gather the nonzeros of r over the touched list; mark the sweep finished.
+// Workgroup 0 reduces k_cut_scan's per-block candidates to the best prefix;
+// all gather the nonzeros of r over the touched list; the last workgroup
+// marks the sweep finished.
 __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
+  if (blockIdx.x == 0 && c->N > 0) cut_final(a, c, c->N);
   __shared__ int32_t s_id[kBlock];
   __shared__ double s_val[kBlock];
   __shared__ int s_n, s_base, s_last;
@@ -667,7 +662,7 @@ hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid) {
   return hipGetLastError();
 }
 
-hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid) {
+hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count) {
   hipLaunchKernelGGL(k_sweep_keys, dim3(grid), dim3(kBlock), 0, s, a);
   SortArgs sa;
   sa.buf[0] = a.sbuf[0];
@@ -677,13 +672,11 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid) {
   sa.done = &a.ctl->done[DONE_SORT];
   sa.active = &a.ctl->status;
   sa.active_value = ST_SWEEPING;
-  hipError_t e = launch_sort(s, sa, a.n, grid);
+  hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sweep_rank, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_vol_scan, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_cut_count, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_cut_scan, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_cut_final, dim3(1), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sweep_finish, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

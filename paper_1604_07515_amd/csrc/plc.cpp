@@ -2,13 +2,14 @@
 //
 // A context owns a view of the caller's device arena, the caller's stream and
 // a pinned host mirror of the device control block.  plc_run drives the plain
-// path: per query it queues the seed initialisation, a chunk of rounds whose
-// kernels exit at once after the frontier empties, the whole sweep sequence
-// (which only runs once the push has finished) and a read-back of the control
-// block, then synchronises once; if the frontier was still non-empty it
-// queues another, larger chunk.  Results are copied device-to-device into an
-// exact-size arena block, and the dense per-vertex state is reset through the
-// touched list.
+// path: per query it queues the seed initialisation and a chunk of rounds
+// (kernels of rounds past the end of the push exit at once), reads the
+// control block back, and queues short further chunks until the frontier is
+// empty; then the sweep sequence, recorded for the support size's number of
+// merge passes, and one more read-back.  Results are copied device-to-device
+// into an exact-size arena block, and the dense per-vertex state is reset
+// through the touched list.  The batch engine (plc_batch_reserve and after)
+// runs many queries per launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -152,8 +153,8 @@ struct plc_graph {
   int plain_self = 0, plain_scatter = 0, plain_sweep = 0;
   int batch_self = 0, batch_scatter = 0, batch_sweep = 0;
   BatchEngine* batch = nullptr;
-  std::map<int, Captured> chunk_g;  // plain path: R rounds of (self, scatter), R a power of 2
-  Captured sweep_g;                 // plain path: the sweep sequence
+  std::map<int, Captured> chunk_g;  // plain path: R rounds of (self, scatter), by R
+  std::map<int64_t, Captured> sweep_g;  // plain path: the sweep, by sort bound (power of 2)
 };
 
 struct plc_ctx {
@@ -169,7 +170,7 @@ struct plc_ctx {
   std::set<plc_graph*> graphs;
   int num_cu = 256;
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
-  int chunk_rounds = 16;
+  std::deque<int> round_hist;  // plain path: round counts of the last queries
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
   hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
   bool timing = false;
@@ -242,7 +243,8 @@ static void batch_free(plc_ctx* ctx, plc_graph* g);
 static void graph_captures_free(plc_graph* g) {
   for (auto& kv : g->chunk_g) captured_free(kv.second);
   g->chunk_g.clear();
-  captured_free(g->sweep_g);
+  for (auto& kv : g->sweep_g) captured_free(kv.second);
+  g->sweep_g.clear();
 }
 
 static void free_events(plc_ctx* c) {
@@ -550,10 +552,11 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
   return ok ? &c : nullptr;
 }
 
-// Graph of the plain sweep sequence.
-static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g) {
+// Graph of the plain sweep sequence for supports of at most max_count
+// vertices (a power of 2: it sets the number of merge passes).
+static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count) {
   const int gw = shape(g->plain_sweep, ctx->grid_sweep);
-  Captured& c = g->sweep_g;
+  Captured& c = g->sweep_g[max_count];
   if (c.matches(0, 0, gw, 0, ctx->timing)) return &c;
   captured_free(c);
   c.gs = 0;
@@ -570,7 +573,7 @@ static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g) {
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
     hipError_t r;
     if (c.timed && (r = ev_ext(c.ev_sweep.a, cs)) != hipSuccess) return r;
-    if ((r = plc::launch_sweep(cs, a, gw)) != hipSuccess) return r;
+    if ((r = plc::launch_sweep(cs, a, gw, max_count)) != hipSuccess) return r;
     if (c.timed && (r = ev_ext(c.ev_sweep.b, cs)) != hipSuccess) return r;
     return hipSuccess;
   });
@@ -613,20 +616,22 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   const PlainArgs& a = g->args;
   HIPCHK(ctx, plc::launch_query_init(s, a, q.seed, (int32_t)q.rule, q.alpha, q.eps,
                                      ctx->opt.max_rounds));
+  // Push: chunks of rounds, each followed by a read-back of the control
+  // block.  Rounds queued past the end of the push exit at once but still
+  // cost a dispatch each, so the first chunk is the lower quartile of the
+  // last queries' round counts and later chunks are short.
   int queued = 0;
-  int chunk = std::max(2, ctx->chunk_rounds);
+  int chunk = 16;
+  if (!ctx->round_hist.empty()) {
+    std::vector<int> hs(ctx->round_hist.begin(), ctx->round_hist.end());
+    std::sort(hs.begin(), hs.end());
+    chunk = hs[hs.size() / 4];
+  }
+  chunk = std::max(2, std::min(256, chunk));
   Ctl& h = *ctx->ctl_host;
-  const EventPair* sweep_ev = &ctx->ev_sweep;
   for (;;) {
-    // a chunk of R rounds: a replayed graph (R rounded up to a power of 2) or
-    // direct launches
-    int R = chunk;
-    Captured* cg = nullptr;
-    if (ctx->use_graphs) {
-      R = 2;
-      while (R < chunk) R <<= 1;
-      cg = plain_chunk_graph(ctx, g, R);
-    }
+    const int R = chunk;
+    Captured* cg = ctx->use_graphs ? plain_chunk_graph(ctx, g, R) : nullptr;
     const EventPair* ev_s;
     const EventPair* ev_c;
     if (cg) {
@@ -634,29 +639,14 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       ev_s = cg->ev_self.data();
       ev_c = cg->ev_scatter.data();
     } else {
-      R = chunk;
       HIPCHK(ctx, queue_rounds(ctx, g, R));
       ev_s = ctx->ev_self.data();
       ev_c = ctx->ev_scatter.data();
     }
-    // the sweep (its kernels exit at once while the push is still running)
-    Captured* sg = ctx->use_graphs ? plain_sweep_graph(ctx, g) : nullptr;
-    if (sg) {
-      HIPCHK(ctx, hipGraphLaunch(sg->exec, s));
-      sweep_ev = &sg->ev_sweep;
-    } else {
-      if (ctx->timing) {
-        HIPCHK(ctx, ev_pair(ctx->ev_sweep));
-        HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
-      }
-      HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
-      if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
-      sweep_ev = &ctx->ev_sweep;
-    }
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (ctx->timing) {
-      // every round of an earlier chunk pushed (else the query would have
+      // every round of an earlier chunk pushed (else the push would have
       // ended there), so this chunk's pushing rounds are the first h.round - queued
       const int ran = std::max(0, std::min(R, h.round - queued));
       float ms = 0;
@@ -670,15 +660,39 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       }
     }
     queued += R;
-    if (h.status == plc::ST_SWEPT) break;
-    if (h.status != plc::ST_PUSH) {  // unexpected state: device-side fault
+    if (h.status == plc::ST_LIMIT) break;  // watchdog: sweep the partial p
+    if (h.status != plc::ST_PUSH) {         // unexpected state: device-side fault
       ctx->broken = true;
       return PLC_E_HIP;
     }
-    chunk = std::min(chunk * 2, 256);
+    if (h.cnt[h.round & 1] == 0) break;     // next frontier empty: the push is done
+    chunk = std::max(2, std::min(64, queued / 3));
   }
-  // Next query starts with a chunk that covers this one's rounds.
-  ctx->chunk_rounds = std::min(256, std::max(4, h.round + 2));
+  ctx->round_hist.push_back(h.round);
+  if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
+  // Sweep, recorded for the smallest power-of-2 bound on the support size
+  // (it sets the number of merge passes).
+  int64_t bound = 1024;
+  while (bound < h.support_cnt) bound <<= 1;
+  const EventPair* sweep_ev = &ctx->ev_sweep;
+  Captured* sg = ctx->use_graphs ? plain_sweep_graph(ctx, g, bound) : nullptr;
+  if (sg) {
+    HIPCHK(ctx, hipGraphLaunch(sg->exec, s));
+    sweep_ev = &sg->ev_sweep;
+  } else {
+    if (ctx->timing) {
+      HIPCHK(ctx, ev_pair(ctx->ev_sweep));
+      HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
+    }
+    HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep), bound));
+    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
+  }
+  HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (h.status != plc::ST_SWEPT) {  // unexpected state: device-side fault
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
   if (h.fault) {
     ctx->broken = true;
     return PLC_E_HIP;

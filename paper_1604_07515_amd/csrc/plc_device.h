@@ -121,7 +121,8 @@ hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, in
                              double alpha, double eps, int32_t max_rounds);
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid);
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid);
-hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid);
+// max_count: bound on the support size, sets the number of merge passes
+hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count);
 hipError_t launch_cleanup(hipStream_t s, const PlainArgs& a, int grid);
 
 }  // namespace plc
