@@ -238,11 +238,14 @@ class Context:
         self.close()
 
     def load_graph(self, off: np.ndarray, nbr: np.ndarray, validate: bool = False) -> Graph:
-        off = np.ascontiguousarray(off, dtype=np.int64)
+        """Copy a CSR graph into the arena.  int32 offsets are passed as such
+        (32-bit CSR), anything else as int64."""
+        bits = 32 if np.asarray(off).dtype == np.int32 else 64
+        off = np.ascontiguousarray(off, dtype=np.int32 if bits == 32 else np.int64)
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
         n = len(off) - 1
         h = C.c_void_p()
-        _check(self.lib.plc_graph_load(self.handle, n, len(nbr), _ptr(off), 64, _ptr(nbr),
+        _check(self.lib.plc_graph_load(self.handle, n, len(nbr), _ptr(off), bits, _ptr(nbr),
                                        PLC_GRAPH_VALIDATE if validate else 0, C.byref(h)),
                "plc_graph_load")
         return Graph(self, h, n, len(nbr))

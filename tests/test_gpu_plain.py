@@ -181,3 +181,19 @@ def test_launch_modes_agree_and_time(plc, graphs):
         ids2, infos2 = c.run(hg, seeds, 0.01, 1e-6)
         for qid, s in zip(ids2, seeds):
             check_query(g, c.result(qid, release=True), s, 0.01, 1e-6, OPT)
+
+
+def test_int32_offsets_rmat16_seed0(plc):
+    """R-MAT 2^16 with int32 CSR offsets (the 32-bit load path): seed 0 of the
+    largest component, alpha 0.01, eps 1e-7, against the oracle; the same
+    result as the 64-bit load."""
+    g = synth.rmat(16, 8, seed=1)
+    x = synth.largest_component_min_vertex(g)
+    out = []
+    for off in (g.off.astype(np.int32), g.off.astype(np.int64)):
+        with plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (64 << 20)) as c:
+            hg = c.load_graph(off, g.nbr, validate=True)
+            ids, _ = c.run(hg, [x], 0.01, 1e-7)
+            out.append(c.result(ids[0], release=True))
+    check_query(g, out[0], x, 0.01, 1e-7, OPT)
+    check_same(g, out[0], out[1])
