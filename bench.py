@@ -94,22 +94,36 @@ def roofline(tm, kernel):
 
 
 def timed_steps(ctx, step, steps, warmup):
+    """Warm-up, then the timed steps with no per-kernel events (an event node
+    between dependent kernels costs about as much as a short kernel), then
+    the same steps again with HIP events around every kernel on the
+    library's stream: the kernel durations of the roofline come from that
+    instrumented replay."""
     import torch
     acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
     for i in range(warmup):
         step([], dict(acc))
         log("  warmup step %d done" % i)
     torch.cuda.synchronize()
-    ctx.timing(True)
     lat = []
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step(lat, acc)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    log("  timed steps done")
+    ctx.timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat_i = []
+    for _ in range(steps):
+        step(lat_i, dict(acc))
+    torch.cuda.synchronize()
     tm = ctx.timing_get()
     ctx.timing(False)
+    tm["instrumented_replay"] = {"elapsed_s": time.perf_counter() - t1,
+                                 "p50_ms": pct(lat_i, 50) * 1e3 if lat_i else None}
+    log("  instrumented replay done")
     return elapsed, lat, acc, tm
 
 
@@ -304,6 +318,29 @@ def cpu_baseline(oracle, g, work, budget):
                       "R-MAT 2^22 graph, %.1f s" % (done, ct)}
 
 
+def cpu_multicore_baseline(g, work, budget):
+    """The OpenMP PR-Nibble + sweep (all host threads) on the same queries in
+    the same order, repeated until `budget` seconds."""
+    import cpu_multicore
+    s = cpu_multicore.Solver(g.off, g.nbr)
+    try:
+        c0 = time.perf_counter()
+        done = e_sum = 0
+        while work and time.perf_counter() - c0 <= budget:
+            for sd, al, ep in work:
+                e_sum += s.run(int(sd), float(al), float(ep))["edges"]
+                done += 1
+                if time.perf_counter() - c0 > budget:
+                    break
+        ct = time.perf_counter() - c0
+    finally:
+        s.close()
+    return {"value": e_sum / ct, "unit": "pushed edges/s", "cores": cpu_multicore.threads(),
+            "kind": "openmp", "queries_per_s": done / ct,
+            "sample": "%d queries (same list and order as cpu_baseline), OpenMP push with "
+                      "atomic adds + parallel sweep, %.1f s" % (done, ct)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -316,8 +353,12 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=2048)
     ap.add_argument("--serve-state", choices=["dense", "compact"], default="compact",
                     help="state layout of the serving engine")
+    ap.add_argument("--serve-slots", type=int, default=256,
+                    help="batch slots of the serving engine")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle time for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-mc-budget", type=float, default=10.0,
+                    help="seconds for the multicore (OpenMP) CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a device copy of MIB MiB three times (reference kernel "
                          "for hardware byte counters)")
@@ -357,7 +398,7 @@ def main():
     if bat_c:
         log("batched (compact tables): %.3g edges/s, %.1f queries/s" % (
             bat_c["edges_per_s"], bat_c["queries_per_s"]))
-    srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries,
+    srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries, args.serve_slots,
                          compact=args.serve_state == "compact") if want("serving") else None)
     big = bench_large(plc, synth) if args.only == "large" else None
     if big:
@@ -400,16 +441,17 @@ def main():
         out["large"] = big
     if srv:
         out["serving"] = srv
-    if args.cpu_budget > 0:
+    work = []
+    if plain:
+        work += [(s, 0.01, 1e-7) for s in plain["seeds"]]
+    if bat:
+        q = bat["queries"]
+        work += list(zip(q.seeds, q.alpha, q.eps))
+    if args.cpu_budget > 0 and work:
         import oracle
-        work = []
-        if plain:
-            work += [(s, 0.01, 1e-7) for s in plain["seeds"]]
-        if bat:
-            q = bat["queries"]
-            work += list(zip(q.seeds, q.alpha, q.eps))
-        if work:
-            out["cpu_baseline"] = cpu_baseline(oracle, g, work, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(oracle, g, work, args.cpu_budget)
+    if args.cpu_mc_budget > 0 and work:
+        out["cpu_multicore"] = cpu_multicore_baseline(g, work, args.cpu_mc_budget)
     print(json.dumps(out), flush=True)
 
 
