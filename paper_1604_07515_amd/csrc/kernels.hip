@@ -40,7 +40,7 @@ __global__ void k_graph_init(PlainArgs a) {
     VRec rec;
     rec.r = 0.0;
     rec.deg = (int32_t)(a.off[v + 1] - a.off[v]);
-    rec.rank = a.hotcode[v];
+    rec.rank = 0;
     a.vr[v] = rec;
     a.p[v] = 0.0;
   }
@@ -203,10 +203,11 @@ __device__ __forceinline__ void decide(double old, double c, double thr, int32_t
 }
 
 // edgeMap(G, Frontier, UpdateNgh) with the filter folded in.  Each
-// workgroup takes a contiguous range of edge tiles.  Contributions to hot
-// destinations (the highest-degree vertices, which many frontier edges hit)
-// are summed in LDS and added to r once per workgroup; every other edge is
-// one device-scope FP64 atomic.
+// workgroup takes a contiguous range of edge tiles; every edge is one
+// device-scope FP64 atomic.  (Combining the contributions to the
+// highest-degree destinations in LDS, as the batched scatter does, measured
+// slower here: one query's round spreads over few workgroups, and the
+// per-workgroup clear and flush cost more than the contention they save.)
 __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   Ctl* c = a.ctl;
   int t, nf;
@@ -217,7 +218,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   __shared__ double s_coef[kEdgeTile + 1];
   __shared__ int32_t s_fn[kEdgeTile];
   __shared__ int32_t s_tv[kEdgeTile];
-  __shared__ double s_hacc[kHot];
   __shared__ int s_nfn, s_ntv, s_base, s_last;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->etotal;
@@ -229,9 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   const int te = tb + per < ntiles ? tb + per : ntiles;
   // a workgroup without tiles (large grids, small rounds) only takes part in
   // the round's closing count
-  const bool busy = tb < te;
-  if (busy) {
-    for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
+  if (tb < te) {
     if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
     __syncthreads();
   }
@@ -253,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
     }
     __syncthreads();
     // Four independent edges per thread: all neighbour loads, then all
-    // record loads and atomics, then the decisions, so latencies overlap.
+    // degree loads and atomics, then the decisions, so latencies overlap.
     int32_t w[kEdgesPerThread];
     double cf[kEdgesPerThread];
 #pragma unroll
@@ -271,43 +269,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
         cf[k] = s_coef[lo];
       }
     }
-    int2 dr[kEdgesPerThread];
+    int32_t dw[kEdgesPerThread];
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) {
-      dr[k] = make_int2(0, 0);
-      if (w[k] >= 0) dr[k] = *reinterpret_cast<const int2*>(&a.vr[w[k]].deg);
-    }
+    for (int k = 0; k < kEdgesPerThread; k++) dw[k] = w[k] >= 0 ? a.vr[w[k]].deg : 0;
     double old[kEdgesPerThread];
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) {
-      old[k] = 0.0;
-      if (w[k] < 0) continue;
-      const int hj = -dr[k].y - 1;
-      if (hj >= 0 && hj < kHot) {
-        atomicAdd(&s_hacc[hj], cf[k]);  // hot: combined in LDS
-        w[k] = -1;
-      } else {
-        old[k] = unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]);
-      }
-    }
+    for (int k = 0; k < kEdgesPerThread; k++)
+      old[k] = w[k] >= 0 ? unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]) : 0.0;
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++)
-      if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dr[k].x, w[k], s_fn, &s_nfn, s_tv, &s_ntv);
-    block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
-    block_flush(&c->touched_cnt, a.touched, a.n, s_tv, &s_ntv, &s_base, &c->fault);
-  }
-  // flush the hot sums: one atomic per hot destination this workgroup hit,
-  // kEdgeTile entries at a time (the size of the LDS append lists)
-  __syncthreads();
-  for (int j0 = 0; busy && j0 < kHot; j0 += kEdgeTile) {
-    for (int j = j0 + threadIdx.x; j < j0 + kEdgeTile; j += kBlock) {
-      const double sum = s_hacc[j];
-      if (sum != 0.0) {
-        const int32_t w = a.hot_ids[j];
-        const double old = unsafeAtomicAdd(&a.vr[w].r, sum);
-        decide(old, sum, eps * (double)a.vr[w].deg, w, s_fn, &s_nfn, s_tv, &s_ntv);
-      }
-    }
+      if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dw[k], w[k], s_fn, &s_nfn, s_tv, &s_ntv);
     block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
     block_flush(&c->touched_cnt, a.touched, a.n, s_tv, &s_ntv, &s_base, &c->fault);
   }
@@ -335,6 +306,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_keys(PlainArgs a) {
   Ctl* c = a.ctl;
   if (!sweep_ready(c)) return;
   __shared__ int s_last;
+  if (blockIdx.x == 0 && threadIdx.x < sizeof(SweepOut) / 8) {
+    // this sweep's result destinations, from pinned host memory (system
+    // scope: the host wrote them just before the launch)
+    unsigned long long* src = reinterpret_cast<unsigned long long*>(
+        const_cast<SweepOut*>(a.out_host));
+    reinterpret_cast<unsigned long long*>(&c->out)[threadIdx.x] =
+        __hip_atomic_load(src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
   const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     int32_t v = a.support[i];
@@ -364,6 +343,8 @@ __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
   const int N = c->N;
   if (N <= 0) return;
   const SortElem* el = a.sbuf[c->sort_flip & 1];
+  int32_t* const out_ids = c->out.ids;
+  double* const out_p = c->out.p;
   __shared__ long long sh[kBlock / 64 + 1];
   __shared__ long long s_excl;
   __shared__ int s_tk[2];
@@ -385,8 +366,8 @@ __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
         a.vr[v].rank = i + 1;
         dk[k] = a.vr[v].deg;
         a.sdeg[i] = dk[k];
-        a.sp[i] = a.p[v];
-        a.sid[i] = v;
+        out_p[i] = a.p[v];
+        out_ids[i] = v;
         a.scnt[i] = 0;
       }
       dsum += dk[k];
@@ -426,6 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_count(PlainArgs a) {
   __shared__ int32_t s_start[kEdgeTile + 1];
   __shared__ int64_t s_row[kEdgeTile + 1];
   __shared__ int32_t s_cnt[kEdgeTile + 1];
+  const int32_t* const sid = c->out.ids;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->etotal;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -441,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_count(PlainArgs a) {
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
       int k = i0 + j;
       s_start[j] = (int32_t)(a.svol[k] - a.sdeg[k] - e0);
-      s_row[j] = a.off[a.sid[k]];
+      s_row[j] = a.off[sid[k]];
       s_cnt[j] = 0;
     }
     __syncthreads();
@@ -580,8 +562,10 @@ __device__ void cut_final(const PlainArgs& a, Ctl* c, int N) {
 }
 
 // Workgroup 0 reduces k_cut_scan's per-block candidates to the best prefix;
-// all gather the nonzeros of r over the touched list; the last workgroup
-// marks the sweep finished.
+// all gather the nonzeros of r over the touched list into the result and
+// reset the query's dense state (r of every touched vertex; p and the sweep
+// rank of every support vertex: both were read by
+// earlier sweep kernels only); the last workgroup marks the sweep finished.
 __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
@@ -589,7 +573,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   __shared__ int32_t s_id[kBlock];
   __shared__ double s_val[kBlock];
   __shared__ int s_n, s_base, s_last;
+  int32_t* const out_rid = c->out.rid;
+  double* const out_rval = c->out.rval;
+  const long long rcap = c->out.rcap;
   const int T = (int64_t)c->touched_cnt > a.n ? (int)a.n : c->touched_cnt;
+  const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   for (int base = blockIdx.x * kBlock; base < T; base += gridDim.x * kBlock) {
@@ -597,6 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
     if (i < T) {
       int32_t v = a.touched[i];
       double rv = a.vr[v].r;
+      a.vr[v].r = 0.0;
       if (rv != 0.0) {
         int j = atomicAdd(&s_n, 1);
         s_id[j] = v;
@@ -609,29 +598,19 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
     __syncthreads();
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
       long long slot = (long long)s_base + j;
-      if (slot < a.n) { a.rid[slot] = s_id[j]; a.rval[slot] = s_val[j]; } else c->fault = 1;
+      if (slot < rcap) { out_rid[slot] = s_id[j]; out_rval[slot] = s_val[j]; } else c->fault = 1;
     }
     __syncthreads();
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
   }
-  if (last_block(&c->done[DONE_FINISH], &s_last, false)) {
-    if (threadIdx.x == 0) c->status = ST_SWEPT;
-  }
-}
-
-// Reset the dense per-vertex state: r of every touched vertex; p and the
-// sweep rank (back to the hot code) of every support vertex.
-__global__ __launch_bounds__(kBlock) void k_cleanup(PlainArgs a) {
-  Ctl* c = a.ctl;
-  const int T = (int64_t)c->touched_cnt > a.n ? (int)a.n : c->touched_cnt;
-  const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < T; i += gridDim.x * kBlock)
-    a.vr[a.touched[i]].r = 0.0;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
     int32_t v = a.support[i];
-    a.vr[v].rank = a.hotcode[v];
+    a.vr[v].rank = 0;
     a.p[v] = 0.0;
+  }
+  if (last_block(&c->done[DONE_FINISH], &s_last, false)) {
+    if (threadIdx.x == 0) c->status = ST_SWEPT;
   }
 }
 
@@ -678,11 +657,6 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max
   hipLaunchKernelGGL(k_cut_count, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_cut_scan, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sweep_finish, dim3(grid), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_cleanup(hipStream_t s, const PlainArgs& a, int grid) {
-  hipLaunchKernelGGL(k_cleanup, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

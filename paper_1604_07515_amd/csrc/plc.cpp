@@ -163,6 +163,7 @@ struct plc_ctx {
   Arena arena;
   plc_options opt{};
   Ctl* ctl_host = nullptr;  // pinned
+  plc::SweepOut* out_host = nullptr;  // pinned, coherent: the plain sweep's result destinations
   std::map<uint64_t, Result> results;
   std::map<uint64_t, plc_graph*> inflight;  // submitted to a batch engine, not finished
   uint64_t next_id = 1;
@@ -229,6 +230,13 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
     return PLC_E_HIP;
   }
   std::memset(c->ctl_host, 0, sizeof(Ctl));
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->out_host), sizeof(plc::SweepOut),
+                    hipHostMallocCoherent) != hipSuccess) {
+    (void)hipHostFree(c->ctl_host);
+    delete c;
+    return PLC_E_HIP;
+  }
+  std::memset(c->out_host, 0, sizeof(plc::SweepOut));
   // The caller's stream may be the null stream, which cannot be captured, so
   // graphs are recorded on a stream of our own and replayed on the caller's.
   if (c->opt.launch_mode == PLC_LAUNCH_GRAPH &&
@@ -268,6 +276,7 @@ extern "C" plc_status plc_destroy(plc_ctx* ctx) {
   free_events(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
+  if (ctx->out_host) (void)hipHostFree(ctx->out_host);
   delete ctx;
   return PLC_OK;
 }
@@ -392,6 +401,7 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   int32_t* hotcode = static_cast<int32_t*>(take(4 * N));
   a.hot_ids = hot_ids;
   a.hotcode = hotcode;
+  a.out_host = ctx->out_host;
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -670,6 +680,30 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   ctx->round_hist.push_back(h.round);
   if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
+  // The result block, sized from the push's counters (support N; the
+  // nonzeros of r are among the T touched vertices), before the sweep: the
+  // sweep writes into it directly.  Without room, it writes into the
+  // library's own buffers and the query reports PLC_E_NOMEM.
+  const size_t N = (size_t)std::min<int64_t>(std::max(h.support_cnt, 0), g->n);
+  const size_t T = (size_t)std::min<int64_t>(std::max(h.touched_cnt, 0), g->n);
+  const size_t off_p = (4 * N + 255) & ~(size_t)255;
+  const size_t off_rid = off_p + ((8 * N + 255) & ~(size_t)255);
+  const size_t off_rval = off_rid + ((4 * T + 255) & ~(size_t)255);
+  Result res;
+  res.block = ctx->arena.alloc(off_rval + 8 * T);
+  plc::SweepOut& o = *ctx->out_host;
+  if (res.block) {
+    char* b = static_cast<char*>(res.block);
+    res.ids = reinterpret_cast<int32_t*>(b);
+    res.p = reinterpret_cast<double*>(b + off_p);
+    res.rid = reinterpret_cast<int32_t*>(b + off_rid);
+    res.rval = reinterpret_cast<double*>(b + off_rval);
+    o.ids = res.ids; o.p = res.p; o.rid = res.rid; o.rval = res.rval;
+    o.rcap = (long long)T;
+  } else {
+    o.ids = a.sid; o.p = a.sp; o.rid = a.rid; o.rval = a.rval;
+    o.rcap = (long long)g->n;
+  }
   // Sweep, recorded for the smallest power-of-2 bound on the support size
   // (it sets the number of merge passes).
   int64_t bound = 1024;
@@ -689,11 +723,8 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
-  if (h.status != plc::ST_SWEPT) {  // unexpected state: device-side fault
-    ctx->broken = true;
-    return PLC_E_HIP;
-  }
-  if (h.fault) {
+  if (h.status != plc::ST_SWEPT || h.fault) {  // unexpected state: device-side fault
+    ctx->arena.release(res.block);
     ctx->broken = true;
     return PLC_E_HIP;
   }
@@ -710,7 +741,6 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     ctx->t_sweep.entries += h.N;
   }
 
-  Result res;
   plc_result_info& info = res.info;
   info.status = h.limited ? PLC_E_LIMIT : PLC_OK;
   info.rounds = h.round;
@@ -722,33 +752,11 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   info.vol = h.best_vol;
   info.phi = h.phi;
   info.r_nnz = h.rnnz;
-  size_t N = (size_t)h.N, R = (size_t)h.rnnz;
-  size_t off_p = (4 * N + 255) & ~(size_t)255;
-  size_t off_rid = off_p + ((8 * N + 255) & ~(size_t)255);
-  size_t off_rval = off_rid + ((4 * R + 255) & ~(size_t)255);
-  size_t total = off_rval + 8 * R;
   plc_status st = PLC_OK;
-  res.block = ctx->arena.alloc(total);
   if (!res.block) {
     info.status = PLC_E_NOMEM;
     st = PLC_E_NOMEM;
-  } else {
-    char* b = static_cast<char*>(res.block);
-    res.ids = reinterpret_cast<int32_t*>(b);
-    res.p = reinterpret_cast<double*>(b + off_p);
-    res.rid = reinterpret_cast<int32_t*>(b + off_rid);
-    res.rval = reinterpret_cast<double*>(b + off_rval);
-    const int32_t* sorted = a.sid;
-    if (N) {
-      HIPCHK(ctx, hipMemcpyAsync(res.ids, sorted, 4 * N, hipMemcpyDeviceToDevice, s));
-      HIPCHK(ctx, hipMemcpyAsync(res.p, a.sp, 8 * N, hipMemcpyDeviceToDevice, s));
-    }
-    if (R) {
-      HIPCHK(ctx, hipMemcpyAsync(res.rid, a.rid, 4 * R, hipMemcpyDeviceToDevice, s));
-      HIPCHK(ctx, hipMemcpyAsync(res.rval, a.rval, 8 * R, hipMemcpyDeviceToDevice, s));
-    }
   }
-  HIPCHK(ctx, plc::launch_cleanup(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
   uint64_t id = ctx->next_id++;
   ctx->results[id] = res;
   if (id_out) *id_out = id;

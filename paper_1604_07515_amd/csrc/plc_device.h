@@ -10,8 +10,9 @@
 //   p     double[n]      approximate PageRank vector
 // plus work buffers sized by n (frontier ping-pong, per-entry coefficient,
 // row offset and edge start, support and touched lists, sort buffers).
-// Dense per-vertex state is reset after every query through the touched list,
-// so a query's cost stays proportional to the vertices it touched.
+// Dense per-vertex state is reset at the end of every query's sweep through
+// the touched and support lists, so a query's cost stays proportional to the
+// vertices it touched.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,8 +25,7 @@ namespace plc {
 struct __align__(16) VRec {
   double r;      // residual; +0.0 = never touched by this query, -0.0 = pushed (optimized rule)
   int32_t deg;   // d(v), constant for the graph
-  int32_t rank;  // sweep rank 1..N while a sweep runs; otherwise the hot code:
-                 // -(j+1) for hot vertex j (see hot_ids), 0 for the others
+  int32_t rank;  // sweep rank 1..N while a sweep runs, 0 otherwise
 };
 
 // Query status in the control block.  ST_PUSH: rounds in progress (done when
@@ -38,6 +38,19 @@ enum : int32_t { SCAN_FRONTIER = 0, SCAN_VOL = 1, SCAN_CUT = 2, NUM_SCANS = 3 };
 
 // Last-workgroup counters.
 enum : int32_t { DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, NUM_DONE = 8 };
+
+// Where one query's sweep writes its results: the host's result block, or
+// the library's own buffers when none could be allocated.  The host fills a
+// pinned, coherent copy before the sweep; k_sweep_keys moves it into the
+// control block, where the later sweep kernels read it.
+struct SweepOut {
+  int32_t* ids;     // [N] support in sweep order
+  double* p;        // [N] p in sweep order
+  int32_t* rid;     // [rcap] ids of the nonzeros of r
+  double* rval;     // [rcap] their values
+  long long rcap;   // capacity of rid and rval
+  long long pad;
+};
 
 // Device control block of one plain-path query.  Written by kernels only,
 // except at query start (k_query_init) and read back by the host.
@@ -68,6 +81,7 @@ struct __align__(64) Ctl {
   long long best_cut, best_vol, best_den;
   long long kstar;
   double phi;
+  SweepOut out;           // result destinations of the running sweep
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
@@ -96,14 +110,16 @@ struct PlainArgs {
   int32_t* sdeg;       // degree in sweep order
   int64_t* svol;       // inclusive volume prefix in sweep order
   int32_t* scnt;       // # earlier-ranked neighbours per sweep position
-  double* sp;          // p in sweep order
-  int32_t* sid;        // vertex ids in sweep order
-  int32_t* rid;        // r nonzero ids
-  double* rval;        // r nonzero values
+  double* sp;          // p in sweep order      } fallback result destinations
+  int32_t* sid;        // vertex ids in sweep order } when no result block
+  int32_t* rid;        // r nonzero ids           } could be allocated
+  double* rval;        // r nonzero values        }
+  const SweepOut* out_host;  // pinned host memory: this sweep's result destinations
   long long* bbest;    // per-block argmin candidates (cut, den, k)
-  // hot destinations: the highest-degree vertices, combined in LDS by the scatter
+  // hot destinations of the batched scatter (the highest-degree vertices,
+  // combined in LDS there), kept with the graph
   const int32_t* hot_ids;  // [kHot] vertex of hot index j
-  const int32_t* hotcode;  // [n] -(j+1) or 0, restored into VRec::rank after a sweep
+  const int32_t* hotcode;  // [n] -(j+1) for hot vertex j, else 0
 };
 
 // Launch configuration.
@@ -112,7 +128,7 @@ constexpr int kScanItems = 4;                    // items per thread in scan-typ
 constexpr int kScanBlock = kBlock * kScanItems;  // items per scan block
 constexpr int kEdgeTile = 1024;                  // edges per scatter / cut tile
 constexpr int kEdgesPerThread = kEdgeTile / kBlock;
-constexpr int kHot = 2048;                       // hot destinations combined in LDS
+constexpr int kHot = 2048;                       // hot destinations (batched scatter)
 static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 
 // Host-side launchers (return hipError_t of the launch).
@@ -121,8 +137,10 @@ hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, in
                              double alpha, double eps, int32_t max_rounds);
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid);
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid);
-// max_count: bound on the support size, sets the number of merge passes
+// max_count: bound on the support size, sets the number of merge passes.
+// The sweep writes its results to the destinations in *a.out_host and, in
+// its last kernel, resets the query's dense state (r over the touched list,
+// p and the rank over the support list).
 hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count);
-hipError_t launch_cleanup(hipStream_t s, const PlainArgs& a, int grid);
 
 }  // namespace plc

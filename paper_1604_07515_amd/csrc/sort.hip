@@ -4,12 +4,15 @@
 // queries, key is the bit-inverted IEEE pattern of the positive ratio p/d
 // (ascending key = non-increasing ratio) and id breaks ties (ascending id).
 //
-// Merge sort: one launch sorts 1024-element tiles in LDS (bitonic network),
-// then each merge pass doubles the sorted run length.  A pass produces
+// Merge sort: one launch sorts 4096-element tiles in LDS (each thread sorts
+// 16 elements in registers with a bitonic network, then eight rounds of
+// merge-path merges in LDS double the sorted runs up to the tile), then
+// each merge pass doubles the sorted run length.  A pass produces
 // 1024-element output tiles; the two split points of a tile on the merge
 // path are found by a cooperative 128-ary search (a few rounds of parallel
-// global loads instead of a serial binary search), the inputs are staged in
-// LDS and every thread merges four outputs.  The element count lives in
+// global loads, each resolved with wave ballots instead of a serial binary
+// search), the inputs are staged in LDS and every thread merges four
+// outputs.  The element count lives in
 // device memory; passes whose run length already covers it return at once,
 // so the whole sequence is queued without a host round trip.
 #include <hip/hip_runtime.h>
@@ -21,8 +24,15 @@
 namespace plc {
 
 constexpr int kSortBlk = 256;
-constexpr int kTileS = 1024;        // elements per tile
+constexpr int kTileS = 1024;        // elements per merge-pass output tile
 constexpr int kPerThr = kTileS / kSortBlk;
+constexpr int kBT = 16;             // elements per thread in the block sort
+constexpr int kTileB = kSortBlk * kBT;  // elements per block-sort tile
+
+// LDS index of element i of a block-sort tile: one spare slot after every
+// 16 elements, so the 16-element rows of consecutive threads start on
+// different banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 
 __device__ __forceinline__ bool elem_lt(const SortElem& a, const SortElem& b) {
   if (a.seg != b.seg) return a.seg < b.seg;
@@ -34,42 +44,89 @@ __device__ __forceinline__ bool sort_enabled(const SortArgs& s) {
   return s.active == nullptr || *s.active == s.active_value;
 }
 
+// Compare-exchange: afterwards a <= b when up, a >= b otherwise.
+__device__ __forceinline__ void cswap(SortElem& a, SortElem& b, bool up) {
+  if (elem_lt(b, a) == up) {
+    SortElem t = a;
+    a = b;
+    b = t;
+  }
+}
+
 __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
   if (!sort_enabled(s)) return;
   const int N = *s.count;
   const int flip = *s.flip;
   SortElem* buf = s.buf[flip];
-  __shared__ SortElem sh[kTileS];
-  const int ntiles = (N + kTileS - 1) / kTileS;
+  __shared__ SortElem sh[kTileB + kTileB / 16];
+  const int ntiles = (N + kTileB - 1) / kTileB;
+  const int t = threadIdx.x;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int base = tile * kTileS;
-    for (int k = 0; k < kPerThr; k++) {
-      int i = k * kSortBlk + threadIdx.x;
+    const int base = tile * kTileB;
+    // coalesced load (element k*256 + t), padded past N with the largest element
+#pragma unroll
+    for (int k = 0; k < kBT; k++) {
+      const int i = k * kSortBlk + t;
       SortElem e;
       if (base + i < N) {
         e = buf[base + i];
       } else {
         e.seg = INT32_MAX; e.key = ~0ull; e.id = INT32_MAX;
       }
-      sh[i] = e;
+      sh[lds_pad(i)] = e;
     }
     __syncthreads();
-    for (int k = 2; k <= kTileS; k <<= 1) {
+    // elements 16t .. 16t+15, sorted in registers (bitonic network)
+    SortElem x[kBT];
+#pragma unroll
+    for (int k = 0; k < kBT; k++) x[k] = sh[lds_pad(t * kBT + k)];
+#pragma unroll
+    for (int k = 2; k <= kBT; k <<= 1) {
+#pragma unroll
       for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int q = 0; q < kTileS / 2 / kSortBlk; q++) {
-          int p = q * kSortBlk + threadIdx.x;           // pair index 0..511
-          int i = 2 * j * (p / j) + (p % j);
-          int l = i + j;
-          bool up = (i & k) == 0;
-          SortElem a = sh[i], b = sh[l];
-          if (elem_lt(b, a) == up) { sh[i] = b; sh[l] = a; }
+#pragma unroll
+        for (int i = 0; i < kBT; i++) {
+          const int l = i ^ j;
+          if (l > i) cswap(x[i], x[l], (i & k) == 0);
         }
-        __syncthreads();
       }
     }
-    for (int k = 0; k < kPerThr; k++) {
-      int i = k * kSortBlk + threadIdx.x;
-      if (base + i < N) buf[base + i] = sh[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kBT; k++) sh[lds_pad(t * kBT + k)] = x[k];
+    __syncthreads();
+    // merge runs of L into runs of 2L; thread t produces outputs
+    // [16t, 16t + 16) of the tile, i.e. diagonal d of its pair of runs
+    for (int L = kBT; L < kTileB; L <<= 1) {
+      const int o = t * kBT;
+      const int pb = (o / (2 * L)) * (2 * L);
+      const int d = o - pb;
+      const int A = pb, B = pb + L;  // run starts (tile positions)
+      int lo = d - L > 0 ? d - L : 0;
+      int hi = d < L ? d : L;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (elem_lt(sh[lds_pad(B + d - 1 - mid)], sh[lds_pad(A + mid)])) hi = mid; else lo = mid + 1;
+      }
+      int ia = lo, ib = d - lo;
+#pragma unroll
+      for (int k = 0; k < kBT; k++) {
+        bool takeA;
+        if (ib >= L) takeA = true;
+        else if (ia >= L) takeA = false;
+        else takeA = !elem_lt(sh[lds_pad(B + ib)], sh[lds_pad(A + ia)]);
+        if (takeA) { x[k] = sh[lds_pad(A + ia)]; ia++; }
+        else { x[k] = sh[lds_pad(B + ib)]; ib++; }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kBT; k++) sh[lds_pad(o + k)] = x[k];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < kBT; k++) {
+      const int i = k * kSortBlk + t;
+      if (base + i < N) buf[base + i] = sh[lds_pad(i)];
     }
     __syncthreads();
   }
@@ -79,47 +136,45 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
 // first d0 (threads 0..127) and d1 (threads 128..255) outputs of merge(A, B),
 // i.e. the first i with A[i] > B[d-1-i] (or the upper end of the range).
 // Found by a cooperative 128-ary search: each round every thread tests one
-// position, which shrinks the range by a factor of 128.  Every thread of the
-// workgroup must call it; the result for both halves lands in s_res[0..3]
-// as (lo, hi) pairs with lo == hi.
+// position, which shrinks the range by a factor of 128; the tests are
+// monotone in the position, so the first true one is the count of false
+// ones, summed from the two wave ballots of the half.  Every thread of the
+// workgroup must call it; the splits of both halves land in s_res[0..1].
 __device__ void merge_splits(const SortElem* A, int la, const SortElem* B, int lb, int d0, int d1,
-                             int* s_flag /* 256 */, int* s_res /* 4 */) {
+                             int* s_cnt /* 4 */, int* s_done /* 2 */, int* s_res /* 2 */) {
   const int half = threadIdx.x >> 7;
   const int t = threadIdx.x & 127;
-  if (t == 0) {
-    int d = half ? d1 : d0;
-    s_res[half * 2] = d - lb > 0 ? d - lb : 0;
-    s_res[half * 2 + 1] = d < la ? d : la;
-  }
-  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int d = half ? d1 : d0;
+  int lo = d - lb > 0 ? d - lb : 0;
+  int hi = d < la ? d : la;
   for (int it = 0; it < 8; it++) {  // 128^5 > 2^31: the loop always converges before 8
-    int lo = s_res[half * 2], hi = s_res[half * 2 + 1];
-    bool done = s_res[0] == s_res[1] && s_res[2] == s_res[3];
+    if (t == 0) s_done[half] = lo == hi;
     __syncthreads();
+    const bool done = s_done[0] && s_done[1];
     if (done) break;
-    const int d = half ? d1 : d0;
-    int span = hi - lo;
+    const int span = hi - lo;
     int step = (span + 127) / 128;
     if (step < 1) step = 1;
-    int pos = lo + t * step;
-    int test = 1;
-    if (span > 0 && pos < hi) test = elem_lt(B[d - 1 - pos], A[pos]) ? 1 : 0;
-    s_flag[threadIdx.x] = test;
+    const int pos = lo + t * step;
+    bool test = true;
+    if (span > 0 && pos < hi) test = elem_lt(B[d - 1 - pos], A[pos]);
+    const unsigned long long falses = __ballot(!test);
+    if ((threadIdx.x & 63) == 0) s_cnt[wave] = __popcll(falses);
     __syncthreads();
-    if (t == 0 && span > 0) {
-      int first = 128;
-      for (int u = 0; u < 128; u++)
-        if (s_flag[half * 128 + u]) { first = u; break; }
+    if (span > 0) {
       // positions lo + u*step are false for u < first and true at u = first
+      const int first = s_cnt[2 * half] + s_cnt[2 * half + 1];
       int nlo = first == 0 ? lo : lo + (first - 1) * step + 1;
-      int cap = lo + first * step;
-      int nhi = cap < hi ? cap : hi;
+      const int cap = lo + first * step;
+      const int nhi = cap < hi ? cap : hi;
       if (nlo > nhi) nlo = nhi;
-      s_res[half * 2] = nlo;
-      s_res[half * 2 + 1] = nhi;
+      lo = nlo;
+      hi = nhi;
     }
-    __syncthreads();
   }
+  if (t == 0) s_res[half] = lo;
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
@@ -130,8 +185,7 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
   const SortElem* src = s.buf[flip];
   SortElem* dst = s.buf[flip ^ 1];
   __shared__ SortElem sm[kTileS];
-  __shared__ int s_flag[256];
-  __shared__ int s_res[4];
+  __shared__ int s_cnt[4], s_done[2], s_res[2];
   __shared__ int s_last;
   const int ntiles = (N + kTileS - 1) / kTileS;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -143,8 +197,8 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
     const SortElem* A = src + pb;
     const SortElem* B = src + pb + la;
     const int d0 = (int)(o0 - pb), d1 = (int)(o1 - pb);
-    merge_splits(A, la, B, lb, d0, d1, s_flag, s_res);
-    const int a0 = s_res[0], a1 = s_res[2];
+    merge_splits(A, la, B, lb, d0, d1, s_cnt, s_done, s_res);
+    const int a0 = s_res[0], a1 = s_res[1];
     const int b0 = d0 - a0, b1 = d1 - a1;
     const int na = a1 - a0, nb = b1 - b0;
     for (int j = threadIdx.x; j < na + nb; j += kSortBlk)
@@ -177,7 +231,7 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
 
 hipError_t launch_sort(hipStream_t st, const SortArgs& s, int64_t max_count, int grid) {
   hipLaunchKernelGGL(k_block_sort, dim3(grid), dim3(kSortBlk), 0, st, s);
-  for (int64_t L = kTileS; L < max_count; L <<= 1)
+  for (int64_t L = kTileB; L < max_count; L <<= 1)
     hipLaunchKernelGGL(k_merge_pass, dim3(grid), dim3(kSortBlk), 0, st, s, (int)L);
   return hipGetLastError();
 }
