@@ -406,7 +406,10 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
     }
     long long agg;
     (void)block_excl_scan<kBlock>(dsum, &agg, sh);
-    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    if (threadIdx.x < 64) {
+      const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
+      if (threadIdx.x == 0) s_excl = ex0;
+    }
     __syncthreads();
     long long run = s_excl;
     for (int k = 0; k < kScanItems; k++) {
@@ -863,7 +866,10 @@ __global__ __launch_bounds__(kBlock) void k_sw_scan(BatchArgs a) {
     }
     long long agg;
     (void)block_excl_scan<kBlock>(xsum, &agg, sh);
-    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    if (threadIdx.x < 64) {
+      const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
+      if (threadIdx.x == 0) s_excl = ex0;
+    }
     __syncthreads();
     long long run = s_excl;
     for (int k = 0; k < kScanItems; k++) {

@@ -87,31 +87,49 @@ __device__ __forceinline__ void scan_clear_prev(ScanSite* site, unsigned long lo
     other[j] = 0ull;
 }
 
-// Decoupled look-back for block b (call from thread 0).  Predecessors claimed
-// their tickets earlier, so they are running or done; the spin is bounded and
-// raises *fault if it ever runs out.  Returns the exclusive prefix.
+// Decoupled look-back for block b, by the 64 lanes of wave 0 together (call
+// from threads 0..63; every lane gets the result).  Each round reads the
+// descriptors of the 64 nearest unresolved predecessors at once and sums
+// back to the nearest inclusive prefix; lanes past block 0 count as an
+// inclusive prefix of 0.  A round that meets a predecessor without a
+// descriptor before any inclusive one waits and reads again.  Predecessors
+// claimed their tickets earlier, so they are running or done; the wait is
+// bounded and raises *fault if it ever runs out.  Returns the exclusive
+// prefix.
 __device__ long long scan_lookback(unsigned long long* desc, int b, long long agg, int* fault) {
+  const int lane = PLC_LANE;
   if (b == 0) {
-    atomic_st64(&desc[0], desc_pack(2, agg));
+    if (lane == 0) atomic_st64(&desc[0], desc_pack(2, agg));
     return 0;
   }
-  atomic_st64(&desc[b], desc_pack(1, agg));
+  if (lane == 0) atomic_st64(&desc[b], desc_pack(1, agg));
   long long excl = 0;
-  int j = b - 1;
+  int j = b - 1;  // nearest predecessor not yet summed
   long spins = 0;
-  while (j >= 0) {
-    unsigned long long w = atomic_ld64(&desc[j]);
-    unsigned flag = (unsigned)(w >> 62);
-    if (flag == 0) {
-      if (++spins > kSpinLimit) { atomicExch(fault, 1); break; }
+  for (;;) {
+    const int idx = j - lane;
+    const unsigned long long w = idx >= 0 ? atomic_ld64(&desc[idx]) : desc_pack(2, 0);
+    const unsigned flag = (unsigned)(w >> 62);
+    const unsigned long long incl = __ballot(flag == 2);
+    const unsigned long long none = __ballot(flag == 0);
+    const int fi = incl ? __ffsll((long long)incl) - 1 : 64;
+    const int fz = none ? __ffsll((long long)none) - 1 : 64;
+    if (fz < fi) {
+      if (++spins > kSpinLimit) {
+        if (lane == 0) atomicExch(fault, 1);
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += desc_value(w);
-    if (flag == 2) break;
-    --j;
+    long long v = lane <= fi ? desc_value(w) : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    excl += v;
+    if (fi < 64) break;
+    j -= 64;
   }
-  atomic_st64(&desc[b], desc_pack(2, excl + agg));
+  if (lane == 0) atomic_st64(&desc[b], desc_pack(2, excl + agg));
   return excl;
 }
 

@@ -146,11 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
     bool last;
     int b = scan_ticket(site, nblk, s_tk, &last);
     if (b >= nblk) break;
+    // each thread takes kScanItems consecutive entries: one workgroup scan
+    // of the per-thread sums, then a serial prefix inside the thread
+    const int i0 = b * kScanBlock + (int)threadIdx.x * kScanItems;
     int32_t dk[kScanItems];
     long long dsum = 0;
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
+      const int i = i0 + k;
       int32_t d = 0;
       if (i < nf) {
         int32_t v = F[i];
@@ -170,27 +173,29 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
       dsum += d;
     }
     long long agg;
-    (void)block_excl_scan<kBlock>(dsum, &agg, sh);
-    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    const long long ex = block_excl_scan<kBlock>(dsum, &agg, sh);
+    if (threadIdx.x < 64) {
+      const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
+      if (threadIdx.x == 0) s_excl = ex0;
+    }
     __syncthreads();
-    long long base = s_excl;
+    long long s = s_excl + ex;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
-      long long tot;
-      long long ex = block_excl_scan<kBlock>(dk[k], &tot, sh);
+      const int i = i0 + k;
       if (i < nf) {
-        long long s = base + ex;
         a.estart[i] = s;
         mark_tiles(a.tile_start, a.tile_cap, s, dk[k], i, &c->fault);
       }
-      base += tot;
+      s += dk[k];
     }
     if (b == nblk - 1 && threadIdx.x == 0) {
-      c->etotal = base;
-      c->ntiles = (int)((base + kEdgeTile - 1) / kEdgeTile);
+      const long long tot = s_excl + agg;
+      c->etotal = tot;
+      c->ntiles = (int)((tot + kEdgeTile - 1) / kEdgeTile);
     }
     block_flush(&c->support_cnt, a.support, a.n, s_sup, &s_nsup, &s_base, &c->fault);
-    block_flush(cntn, Fn, a.n, s_stay, &s_nstay, &s_base, &c->fault);
+    if (!opt) block_flush(cntn, Fn, a.n, s_stay, &s_nstay, &s_base, &c->fault);
   }
 }
 
@@ -356,10 +361,13 @@ __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
     bool last;
     int b = scan_ticket(site, nblk, s_tk, &last);
     if (b >= nblk) break;
+    // kScanItems consecutive positions per thread (see k_self)
+    const int i0 = b * kScanBlock + (int)threadIdx.x * kScanItems;
     int32_t dk[kScanItems];
     long long dsum = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
+      const int i = i0 + k;
       dk[k] = 0;
       if (i < N) {
         const int32_t v = el[i].id;
@@ -373,22 +381,24 @@ __global__ __launch_bounds__(kBlock) void k_vol_scan(PlainArgs a) {
       dsum += dk[k];
     }
     long long agg;
-    (void)block_excl_scan<kBlock>(dsum, &agg, sh);
-    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    const long long ex = block_excl_scan<kBlock>(dsum, &agg, sh);
+    if (threadIdx.x < 64) {
+      const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
+      if (threadIdx.x == 0) s_excl = ex0;
+    }
     __syncthreads();
-    long long base = s_excl;
+    long long s = s_excl + ex;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
-      long long tot;
-      long long ex = block_excl_scan<kBlock>(dk[k], &tot, sh);
+      const int i = i0 + k;
       if (i < N) {
-        long long s = base + ex;
         a.svol[i] = s + dk[k];
         mark_tiles(a.tile_start, a.tile_cap, s, dk[k], i, &c->fault);
       }
-      base += tot;
+      s += dk[k];
     }
     if (b == nblk - 1 && threadIdx.x == 0) {
+      const long long base = s_excl + agg;
       c->etotal = base;
       c->ntiles = (int)((base + kEdgeTile - 1) / kEdgeTile);
     }
@@ -502,30 +512,34 @@ __global__ __launch_bounds__(kBlock) void k_cut_scan(PlainArgs a) {
     bool last;
     int b = scan_ticket(site, nblk, s_tk, &last);
     if (b >= nblk) break;
+    // kScanItems consecutive positions per thread (see k_self)
+    const int i0 = b * kScanBlock + (int)threadIdx.x * kScanItems;
     long long dk[kScanItems];
     long long dsum = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
+      const int i = i0 + k;
       dk[k] = i < N ? (long long)a.sdeg[i] - 2ll * a.scnt[i] : 0;
       dsum += dk[k];
     }
     long long agg;
-    (void)block_excl_scan<kBlock>(dsum, &agg, sh);
-    if (threadIdx.x == 0) s_excl = scan_lookback(desc, b, agg, &c->fault);
+    const long long ex = block_excl_scan<kBlock>(dsum, &agg, sh);
+    if (threadIdx.x < 64) {
+      const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
+      if (threadIdx.x == 0) s_excl = ex0;
+    }
     __syncthreads();
-    long long base = s_excl;
+    long long cut = s_excl + ex;
     long long mc = -1, md = 1, mk = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
-      int i = b * kScanBlock + k * kBlock + (int)threadIdx.x;
-      long long tot;
-      long long ex = block_excl_scan<kBlock>(dk[k], &tot, sh);
+      const int i = i0 + k;
+      cut += dk[k];
       if (i < N) {
-        long long cut = base + ex + dk[k];
-        long long vol = a.svol[i];
-        long long den = vol < vt - vol ? vol : vt - vol;
+        const long long vol = a.svol[i];
+        const long long den = vol < vt - vol ? vol : vt - vol;
         if (den > 0 && (mk <= 0 || ratio_lt(cut, den, mc, md))) { mc = cut; md = den; mk = i + 1; }
       }
-      base += tot;
     }
     s_bc[threadIdx.x] = mc; s_bd[threadIdx.x] = md; s_bk[threadIdx.x] = mk;
     __syncthreads();

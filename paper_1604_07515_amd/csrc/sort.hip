@@ -29,6 +29,9 @@ constexpr int kPerThr = kTileS / kSortBlk;
 constexpr int kBT = 16;             // elements per thread in the block sort
 constexpr int kTileB = kSortBlk * kBT;  // elements per block-sort tile
 
+// The largest element: pads a tile past the element count.
+constexpr SortElem kMaxElem = {~0ull, INT32_MAX, INT32_MAX};
+
 // LDS index of element i of a block-sort tile: one spare slot after every
 // 16 elements, so the 16-element rows of consecutive threads start on
 // different banks.
@@ -67,13 +70,7 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
 #pragma unroll
     for (int k = 0; k < kBT; k++) {
       const int i = k * kSortBlk + t;
-      SortElem e;
-      if (base + i < N) {
-        e = buf[base + i];
-      } else {
-        e.seg = INT32_MAX; e.key = ~0ull; e.id = INT32_MAX;
-      }
-      sh[lds_pad(i)] = e;
+      sh[lds_pad(i)] = base + i < N ? buf[base + i] : kMaxElem;
     }
     __syncthreads();
     // elements 16t .. 16t+15, sorted in registers (bitonic network)
@@ -108,15 +105,23 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
         const int mid = (lo + hi) >> 1;
         if (elem_lt(sh[lds_pad(B + d - 1 - mid)], sh[lds_pad(A + mid)])) hi = mid; else lo = mid + 1;
       }
+      // the two run heads stay in registers; an exhausted run shows the
+      // largest element, equal to the tile padding, so either choice
+      // between the two then outputs the same value
       int ia = lo, ib = d - lo;
+      SortElem ha = ia < L ? sh[lds_pad(A + ia)] : kMaxElem;
+      SortElem hb = ib < L ? sh[lds_pad(B + ib)] : kMaxElem;
 #pragma unroll
       for (int k = 0; k < kBT; k++) {
-        bool takeA;
-        if (ib >= L) takeA = true;
-        else if (ia >= L) takeA = false;
-        else takeA = !elem_lt(sh[lds_pad(B + ib)], sh[lds_pad(A + ia)]);
-        if (takeA) { x[k] = sh[lds_pad(A + ia)]; ia++; }
-        else { x[k] = sh[lds_pad(B + ib)]; ib++; }
+        if (!elem_lt(hb, ha)) {
+          x[k] = ha;
+          ia++;
+          ha = ia < L ? sh[lds_pad(A + ia)] : kMaxElem;
+        } else {
+          x[k] = hb;
+          ib++;
+          hb = ib < L ? sh[lds_pad(B + ib)] : kMaxElem;
+        }
       }
       __syncthreads();
 #pragma unroll
