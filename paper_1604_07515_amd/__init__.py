@@ -252,6 +252,19 @@ class Context:
 
     @staticmethod
     def queries(seeds, alpha, eps, rule=PLC_RULE_OPT):
+        if isinstance(seeds, (int, np.integer)):
+            seeds = (seeds,)
+        if isinstance(seeds, (list, tuple)) and all(np.isscalar(x) for x in (alpha, eps, rule)):
+            # one parameter set for all seeds: no array broadcasting
+            qa = (plc_query * len(seeds))()
+            a, e, r = float(alpha), float(eps), int(rule)
+            for i, s in enumerate(seeds):
+                q = qa[i]
+                q.seed = int(s)
+                q.rule = r
+                q.alpha = a
+                q.eps = e
+            return qa
         seeds = np.atleast_1d(np.asarray(seeds, dtype=np.int64))
         k = len(seeds)
         alpha = np.broadcast_to(np.asarray(alpha, np.float64), (k,))
