@@ -297,10 +297,13 @@ plc_status plc_release(plc_ctx* ctx, uint64_t id);
 plc_status plc_arena_free_bytes(plc_ctx* ctx, size_t* total, size_t* largest);
 
 /*
- * Device-time accounting, measured with HIP events on the context's stream
- * around kernel launches (event-record nodes inside replayed graphs), off by
- * default.  Plain path: only rounds that pushed something are counted for
- * the scatter and self kernels.  Batch engine: one scatter launch per step
+ * Device-time accounting with HIP events on the context's stream, off by
+ * default.  While it is on, rounds are launched directly instead of from
+ * recorded graphs, and the scatter and self kernels are launched with start
+ * and stop events that take the kernel's own dispatch timestamps
+ * (hipExtLaunchKernelGGL); the sweep is bracketed by an event pair.  Plain
+ * path: only rounds that pushed something are counted for the scatter and
+ * self kernels.  Batch engine: one scatter launch per step
  * (all scheduled queries' edges) and one sweep sequence per step that swept;
  * self is not timed.
  *   scatter: the edgeMap kernel; units = pushed edges, entries = pushes

@@ -21,6 +21,7 @@
 //
 // The kernels that touch per-query state are templates over the state layout
 // (DenseState or CompactState, see batch_device.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1161,12 +1162,21 @@ hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_se
   return hipGetLastError();
 }
 
-hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter,
-                                bool compact) {
-  if (compact)
-    hipLaunchKernelGGL(k_b_scatter<CompactState>, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+template <class St>
+static void scatter_launch(hipStream_t s, const BatchArgs& a, int grid, hipEvent_t t0,
+                           hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_b_scatter<St>, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a);
   else
-    hipLaunchKernelGGL(k_b_scatter<DenseState>, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_b_scatter<St>, dim3(grid), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter,
+                                bool compact, hipEvent_t t0, hipEvent_t t1) {
+  if (compact)
+    scatter_launch<CompactState>(s, a, grid_scatter, t0, t1);
+  else
+    scatter_launch<DenseState>(s, a, grid_scatter, t0, t1);
   return hipGetLastError();
 }
 

@@ -174,8 +174,10 @@ hipError_t launch_gdh_init(hipStream_t s, const BatchArgs& a, int2* gdh);  // co
 hipError_t launch_batch_admit(hipStream_t s, const BatchArgs& a, const Admit* adm, int count,
                               bool compact);
 hipError_t launch_batch_plan_self(hipStream_t s, const BatchArgs& a, int grid_self, bool compact);
+// With t0 set: launched with start and stop events on its own dispatch
+// timestamps (hipExtLaunchKernelGGL); not for graph capture.
 hipError_t launch_batch_scatter(hipStream_t s, const BatchArgs& a, int grid_scatter,
-                                bool compact);
+                                bool compact, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_batch_round_end(hipStream_t s, const BatchArgs& a);
 hipError_t launch_batch_sweep(hipStream_t s, const BatchArgs& a, int nseg, int64_t max_elems,
                               int grid, bool compact);

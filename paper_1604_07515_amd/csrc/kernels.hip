@@ -23,6 +23,7 @@
 // (cn*rho)/d are each rounded separately (the library is built with
 // -ffp-contract=off), and the threshold is eps*(double)d.  Only the order of
 // the atomic additions into r differs from a sequential evaluation.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -584,38 +585,44 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
   if (blockIdx.x == 0 && c->N > 0) cut_final(a, c, c->N);
-  __shared__ int32_t s_id[kBlock];
-  __shared__ double s_val[kBlock];
-  __shared__ int s_n, s_base, s_last;
+  __shared__ long long sh[kBlock / 64 + 1];
+  __shared__ long long s_base;
+  __shared__ int s_last;
   int32_t* const out_rid = c->out.rid;
   double* const out_rval = c->out.rval;
   const long long rcap = c->out.rcap;
   const int T = (int64_t)c->touched_cnt > a.n ? (int)a.n : c->touched_cnt;
   const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  for (int base = blockIdx.x * kBlock; base < T; base += gridDim.x * kBlock) {
-    int i = base + (int)threadIdx.x;
-    if (i < T) {
-      int32_t v = a.touched[i];
-      double rv = a.vr[v].r;
-      a.vr[v].r = 0.0;
-      if (rv != 0.0) {
-        int j = atomicAdd(&s_n, 1);
-        s_id[j] = v;
-        s_val[j] = rv;
+  // kScanBlock touched entries per workgroup step: read and clear r, then
+  // place the nonzeros with one workgroup scan and one global atomic
+  for (int base = blockIdx.x * kScanBlock; base < T; base += gridDim.x * kScanBlock) {
+    int32_t v[kScanItems];
+    double rv[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const int i = base + k * kBlock + (int)threadIdx.x;
+      v[k] = i < T ? a.touched[i] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) rv[k] = v[k] >= 0 ? a.vr[v[k]].r : 0.0;
+    long long cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      if (v[k] >= 0) a.vr[v[k]].r = 0.0;
+      cnt += rv[k] != 0.0;
+    }
+    long long tot;
+    const long long off = block_excl_scan<kBlock>(cnt, &tot, sh);
+    if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&c->rnnz, (int)tot) : 0;
+    __syncthreads();
+    long long slot = s_base + off;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      if (rv[k] != 0.0) {
+        if (slot < rcap) { out_rid[slot] = v[k]; out_rval[slot] = rv[k]; } else c->fault = 1;
+        slot++;
       }
     }
-    __syncthreads();
-    int cnt = s_n;
-    if (threadIdx.x == 0) s_base = cnt > 0 ? atomicAdd(&c->rnnz, cnt) : 0;
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) {
-      long long slot = (long long)s_base + j;
-      if (slot < rcap) { out_rid[slot] = s_id[j]; out_rval[slot] = s_val[j]; } else c->fault = 1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
   }
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
@@ -645,13 +652,20 @@ hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, in
   return hipGetLastError();
 }
 
-hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid) {
-  hipLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0, hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a);
+  else
+    hipLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid) {
-  hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a);
+hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0,
+                          hipEvent_t t1) {
+  if (t0)
+    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a);
+  else
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -668,9 +682,11 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max
   hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vol_scan, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_cut_count, dim3(grid), dim3(kBlock), 0, s, a);
+  // the count and the final gather walk many short, latency-bound steps:
+  // a larger grid keeps each workgroup to about one
+  hipLaunchKernelGGL(k_cut_count, dim3(4 * grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_cut_scan, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sweep_finish, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sweep_finish, dim3(4 * grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -50,32 +50,20 @@ struct EventPair {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
-static void event_pair_free(EventPair& e) {
-  if (e.a) (void)hipEventDestroy(e.a);
-  if (e.b) (void)hipEventDestroy(e.b);
-  e = EventPair{};
-}
-
 // A launch sequence recorded once as a HIP graph (on the context's capture
 // stream) and replayed with one hipGraphLaunch on the caller's stream.  The
-// fields below exec say what it was recorded for; a timed graph also holds
-// event-record nodes around the kernels that are timed, one pair per round.
+// fields below exec say what it was recorded for.  Graphs carry no event
+// nodes: while timing is on, kernels are launched directly instead.
 struct Captured {
   hipGraphExec_t exec = nullptr;
   int gs = -1, gc = -1, gw = -1, rounds = -1;
-  bool timed = false;
-  std::vector<EventPair> ev_self, ev_scatter;
-  EventPair ev_sweep;
-  bool matches(int s, int c, int w, int r, bool t) const {
-    return exec && gs == s && gc == c && gw == w && rounds == r && timed == t;
+  bool matches(int s, int c, int w, int r) const {
+    return exec && gs == s && gc == c && gw == w && rounds == r;
   }
 };
 
 static void captured_free(Captured& c) {
   if (c.exec) (void)hipGraphExecDestroy(c.exec);
-  for (auto& e : c.ev_self) event_pair_free(e);
-  for (auto& e : c.ev_scatter) event_pair_free(e);
-  event_pair_free(c.ev_sweep);
   c = Captured{};
 }
 
@@ -519,43 +507,23 @@ static bool capture(plc_ctx* ctx, Captured& c, F&& body) {
   return true;
 }
 
-static hipError_t ev_ext(hipEvent_t ev, hipStream_t cs) {
-  return hipEventRecordWithFlags(ev, cs, hipEventRecordExternal);
-}
-
-// Graph of R plain rounds (self, scatter); timed graphs bracket each kernel
-// with events.
+// Graph of R plain rounds (self, scatter).
 static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   Captured& c = g->chunk_g[R];
-  if (c.matches(gs, gc, 0, R, ctx->timing)) return &c;
+  if (c.matches(gs, gc, 0, R)) return &c;
   captured_free(c);
   c.gs = gs;
   c.gc = gc;
   c.gw = 0;
   c.rounds = R;
-  c.timed = ctx->timing;
-  if (c.timed) {
-    c.ev_self.resize(R);
-    c.ev_scatter.resize(R);
-    for (int i = 0; i < R; i++)
-      if (ev_pair(c.ev_self[i]) != hipSuccess || ev_pair(c.ev_scatter[i]) != hipSuccess) {
-        captured_free(c);
-        ctx->use_graphs = false;
-        return nullptr;
-      }
-  }
   const PlainArgs& a = g->args;
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
     hipError_t r;
     for (int i = 0; i < R; i++) {
-      if (c.timed && (r = ev_ext(c.ev_self[i].a, cs)) != hipSuccess) return r;
       if ((r = plc::launch_self(cs, a, gs)) != hipSuccess) return r;
-      if (c.timed && (r = ev_ext(c.ev_self[i].b, cs)) != hipSuccess) return r;
-      if (c.timed && (r = ev_ext(c.ev_scatter[i].a, cs)) != hipSuccess) return r;
       if ((r = plc::launch_scatter(cs, a, gc)) != hipSuccess) return r;
-      if (c.timed && (r = ev_ext(c.ev_scatter[i].b, cs)) != hipSuccess) return r;
     }
     return hipSuccess;
   });
@@ -567,30 +535,21 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
 static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count) {
   const int gw = shape(g->plain_sweep, ctx->grid_sweep);
   Captured& c = g->sweep_g[max_count];
-  if (c.matches(0, 0, gw, 0, ctx->timing)) return &c;
+  if (c.matches(0, 0, gw, 0)) return &c;
   captured_free(c);
   c.gs = 0;
   c.gc = 0;
   c.gw = gw;
   c.rounds = 0;
-  c.timed = ctx->timing;
-  if (c.timed && ev_pair(c.ev_sweep) != hipSuccess) {
-    captured_free(c);
-    ctx->use_graphs = false;
-    return nullptr;
-  }
   const PlainArgs& a = g->args;
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
-    hipError_t r;
-    if (c.timed && (r = ev_ext(c.ev_sweep.a, cs)) != hipSuccess) return r;
-    if ((r = plc::launch_sweep(cs, a, gw, max_count)) != hipSuccess) return r;
-    if (c.timed && (r = ev_ext(c.ev_sweep.b, cs)) != hipSuccess) return r;
-    return hipSuccess;
+    return plc::launch_sweep(cs, a, gw, max_count);
   });
   return ok ? &c : nullptr;
 }
 
-// Queue `rounds` rounds; with timing on, bracket each kernel with events
+// Queue `rounds` rounds as direct launches; with timing on, each kernel
+// carries start and stop events on its own dispatch timestamps
 // (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk).
 
 static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
@@ -606,12 +565,11 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
       while (ctx->ev_scatter.size() <= k) ctx->ev_scatter.emplace_back();
       if ((r = ev_pair(ctx->ev_self[k])) != hipSuccess) return r;
       if ((r = ev_pair(ctx->ev_scatter[k])) != hipSuccess) return r;
-      (void)hipEventRecord(ctx->ev_self[k].a, s);
-      if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
-      (void)hipEventRecord(ctx->ev_self[k].b, s);
-      (void)hipEventRecord(ctx->ev_scatter[k].a, s);
-      if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
-      (void)hipEventRecord(ctx->ev_scatter[k].b, s);
+      if ((r = plc::launch_self(s, a, gs, ctx->ev_self[k].a, ctx->ev_self[k].b)) != hipSuccess)
+        return r;
+      if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b)) !=
+          hipSuccess)
+        return r;
     } else {
       if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
       if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
@@ -641,18 +599,14 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   Ctl& h = *ctx->ctl_host;
   for (;;) {
     const int R = chunk;
-    Captured* cg = ctx->use_graphs ? plain_chunk_graph(ctx, g, R) : nullptr;
-    const EventPair* ev_s;
-    const EventPair* ev_c;
-    if (cg) {
+    // while timing is on, rounds are launched directly (graphs carry no events)
+    Captured* cg = ctx->use_graphs && !ctx->timing ? plain_chunk_graph(ctx, g, R) : nullptr;
+    if (cg)
       HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
-      ev_s = cg->ev_self.data();
-      ev_c = cg->ev_scatter.data();
-    } else {
+    else
       HIPCHK(ctx, queue_rounds(ctx, g, R));
-      ev_s = ctx->ev_self.data();
-      ev_c = ctx->ev_scatter.data();
-    }
+    const EventPair* ev_s = ctx->ev_self.data();
+    const EventPair* ev_c = ctx->ev_scatter.data();
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (ctx->timing) {
@@ -709,10 +663,9 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   int64_t bound = 1024;
   while (bound < h.support_cnt) bound <<= 1;
   const EventPair* sweep_ev = &ctx->ev_sweep;
-  Captured* sg = ctx->use_graphs ? plain_sweep_graph(ctx, g, bound) : nullptr;
+  Captured* sg = ctx->use_graphs && !ctx->timing ? plain_sweep_graph(ctx, g, bound) : nullptr;
   if (sg) {
     HIPCHK(ctx, hipGraphLaunch(sg->exec, s));
-    sweep_ev = &sg->ev_sweep;
   } else {
     if (ctx->timing) {
       HIPCHK(ctx, ev_pair(ctx->ev_sweep));
@@ -1119,35 +1072,23 @@ extern "C" plc_status plc_submit(plc_ctx* ctx, plc_graph* g, const plc_query* q,
   return first;
 }
 
-// Graph of one batched round: plan, self, scatter (timed graphs bracket it
-// with events), round end.
+// Graph of one batched round: plan, self, scatter, round end.
 static Captured* batch_round_graph(plc_ctx* ctx, plc_graph* g) {
   const int gs = shape(g->batch_self, ctx->grid_self);
   const int gc = shape(g->batch_scatter, ctx->grid_scatter);
   Captured& c = g->batch->round_g;
-  if (c.matches(gs, gc, 0, 1, ctx->timing)) return &c;
+  if (c.matches(gs, gc, 0, 1)) return &c;
   captured_free(c);
   c.gs = gs;
   c.gc = gc;
   c.gw = 0;
   c.rounds = 1;
-  c.timed = ctx->timing;
-  if (c.timed) {
-    c.ev_scatter.resize(1);
-    if (ev_pair(c.ev_scatter[0]) != hipSuccess) {
-      captured_free(c);
-      ctx->use_graphs = false;
-      return nullptr;
-    }
-  }
   const plc::BatchArgs& a = g->batch->args;
   const bool compact = g->batch->compact;
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
     hipError_t r;
     if ((r = plc::launch_batch_plan_self(cs, a, gs, compact)) != hipSuccess) return r;
-    if (c.timed && (r = ev_ext(c.ev_scatter[0].a, cs)) != hipSuccess) return r;
     if ((r = plc::launch_batch_scatter(cs, a, gc, compact)) != hipSuccess) return r;
-    if (c.timed && (r = ev_ext(c.ev_scatter[0].b, cs)) != hipSuccess) return r;
     return plc::launch_batch_round_end(cs, a);
   });
   return ok ? &c : nullptr;
@@ -1380,22 +1321,24 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
   for (int q = 0; q < E.B; q++) any_run |= E.state[q] == HS_RUN;
   const EventPair* scatter_ev = nullptr;
   if (any_run) {
-    Captured* rg = ctx->use_graphs ? batch_round_graph(ctx, g) : nullptr;
+    // while timing is on, the round is launched directly (graphs carry no
+    // events) and the scatter carries events on its own dispatch timestamps
+    Captured* rg = ctx->use_graphs && !ctx->timing ? batch_round_graph(ctx, g) : nullptr;
     if (rg) {
       HIPCHK(ctx, hipGraphLaunch(rg->exec, s));
-      if (ctx->timing) scatter_ev = &rg->ev_scatter[0];
     } else {
       HIPCHK(ctx, plc::launch_batch_plan_self(s, a, shape(g->batch_self, ctx->grid_self),
                                               E.compact));
+      hipEvent_t t0 = nullptr, t1 = nullptr;
       if (ctx->timing) {
         if (ctx->ev_scatter.empty()) ctx->ev_scatter.emplace_back();
         HIPCHK(ctx, ev_pair(ctx->ev_scatter[0]));
-        HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].a, s));
         scatter_ev = &ctx->ev_scatter[0];
+        t0 = scatter_ev->a;
+        t1 = scatter_ev->b;
       }
       HIPCHK(ctx, plc::launch_batch_scatter(s, a, shape(g->batch_scatter, ctx->grid_scatter),
-                                            E.compact));
-      if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_scatter[0].b, s));
+                                            E.compact, t0, t1));
       HIPCHK(ctx, plc::launch_batch_round_end(s, a));
     }
   }

@@ -135,8 +135,12 @@ static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
                              double alpha, double eps, int32_t max_rounds);
-hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid);
-hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid);
+// With t0 set, the kernel is launched with start and stop events that take
+// its own dispatch timestamps (hipExtLaunchKernelGGL); not for graph capture.
+hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
+                       hipEvent_t t1 = nullptr);
+hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
+                          hipEvent_t t1 = nullptr);
 // max_count: bound on the support size, sets the number of merge passes.
 // The sweep writes its results to the destinations in *a.out_host and, in
 // its last kernel, resets the query's dense state (r over the touched list,

@@ -4,9 +4,10 @@
 // queries, key is the bit-inverted IEEE pattern of the positive ratio p/d
 // (ascending key = non-increasing ratio) and id breaks ties (ascending id).
 //
-// Merge sort: one launch sorts 4096-element tiles in LDS (each thread sorts
-// 16 elements in registers with a bitonic network, then eight rounds of
-// merge-path merges in LDS double the sorted runs up to the tile), then
+// Merge sort: one launch sorts 4096-element tiles in LDS (each of 512
+// threads sorts 8 elements in registers with a bitonic network, then nine
+// rounds of merge-path merges in LDS double the sorted runs up to the tile),
+// then
 // each merge pass doubles the sorted run length.  A pass produces
 // 1024-element output tiles; the two split points of a tile on the merge
 // path are found by a cooperative 128-ary search (a few rounds of parallel
@@ -26,16 +27,17 @@ namespace plc {
 constexpr int kSortBlk = 256;
 constexpr int kTileS = 1024;        // elements per merge-pass output tile
 constexpr int kPerThr = kTileS / kSortBlk;
-constexpr int kBT = 16;             // elements per thread in the block sort
-constexpr int kTileB = kSortBlk * kBT;  // elements per block-sort tile
+constexpr int kBSBlk = 512;         // threads of the block sort
+constexpr int kBT = 8;              // elements per thread in the block sort
+constexpr int kTileB = kBSBlk * kBT;    // elements per block-sort tile
 
 // The largest element: pads a tile past the element count.
 constexpr SortElem kMaxElem = {~0ull, INT32_MAX, INT32_MAX};
 
 // LDS index of element i of a block-sort tile: one spare slot after every
-// 16 elements, so the 16-element rows of consecutive threads start on
+// kBT elements, so the kBT-element rows of consecutive threads start on
 // different banks.
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__device__ __forceinline__ int lds_pad(int i) { return i + i / kBT; }
 
 __device__ __forceinline__ bool elem_lt(const SortElem& a, const SortElem& b) {
   if (a.seg != b.seg) return a.seg < b.seg;
@@ -56,12 +58,12 @@ __device__ __forceinline__ void cswap(SortElem& a, SortElem& b, bool up) {
   }
 }
 
-__global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
+__global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
   if (!sort_enabled(s)) return;
   const int N = *s.count;
   const int flip = *s.flip;
   SortElem* buf = s.buf[flip];
-  __shared__ SortElem sh[kTileB + kTileB / 16];
+  __shared__ SortElem sh[kTileB + kTileB / kBT];
   const int ntiles = (N + kTileB - 1) / kTileB;
   const int t = threadIdx.x;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -69,11 +71,11 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
     // coalesced load (element k*256 + t), padded past N with the largest element
 #pragma unroll
     for (int k = 0; k < kBT; k++) {
-      const int i = k * kSortBlk + t;
+      const int i = k * kBSBlk + t;
       sh[lds_pad(i)] = base + i < N ? buf[base + i] : kMaxElem;
     }
     __syncthreads();
-    // elements 16t .. 16t+15, sorted in registers (bitonic network)
+    // elements kBT*t .. kBT*t + kBT - 1, sorted in registers (bitonic network)
     SortElem x[kBT];
 #pragma unroll
     for (int k = 0; k < kBT; k++) x[k] = sh[lds_pad(t * kBT + k)];
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
     for (int k = 0; k < kBT; k++) sh[lds_pad(t * kBT + k)] = x[k];
     __syncthreads();
     // merge runs of L into runs of 2L; thread t produces outputs
-    // [16t, 16t + 16) of the tile, i.e. diagonal d of its pair of runs
+    // [kBT*t, kBT*t + kBT) of the tile, i.e. diagonal d of its pair of runs
     for (int L = kBT; L < kTileB; L <<= 1) {
       const int o = t * kBT;
       const int pb = (o / (2 * L)) * (2 * L);
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(kSortBlk) void k_block_sort(SortArgs s) {
     }
 #pragma unroll
     for (int k = 0; k < kBT; k++) {
-      const int i = k * kSortBlk + t;
+      const int i = k * kBSBlk + t;
       if (base + i < N) buf[base + i] = sh[lds_pad(i)];
     }
     __syncthreads();
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
 }
 
 hipError_t launch_sort(hipStream_t st, const SortArgs& s, int64_t max_count, int grid) {
-  hipLaunchKernelGGL(k_block_sort, dim3(grid), dim3(kSortBlk), 0, st, s);
+  hipLaunchKernelGGL(k_block_sort, dim3(grid), dim3(kBSBlk), 0, st, s);
   for (int64_t L = kTileB; L < max_count; L <<= 1)
     hipLaunchKernelGGL(k_merge_pass, dim3(grid), dim3(kSortBlk), 0, st, s, (int)L);
   return hipGetLastError();

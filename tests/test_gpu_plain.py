@@ -197,3 +197,32 @@ def test_int32_offsets_rmat16_seed0(plc):
             out.append(c.result(ids[0], release=True))
     check_query(g, out[0], x, 0.01, 1e-7, OPT)
     check_same(g, out[0], out[1])
+
+
+def test_result_block_does_not_fit(plc):
+    """No room for a query's result block: the sweep writes into the
+    library's own buffers, the query reports PLC_E_NOMEM with its counters,
+    and the dense state is still reset (a following query, whose neighbours
+    the first one touched, matches the oracle)."""
+    g = synth.rmat(14, 8, seed=2)
+    probe = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs))
+    probe.load_graph(g.off, g.nbr)
+    total, _ = probe.arena_free()
+    used = probe.arena_bytes - total
+    probe.close()
+    with plc.Context(arena_bytes=used + (16 << 10)) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        big = int(np.argmax(g.deg))
+        say("case result block does not fit: seed", big)
+        ids, infos = c.run(hg, [big], 0.01, 1e-7, OPT, check=False)
+        assert infos[0]["status"] == plc.PLC_E_NOMEM
+        ref = oracle.prnibble(g.off, g.nbr, big, 0.01, 1e-7, OPT)
+        assert infos[0]["support"] > 1000
+        if ref.min_rel_gap >= 1e-10:
+            assert infos[0]["rounds"] == ref.rounds and infos[0]["edges"] == ref.edges
+        c.release(ids[0])
+        # support 1, touched d + 1: its block fits in the headroom
+        small = int(np.flatnonzero(g.deg == 3)[0])
+        for _ in range(2):
+            ids2, _ = c.run(hg, [small], 0.05, 0.5, OPT)
+            check_query(g, c.result(ids2[0], release=True), small, 0.05, 0.5, OPT)
