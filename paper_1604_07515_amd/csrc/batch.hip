@@ -1021,43 +1021,68 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int nseg = c->sw_nseg;
   const long long total = c->sw_touch_total;
+  // per segment: start in the flattened touched space, its slot's touched
+  // list and records, and where its r nonzeros go
   __shared__ long long s_toff[kMaxSlots];
-  __shared__ int s_cnt[kBlock], s_base[kBlock];
+  __shared__ const int32_t* s_tl[kMaxSlots];
+  __shared__ VRec* s_tb[kMaxSlots];
+  __shared__ int32_t* s_orid[kMaxSlots];
+  __shared__ double* s_orval[kMaxSlots];
+  __shared__ int s_cnt[kMaxSlots], s_base[kMaxSlots];
   __shared__ int s_lo;
-  for (int j = threadIdx.x; j < nseg; j += kBlock) s_toff[j] = a.segs[j].touch_off;
+  for (int j = threadIdx.x; j < nseg; j += kBlock) {
+    const SweepSeg& sg = a.segs[j];
+    const Slot& S = a.slots[sg.slot];
+    s_toff[j] = sg.touch_off;
+    s_tl[j] = S.touched;
+    s_tb[j] = S.tab;
+    s_orid[j] = sg.out_rid;
+    s_orval[j] = sg.out_rval;
+  }
   __syncthreads();
-  for (long long x0 = (long long)blockIdx.x * kBlock; x0 < total; x0 += (long long)gridDim.x * kBlock) {
+  // kScanBlock entries per workgroup step (a step spans at most nseg <=
+  // kMaxSlots segments), four per thread with their loads issued together
+  for (long long x0 = (long long)blockIdx.x * kScanBlock; x0 < total;
+       x0 += (long long)gridDim.x * kScanBlock) {
     if (threadIdx.x == 0) s_lo = seg_of(s_toff, nseg, x0);
-    s_cnt[threadIdx.x] = 0;
+    for (int j = threadIdx.x; j < kMaxSlots; j += kBlock) s_cnt[j] = 0;
     __syncthreads();
     const int slo = s_lo;
-    const long long x = x0 + threadIdx.x;
-    int s = -1, rk = -1;
-    int32_t v = 0;
-    double rv = 0.0;
-    if (x < total) {
-      s = seg_of(s_toff, nseg, x);
-      const SweepSeg& sg = a.segs[s];
-      const Slot& S = a.slots[sg.slot];
-      const long long i = x - s_toff[s];
-      v = S.touched[i];
-      VRec* rec = S.tab + v;
-      rv = rec->r;
-      rec->r = 0.0;
-      if (rv != 0.0) rk = atomicAdd(&s_cnt[s - slo], 1);  // s - slo < kBlock
+    int sk[kScanItems];
+    int32_t vk[kScanItems];
+    double rv[kScanItems];
+    int rk[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const long long x = x0 + k * kBlock + threadIdx.x;
+      sk[k] = -1;
+      vk[k] = 0;
+      if (x < total) {
+        sk[k] = seg_of(s_toff, nseg, x);
+        vk[k] = s_tl[sk[k]][x - s_toff[sk[k]]];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) rv[k] = sk[k] >= 0 ? s_tb[sk[k]][vk[k]].r : 0.0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      rk[k] = -1;
+      if (sk[k] < 0) continue;
+      s_tb[sk[k]][vk[k]].r = 0.0;
+      if (rv[k] != 0.0) rk[k] = atomicAdd(&s_cnt[sk[k] - slo], 1);
     }
     __syncthreads();
-    {
-      const int j = threadIdx.x;
-      if (slo + j < nseg && s_cnt[j] > 0)
-        s_base[j] = atomicAdd(&a.slots[a.segs[slo + j].slot].rnnz, s_cnt[j]);
-    }
+    for (int j = threadIdx.x; slo + j < nseg && j < kMaxSlots; j += kBlock)
+      if (s_cnt[j] > 0) s_base[j] = atomicAdd(&a.slots[a.segs[slo + j].slot].rnnz, s_cnt[j]);
     __syncthreads();
-    if (rk >= 0) {
-      const SweepSeg& sg = a.segs[s];
-      const long long pos = (long long)s_base[s - slo] + rk;
-      if (pos >= a.slots[sg.slot].touched_cnt) c->fault = 1;
-      else if (sg.out_rid) { sg.out_rid[pos] = v; sg.out_rval[pos] = rv; }
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      if (rk[k] < 0) continue;
+      const int sg = sk[k];
+      const long long pos = (long long)s_base[sg - slo] + rk[k];
+      const long long len = (sg + 1 < nseg ? s_toff[sg + 1] : total) - s_toff[sg];
+      if (pos >= len) c->fault = 1;
+      else if (s_orid[sg]) { s_orid[sg][pos] = vk[k]; s_orval[sg][pos] = rv[k]; }
     }
     __syncthreads();
   }
@@ -1201,14 +1226,16 @@ static hipError_t sweep_kernels(hipStream_t s, const BatchArgs& a, int nseg, int
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sw_rank<St>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_scan<false>, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sw_count<St>, dim3(grid), dim3(kBlock), 0, s, a);
+  // the count, the gathers and the reset walk many short, latency-bound
+  // steps: a larger grid keeps more of them in flight
+  hipLaunchKernelGGL(k_sw_count<St>, dim3(4 * grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_scan<true>, dim3(grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_sw_argmin, dim3(nseg), dim3(kBlock), 0, s, a);
   if (St::kCompact) {
-    hipLaunchKernelGGL(k_sw_gather, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sw_gather, dim3(4 * grid), dim3(kBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_sw_finish, dim3(grid), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_sw_reset, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sw_finish, dim3(4 * grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sw_reset, dim3(4 * grid), dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
