@@ -297,6 +297,45 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
             "roofline": roofline(tm, "k_b_scatter<CompactState>")}
 
 
+def bench_grid3d(plc, synth, side=215, nq=8):
+    """The paper's 3D-grid input (a side^3 torus, every vertex of degree 6;
+    side 215 gives its n = 9,938,375 and 3n edges): one PR-Nibble + sweep at a
+    time, alpha 0.01, eps 1e-7, optimized rule, as in the paper's PR-Nibble
+    timing (40 cores: 0.502 s per query).  Every vertex of a torus is
+    equivalent, so the seeds only relabel the same query."""
+    import numpy as np
+    t0 = time.time()
+    g = synth.torus3d(side)
+    log("grid3d %d^3: n=%d arcs=%d (%.1fs)" % (side, g.n, g.arcs, time.time() - t0))
+    seeds = [int(x) for x in np.random.default_rng(3).integers(0, g.n, nq)]
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (256 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+    ctx.autotune(hg, seeds[:2], 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
+    for s in seeds[:2]:
+        ids, _ = ctx.run(hg, [s], 0.01, 1e-7)
+        ctx.release(ids[0])
+    lat, acc = [], {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
+    import torch
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in seeds:
+        q0 = time.perf_counter()
+        ids, infos = ctx.run(hg, [s], 0.01, 1e-7)
+        lat.append(time.perf_counter() - q0)
+        account(acc, infos, ids, ctx)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    ctx.close()
+    per = el / nq
+    return {"workload": "torus%d_3dgrid_plain" % side, "n": g.n, "arcs": g.arcs,
+            "alpha": 0.01, "eps": 1e-7, "queries": nq, "seconds_per_query": per,
+            "queries_per_s": nq / el, "edges_per_s": acc["edges"] / el,
+            "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
+            "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
+            "paper_40core_seconds_per_query": 0.502,
+            "speedup_vs_paper_40core": 0.502 / per}
+
+
 def cpu_baseline(oracle, g, work, budget):
     """The oracle, single-threaded, on the workload's queries in order (the
     list repeated until `budget` seconds of work)."""
@@ -346,7 +385,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["plain", "batched", "serving", "large"], default=None,
+    ap.add_argument("--only", choices=["plain", "batched", "serving", "large", "grid3d"],
+                    default=None,
                     help="run one workload only (the others are reported as skipped); "
                          "'large' (R-MAT 2^26, 1024 seeds) runs only when asked for")
     ap.add_argument("--serve-scale", type=int, default=24)
@@ -400,6 +440,10 @@ def main():
             bat_c["edges_per_s"], bat_c["queries_per_s"]))
     srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries, args.serve_slots,
                          compact=args.serve_state == "compact") if want("serving") else None)
+    grid = bench_grid3d(plc, synth) if want("grid3d") else None
+    if grid:
+        log("grid3d: %.2f ms per query (%.0fx the paper's 40-core time)" % (
+            grid["seconds_per_query"] * 1e3, grid["speedup_vs_paper_40core"]))
     big = bench_large(plc, synth) if args.only == "large" else None
     if big:
         log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
@@ -422,7 +466,7 @@ def main():
                     "alpha": 0.01, "eps": 1e-7, "rule": "optimized", "queries_per_step": 16,
                     "path": "plain (one query at a time)"} if plain else
                    {"workload": bat["workload"], "n": g.n, "arcs": g.arcs} if bat else
-                   {"workload": (srv or big or {}).get("workload")}),
+                   {"workload": (srv or big or grid or {}).get("workload")}),
     }
     if main_res:
         out["queries_per_s"] = main_res["queries_per_s"]
@@ -439,6 +483,8 @@ def main():
         out["batched_compact"] = {k: v for k, v in bat_c.items() if k != "queries"}
     if big:
         out["large"] = big
+    if grid:
+        out["grid3d"] = grid
     if srv:
         out["serving"] = srv
     work = []
