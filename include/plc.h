@@ -175,6 +175,24 @@ plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count
                    plc_result_info* infos);
 
 /*
+ * Plain path, one query from a seed set (Sec. 3: the local algorithms start
+ * from a seed vertex or a set of seed vertices).  The paper leaves the
+ * initial split of the unit mass open; it is split equally over the
+ * distinct seeds: r = 1/|S| on each, and all of S forms the first frontier.
+ * seeds: host array of nseeds vertex ids (duplicates allowed, counted
+ * once), read before the call returns.  alpha, eps, rule as in plc_query.
+ * *id (may be NULL) and *info (may be NULL) as for plc_run.  Blocks until
+ * done.  Returns PLC_OK (also when max_rounds stopped the push: then
+ * info->status is PLC_E_LIMIT and the partial p is swept), PLC_E_INVALID
+ * (nseeds < 1, a seed out of range or of degree 0, bad alpha/eps/rule;
+ * nothing runs), PLC_E_NOMEM (no room for the result: the counters are
+ * still in *info) or PLC_E_HIP.
+ */
+plc_status plc_run_set(plc_ctx* ctx, plc_graph* g, const int32_t* seeds, int32_t nseeds,
+                       double alpha, double eps, int32_t rule, uint64_t* id,
+                       plc_result_info* info);
+
+/*
  * Batched path.  Many queries advance together: every global step runs one
  * PR-Nibble round for all admitted queries in the same kernel launches, and
  * the queries whose frontier emptied are swept together.  Results are the

@@ -35,7 +35,8 @@ PLC_STATE_COMPACT = 1
 
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
-           "plc_graph_info_get", "plc_run", "plc_result_info_get", "plc_result_copy",
+           "plc_graph_info_get", "plc_run", "plc_run_set", "plc_result_info_get",
+           "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
            "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_wait",
            "plc_query_bytes_estimate", "plc_run_batched", "plc_autotune")
@@ -120,6 +121,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "plc_graph_info_get": ([P, C.POINTER(plc_graph_info)], I32),
         "plc_run": ([P, P, C.POINTER(plc_query), I32, C.POINTER(U64),
                      C.POINTER(plc_result_info)], I32),
+        "plc_run_set": ([P, P, P, I32, C.c_double, C.c_double, I32, C.POINTER(U64),
+                         C.POINTER(plc_result_info)], I32),
         "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
         "plc_result_copy": ([P, U64, P, P, P, P], I32),
         "plc_release": ([P, U64], I32),
@@ -288,6 +291,18 @@ class Context:
         if check and rc not in (PLC_OK,):
             raise PlcError(rc, "plc_run")
         return list(ids), [x.as_dict() for x in infos]
+
+    def run_set(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+        """Plain path from a seed set (unit mass split equally over the
+        distinct seeds).  Returns (id, info)."""
+        sv = np.ascontiguousarray(np.atleast_1d(np.asarray(seeds)), dtype=np.int32)
+        qid = C.c_uint64()
+        info = plc_result_info()
+        rc = self.lib.plc_run_set(self.handle, g.handle, _ptr(sv), len(sv), float(alpha),
+                                  float(eps), int(rule), C.byref(qid), C.byref(info))
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_run_set")
+        return qid.value, info.as_dict()
 
     # ---- batched path
     def batch_reserve(self, g: Graph, slots: int) -> int:

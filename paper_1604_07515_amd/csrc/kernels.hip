@@ -93,6 +93,58 @@ __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alp
   c->status = ST_PUSH;
 }
 
+// Seed-set initialisation (Sec. 3: a set S of seeds): the host has placed
+// the distinct seeds in the first frontier; each gets r = 1/|S| and is
+// listed as touched.  Block 0 also sets up the control block.
+__global__ void k_query_init_set(PlainArgs a, int32_t nseeds, int32_t rule, double alpha,
+                                 double eps, int32_t max_rounds) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctl* c = a.ctl;
+    if (rule == 1) {  // original rule
+      c->cs = alpha;
+      c->cn = (1.0 - alpha) / 2.0;
+      c->keep = (1.0 - alpha) / 2.0;
+      c->opt_rule = 0;
+    } else {          // optimized rule
+      c->cs = 2.0 * alpha / (1.0 + alpha);
+      c->cn = (1.0 - alpha) / (1.0 + alpha);
+      c->keep = 0.0;
+      c->opt_rule = 1;
+    }
+    c->eps = eps;
+    c->seed = a.fbuf0[0];
+    c->rule = rule;
+    c->max_rounds = max_rounds;
+    c->round = 0;
+    c->cnt[0] = nseeds;
+    c->cnt[1] = 0;
+    c->ntiles = 0;
+    c->etotal = 0;
+    c->pushes = 0;
+    c->edges = 0;
+    c->support_cnt = 0;
+    c->touched_cnt = nseeds;
+    c->fault = 0;
+    c->limited = 0;
+    c->N = 0;
+    c->sort_flip = 0;
+    c->rnnz = 0;
+    c->vol_total = a.vol_total;
+    c->best_cut = 0;
+    c->best_vol = 0;
+    c->best_den = 0;
+    c->kstar = 0;
+    c->phi = 0.0;
+    c->status = ST_PUSH;
+  }
+  const double share = 1.0 / (double)nseeds;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nseeds; i += gridDim.x * blockDim.x) {
+    const int32_t v = a.fbuf0[i];
+    a.touched[i] = v;
+    a.vr[v].r = share;
+  }
+}
+
 // ---------------------------------------------------------------- round
 
 __device__ __forceinline__ bool push_active(const Ctl* c, int64_t ncap, int* t_out, int* nf_out) {
@@ -648,6 +700,15 @@ hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a) {
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
                              double alpha, double eps, int32_t max_rounds) {
   hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, a, seed, rule, alpha, eps,
+                     max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nseeds, int32_t rule,
+                                 double alpha, double eps, int32_t max_rounds) {
+  int grid = (nseeds + kBlock - 1) / kBlock;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(k_query_init_set, dim3(grid), dim3(kBlock), 0, s, a, nseeds, rule, alpha, eps,
                      max_rounds);
   return hipGetLastError();
 }

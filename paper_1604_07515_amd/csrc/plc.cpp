@@ -578,12 +578,21 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
   return hipSuccess;
 }
 
+// One plain query: from q.seed, or, with set non-null, from the nset
+// distinct seeds in set (q.seed is then ignored).
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
-                          plc_result_info* info_out) {
+                          plc_result_info* info_out, const int32_t* set = nullptr,
+                          int32_t nset = 0) {
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
-  HIPCHK(ctx, plc::launch_query_init(s, a, q.seed, (int32_t)q.rule, q.alpha, q.eps,
-                                     ctx->opt.max_rounds));
+  if (set) {
+    HIPCHK(ctx, hipMemcpyAsync(a.fbuf0, set, 4 * (size_t)nset, hipMemcpyHostToDevice, s));
+    HIPCHK(ctx, plc::launch_query_init_set(s, a, nset, (int32_t)q.rule, q.alpha, q.eps,
+                                           ctx->opt.max_rounds));
+  } else {
+    HIPCHK(ctx, plc::launch_query_init(s, a, q.seed, (int32_t)q.rule, q.alpha, q.eps,
+                                       ctx->opt.max_rounds));
+  }
   // Push: chunks of rounds, each followed by a read-back of the control
   // block.  Rounds queued past the end of the push exit at once but still
   // cost a dispatch each, so the first chunk is the lower quartile of the
@@ -742,6 +751,33 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
     return PLC_E_HIP;
   }
   return first;
+}
+
+extern "C" plc_status plc_run_set(plc_ctx* ctx, plc_graph* g, const int32_t* seeds,
+                                  int32_t nseeds, double alpha, double eps, int32_t rule,
+                                  uint64_t* id, plc_result_info* info) {
+  if (!ctx || !g || !ctx->graphs.count(g) || !seeds || nseeds < 1) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  plc_query q{};
+  q.seed = seeds[0];
+  q.alpha = alpha;
+  q.eps = eps;
+  q.rule = rule;
+  std::vector<int32_t> set(seeds, seeds + nseeds);
+  for (int32_t v : set) {
+    q.seed = v;
+    if (!query_ok(g, q)) return PLC_E_INVALID;
+  }
+  std::sort(set.begin(), set.end());
+  set.erase(std::unique(set.begin(), set.end()), set.end());
+  (void)hipSetDevice(ctx->device);
+  plc_status st = run_one(ctx, g, q, id, info, set.data(), (int32_t)set.size());
+  if (st == PLC_E_HIP) return st;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  return st;
 }
 
 extern "C" plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out) {

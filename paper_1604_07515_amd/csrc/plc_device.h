@@ -135,6 +135,9 @@ static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
                              double alpha, double eps, int32_t max_rounds);
+// seed set: the nseeds distinct seeds are already in a.fbuf0
+hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nseeds, int32_t rule,
+                                 double alpha, double eps, int32_t max_rounds);
 // With t0 set, the kernel is launched with start and stop events that take
 // its own dispatch timestamps (hipExtLaunchKernelGGL); not for graph capture.
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,

@@ -226,3 +226,43 @@ def test_result_block_does_not_fit(plc):
         for _ in range(2):
             ids2, _ = c.run(hg, [small], 0.05, 0.5, OPT)
             check_query(g, c.result(ids2[0], release=True), small, 0.05, 0.5, OPT)
+
+
+@pytest.mark.parametrize("rule", [OPT, ORIG])
+@pytest.mark.parametrize("kind", ["pair", "seven_with_repeats", "wide"])
+def test_seed_sets(ctx, plc, rule, kind):
+    """plc_run_set against the oracle's seed-set PR-Nibble (unit mass split
+    equally over the distinct seeds); the wide set spans several init and
+    frontier-scan blocks."""
+    g, hg = graph(ctx, "rmat13")
+    rng = np.random.default_rng({"pair": 1, "seven_with_repeats": 2, "wide": 3}[kind])
+    cand = np.flatnonzero(g.deg > 0)
+    k = {"pair": 2, "seven_with_repeats": 7, "wide": 1500}[kind]
+    seeds = rng.choice(cand, k, replace=False).astype(np.int32)
+    if kind == "seven_with_repeats":
+        seeds = np.concatenate([seeds, seeds[:3]])
+    eps = 1e-6 if kind != "wide" else 1e-5
+    say("case seed set", kind, "rule", rule, "size", len(seeds))
+    qid, info = ctx.run_set(hg, seeds, 0.01, eps, rule)
+    orc = oracle.prnibble(g.off, g.nbr, seeds, 0.01, eps, rule)
+    check_query(g, ctx.result(qid, release=True), int(seeds[0]), 0.01, eps, rule, orc=orc)
+
+
+def test_seed_set_of_one_is_a_plain_query(ctx, plc):
+    g, hg = graph(ctx, "rmat13")
+    x = int(np.flatnonzero(g.deg > 2)[7])
+    qid, _ = ctx.run_set(hg, [x, x], 0.01, 1e-6)
+    ids, _ = ctx.run(hg, [x], 0.01, 1e-6)
+    check_same(g, ctx.result(qid, release=True), ctx.result(ids[0], release=True))
+
+
+def test_seed_set_rejects_bad_input(ctx, plc):
+    g, hg = graph(ctx, "rmat13")
+    for bad in ([], [g.n], [0, -1]):
+        with pytest.raises(plc.PlcError) as e:
+            ctx.run_set(hg, np.asarray(bad, dtype=np.int32), 0.01, 1e-6)
+        assert e.value.code == plc.PLC_E_INVALID
+    iso = np.flatnonzero(g.deg == 0)
+    if len(iso):
+        with pytest.raises(plc.PlcError):
+            ctx.run_set(hg, [int(iso[0])], 0.01, 1e-6)

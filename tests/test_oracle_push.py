@@ -252,3 +252,32 @@ def test_invalid_inputs():
             oracle.prnibble(g.off, g.nbr, 0, 0.01, e)
     with pytest.raises(ValueError):
         oracle.prnibble(g.off, g.nbr, 7, 0.01, 1e-4)
+
+
+@pytest.mark.parametrize("rule", [OPT, ORIG])
+def test_seed_set_exact_identity(rule):
+    """Seed sets (Sec. 3): with the unit mass split equally over the distinct
+    seeds, p = R (chi_S / |S| - r) holds exactly (dense solve), mass is
+    conserved, and a repeated seed counts once."""
+    g = synth.rmat(7, 6, seed=12)
+    lab = synth.components(g)
+    x = pick_seed(g, 5)
+    idx = np.flatnonzero(lab == lab[x])
+    sub = synth.from_edges(len(idx), [(int(np.searchsorted(idx, v)), int(np.searchsorted(idx, w)))
+                                      for v in idx for w in g.neighbors(v) if v < w])
+    seeds = [0, len(idx) // 2, len(idx) - 1]
+    alpha = 0.03
+    res = oracle.prnibble(sub.off, sub.nbr, seeds + [seeds[0]], alpha, 1e-7, rule)
+    n = sub.n
+    A = np.zeros((n, n))
+    for v in range(n):
+        A[sub.neighbors(v), v] = 1.0
+    ap = 2 * alpha / (1 + alpha)
+    M = np.eye(n) - (1 - ap) * A / np.maximum(sub.deg, 1)[None, :]
+    chi = np.zeros(n)
+    chi[seeds] = 1.0 / 3.0
+    p_exact = np.linalg.solve(M, ap * (chi - res.r))
+    assert np.max(np.abs(res.p - p_exact)) <= 1e-12 * np.max(p_exact)
+    assert abs(res.p.sum() + res.r.sum() - 1.0) < 1e-12
+    again = oracle.prnibble(sub.off, sub.nbr, seeds, alpha, 1e-7, rule)
+    assert np.array_equal(again.p, res.p) and np.array_equal(again.r, res.r)
