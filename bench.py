@@ -297,6 +297,46 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
             "roofline": roofline(tm, "k_b_scatter<CompactState>")}
 
 
+def bench_rules(plc, synth, g, seeds):
+    """The paper's comparison of the two push rules (Sec. 3.3, "An
+    Optimization": the optimized rule reaches the same conductance with less
+    work): the 16 plain seeds under each rule, one warm pass, then one timed
+    pass each."""
+    import numpy as np
+    import torch
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+    ctx.autotune(hg, seeds[:4], 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
+    out = {}
+    for name, rule in (("optimized", plc.PLC_RULE_OPT), ("original", plc.PLC_RULE_ORIG)):
+        for timed in (False, True):
+            rows = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for x in seeds:
+                ids, infos = ctx.run(hg, [int(x)], 0.01, 1e-7, rule)
+                ctx.release(ids[0])
+                rows.append(infos[0])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        out[name] = {"ms_per_query": el * 1e3 / len(seeds),
+                     "pushes_per_query": float(np.mean([r["pushes"] for r in rows])),
+                     "edges_per_query": float(np.mean([r["edges"] for r in rows])),
+                     "rounds_per_query": float(np.mean([r["rounds"] for r in rows])),
+                     "phi": [r["phi"] for r in rows]}
+    ctx.close()
+    po, pr = np.array(out["optimized"]["phi"]), np.array(out["original"]["phi"])
+    return {"workload": "rmat22_ef16_plain_16seeds", "alpha": 0.01, "eps": 1e-7,
+            "optimized": {k: v for k, v in out["optimized"].items() if k != "phi"},
+            "original": {k: v for k, v in out["original"].items() if k != "phi"},
+            "speedup_optimized": out["original"]["ms_per_query"] / out["optimized"]["ms_per_query"],
+            "push_ratio": out["original"]["pushes_per_query"] / out["optimized"]["pushes_per_query"],
+            "phi_optimized_over_original": {"median": float(np.median(po / pr)),
+                                            "min": float(np.min(po / pr)),
+                                            "max": float(np.max(po / pr))},
+            "paper": "sequential, optimized rule 1.4-6.4x faster at the same conductance"}
+
+
 def bench_grid3d(plc, synth, side=215, nq=8):
     """The paper's 3D-grid input (a side^3 torus, every vertex of degree 6;
     side 215 gives its n = 9,938,375 and 3n edges): one PR-Nibble + sweep at a
@@ -440,6 +480,11 @@ def main():
             bat_c["edges_per_s"], bat_c["queries_per_s"]))
     srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries, args.serve_slots,
                          compact=args.serve_state == "compact") if want("serving") else None)
+    rules = bench_rules(plc, synth, g, plain["seeds"]) if plain else None
+    if rules:
+        log("rules: optimized %.2f ms/query, original %.2f ms/query (%.2fx), pushes x%.2f" % (
+            rules["optimized"]["ms_per_query"], rules["original"]["ms_per_query"],
+            rules["speedup_optimized"], rules["push_ratio"]))
     grid = bench_grid3d(plc, synth) if want("grid3d") else None
     if grid:
         log("grid3d: %.2f ms per query (%.0fx the paper's 40-core time)" % (
@@ -485,6 +530,8 @@ def main():
         out["large"] = big
     if grid:
         out["grid3d"] = grid
+    if rules:
+        out["rules"] = rules
     if srv:
         out["serving"] = srv
     work = []
