@@ -52,6 +52,11 @@ class _SweepResult(C.Structure):
                 ("vol_total", C.c_int64)]
 
 
+class _HkStats(C.Structure):
+    _fields_ = [("levels", C.c_int64), ("pushes", C.c_int64), ("edges", C.c_int64),
+                ("support", C.c_int64), ("min_rel_gap", C.c_double)]
+
+
 _lib = None
 
 
@@ -74,6 +79,10 @@ def _load():
         lib.oracle_sweep_bruteforce.restype = C.c_int
         lib.oracle_sweep_z.argtypes = [C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]
         lib.oracle_sweep_z.restype = C.c_int
+        for fn in (lib.oracle_hkpr, lib.oracle_hkpr_queue):
+            fn.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int32, C.c_double, C.c_double, P,
+                           C.POINTER(_HkStats)]
+            fn.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -208,3 +217,34 @@ def sweep_z(off, nbr, order):
     Zs = np.stack([zfs[:ln], zss[:ln]], 1)
     Zsum = np.stack([zsum[:ln], zss[:ln]], 1)
     return Z, Zs, Zsum, cut[:N].copy()
+
+
+@dataclass
+class HkResult:
+    p: np.ndarray          # dense float64, length n
+    levels: int            # levels processed (the last pushes into p)
+    pushes: int            # (vertex, level) entries processed
+    edges: int             # sum of d(v) over processed entries
+    support: int
+    min_rel_gap: float     # closest approach of a threshold decision to its threshold
+
+
+def _hk(fn, off, nbr, seed, N, eps, t) -> HkResult:
+    off, nbr, n = _csr(off, nbr)
+    p = np.zeros(n, np.float64)
+    st = _HkStats()
+    rc = fn(n, _ptr(off), _ptr(nbr), int(seed), int(N), float(eps), float(t), _ptr(p), C.byref(st))
+    if rc < 0:
+        raise ValueError("HK-PR oracle rejected its input (code %d)" % rc)
+    return HkResult(p, st.levels, st.pushes, st.edges, st.support, st.min_rel_gap)
+
+
+def hkpr(off, nbr, seed, N: int, eps: float, t: float) -> HkResult:
+    """Deterministic HK-PR, level-synchronous (Sec. 3.4, Fig. alg:hkpr)."""
+    return _hk(_load().oracle_hkpr, off, nbr, seed, N, eps, t)
+
+
+def hkpr_queue(off, nbr, seed, N: int, eps: float, t: float) -> HkResult:
+    """Deterministic HK-PR, the sequential queue procedure of Sec. 3.4
+    (dense (N+1) x n residual table: small graphs only)."""
+    return _hk(_load().oracle_hkpr_queue, off, nbr, seed, N, eps, t)

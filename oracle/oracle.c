@@ -356,3 +356,187 @@ int oracle_sweep_z(int64_t n, const int64_t* off, const int32_t* nbr, const int3
   free(cnt); free(rank);
   return (int)len;
 }
+
+/* ------------------------------------------------------------------------
+ * Deterministic heat-kernel PageRank, HK-PR (Sec. 3.4, the Kloster-Gleich
+ * procedure and Fig. alg:hkpr).  Parameters: seed x, Taylor degree N >= 1,
+ * eps > 0, t > 0.
+ *
+ *   psi_k = sum_{m=0}^{N-k} k!/(m+k)! t^m  (k = 0..N), accumulated term by
+ *           term with term_0 = 1, term_m = term_{m-1} * t / (k + m);
+ *   threshold at level k for vertex w:  ((e^{-t} * eps) * d(w)) / (2 * N * psi_k);
+ *   an entry (v, j) that is processed adds r to p[v]; for j + 1 < N each
+ *   neighbour w gets t * r / ((j + 1) d(v)) at level j + 1, and (w, j + 1) is
+ *   processed once its residual reaches the level-(j+1) threshold; for
+ *   j + 1 == N each neighbour w gets r / d(v) added to p[w] directly.
+ *
+ * Readings: the pseudocode's loop test "j+1 == N" and its e^{t} contradict
+ * the text; the text's "j+1 < N" and e^{-t} are taken.  Threshold and
+ * crossing test are inclusive (>=), as for PR-Nibble.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t levels;      /* levels processed (the last one pushes into p) */
+  int64_t pushes;      /* entries processed */
+  int64_t edges;       /* sum of d(v) over processed entries */
+  int64_t support;     /* vertices with p > 0 */
+  double min_rel_gap;  /* closest approach of a threshold decision to its threshold */
+} oracle_hk_stats;
+
+static void hk_psi(int32_t N, double t, double* psi) {
+  for (int32_t k = 0; k <= N; k++) {
+    double term = 1.0, s = 1.0;
+    for (int32_t m = 1; m <= N - k; m++) {
+      term = term * t / (double)(k + m);
+      s += term;
+    }
+    psi[k] = s;
+  }
+}
+
+static double hk_thr(double et_eps, int64_t d, int32_t N, double psi_k) {
+  return (et_eps * (double)d) / (2.0 * (double)N * psi_k);
+}
+
+static void hk_gap(oracle_hk_stats* st, double r, double thr) {
+  const double g = fabs(r - thr) / thr;
+  if (g < st->min_rel_gap) st->min_rel_gap = g;
+}
+
+/*
+ * Level-synchronous HK-PR (Fig. alg:hkpr, with the readings above): the
+ * frontier of level j pushes; r holds level j (on the vertices that level
+ * touched), rn collects level j + 1 with every contribution added (the
+ * fetch-and-add of the figure, here in edge order); the next frontier is
+ * every vertex whose level-(j+1) residual reached its threshold, and level
+ * j's residuals, pushed or not, are dropped.  p dense, length n,
+ * overwritten.
+ */
+int oracle_hkpr(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x, int32_t N,
+                double eps, double t, double* p, oracle_hk_stats* st) {
+  if (n <= 0 || !off || !nbr || !p || !st || N < 1) return ORACLE_E_INVALID;
+  if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
+  if (!(eps >= 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
+  double* psi = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* r = (double*)calloc((size_t)n, sizeof(double));
+  double* rn = (double*)calloc((size_t)n, sizeof(double));
+  int32_t* F = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);   /* frontier of level j */
+  int32_t* T = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);   /* touched at level j */
+  int32_t* G = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);   /* touched at level j + 1 */
+  uint8_t* mark = (uint8_t*)calloc((size_t)n, 1);
+  if (!psi || !r || !rn || !F || !T || !G || !mark) {
+    free(psi); free(r); free(rn); free(F); free(T); free(G); free(mark);
+    return ORACLE_E_NOMEM;
+  }
+  hk_psi(N, t, psi);
+  const double et_eps = exp(-t) * eps;
+  memset(st, 0, sizeof(*st));
+  st->min_rel_gap = INFINITY;
+  for (int64_t v = 0; v < n; v++) p[v] = 0.0;
+  r[x] = 1.0;
+  int64_t nf = 1, nt = 1;
+  F[0] = x;
+  T[0] = x;
+  for (int32_t j = 0; nf > 0; j++) {
+    st->levels++;
+    /* vertexMap(Frontier, UpdateSelf) */
+    for (int64_t i = 0; i < nf; i++) p[F[i]] += r[F[i]];
+    st->pushes += nf;
+    if (j + 1 == N) {  /* last level: edgeMap with UpdateNghLast */
+      for (int64_t i = 0; i < nf; i++) {
+        const int32_t v = F[i];
+        const int64_t d = deg_of(off, v);
+        st->edges += d;
+        const double c = r[v] / (double)d;
+        for (int64_t e = off[v]; e < off[v + 1]; e++) p[nbr[e]] += c;
+      }
+      break;
+    }
+    /* edgeMap(G, Frontier, UpdateNgh) into rn */
+    int64_t ng = 0;
+    for (int64_t i = 0; i < nf; i++) {
+      const int32_t v = F[i];
+      const int64_t d = deg_of(off, v);
+      st->edges += d;
+      const double c = (t * r[v]) / ((double)(j + 1) * (double)d);
+      for (int64_t e = off[v]; e < off[v + 1]; e++) {
+        const int32_t w = nbr[e];
+        rn[w] += c;
+        if (!mark[w]) { mark[w] = 1; G[ng++] = w; }
+      }
+    }
+    /* drop level j, move level j + 1 into r, filter the next frontier */
+    for (int64_t i = 0; i < nt; i++) r[T[i]] = 0.0;
+    nf = 0;
+    for (int64_t i = 0; i < ng; i++) {
+      const int32_t w = G[i];
+      mark[w] = 0;
+      r[w] = rn[w];
+      rn[w] = 0.0;
+      const double thr = hk_thr(et_eps, deg_of(off, w), N, psi[j + 1]);
+      hk_gap(st, r[w], thr);
+      if (r[w] >= thr) F[nf++] = w;
+    }
+    qsort(F, (size_t)nf, sizeof(int32_t), cmp_i32);
+    int32_t* tmp = T; T = G; G = tmp;
+    nt = ng;
+  }
+  for (int64_t v = 0; v < n; v++) st->support += p[v] > 0.0;
+  free(psi); free(r); free(rn); free(F); free(T); free(G); free(mark);
+  return ORACLE_OK;
+}
+
+/*
+ * The sequential procedure of Sec. 3.4 as printed there, for small graphs:
+ * residuals keyed by (v, j) in a dense (N + 1) x n table, a FIFO queue of
+ * entries; an entry is queued when an update makes its residual cross its
+ * level's threshold (r < thr and r + M >= thr), and processing (v, j) adds
+ * r[(v, j)] to p[v] and pushes to the neighbours.  An independent second
+ * formulation to pin oracle_hkpr against.
+ */
+int oracle_hkpr_queue(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x, int32_t N,
+                      double eps, double t, double* p, oracle_hk_stats* st) {
+  if (n <= 0 || !off || !nbr || !p || !st || N < 1) return ORACLE_E_INVALID;
+  if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
+  if (!(eps >= 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
+  const size_t cells = (size_t)(N + 1) * (size_t)n;
+  double* psi = (double*)malloc(sizeof(double) * (size_t)(N + 1));
+  double* r = (double*)calloc(cells, sizeof(double));
+  int64_t* qv = (int64_t*)malloc(sizeof(int64_t) * (cells + 1));   /* queued cells */
+  if (!psi || !r || !qv) { free(psi); free(r); free(qv); return ORACLE_E_NOMEM; }
+  hk_psi(N, t, psi);
+  const double et_eps = exp(-t) * eps;
+  memset(st, 0, sizeof(*st));
+  st->min_rel_gap = INFINITY;
+  for (int64_t v = 0; v < n; v++) p[v] = 0.0;
+  int64_t head = 0, tail = 0;
+  r[x] = 1.0;               /* cell (x, 0) */
+  qv[tail++] = x;
+  int64_t last_level = -1;
+  while (head < tail) {
+    const int64_t cell = qv[head++];
+    const int32_t j = (int32_t)(cell / n);
+    const int32_t v = (int32_t)(cell % n);
+    if (j != last_level) { st->levels++; last_level = j; }
+    const double rv = r[cell];
+    const int64_t d = deg_of(off, v);
+    st->pushes++;
+    st->edges += d;
+    p[v] += rv;
+    const double M = (t * rv) / ((double)(j + 1) * (double)d);
+    for (int64_t e = off[v]; e < off[v + 1]; e++) {
+      const int32_t w = nbr[e];
+      if (j + 1 == N) {
+        p[w] += rv / (double)d;
+      } else {
+        const int64_t cw = (int64_t)(j + 1) * n + w;
+        const double thr = hk_thr(et_eps, deg_of(off, w), N, psi[j + 1]);
+        if (r[cw] < thr && r[cw] + M >= thr) qv[tail++] = cw;
+        r[cw] += M;
+      }
+    }
+  }
+  for (int64_t v = 0; v < n; v++) st->support += p[v] > 0.0;
+  free(psi); free(r); free(qv);
+  return ORACLE_OK;
+}
