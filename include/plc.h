@@ -193,6 +193,27 @@ plc_status plc_run_set(plc_ctx* ctx, plc_graph* g, const int32_t* seeds, int32_t
                        plc_result_info* info);
 
 /*
+ * Plain path, deterministic heat-kernel PageRank from seed x (Sec. 3.4,
+ * the Kloster-Gleich procedure and Fig. alg:hkpr) followed by the sweep cut.
+ * Level j = 0 .. N-1 is one synchronous round: every frontier vertex v adds
+ * its level-j residual r to p[v]; for j + 1 < N each neighbour w gets
+ * t r / ((j + 1) d(v)) at level j + 1, and the next frontier is every w whose
+ * level-(j+1) residual reached ((e^-t eps) d(w)) / (2 N psi_{j+1}), with
+ * psi_k = sum_{m=0}^{N-k} k!/(m+k)! t^m; on the last level (j + 1 = N) each
+ * neighbour gets r / d(v) added to p directly.  Level-j residuals that never
+ * reach the threshold are dropped.  Readings: the pseudocode's loop test
+ * "j+1 == N" and its e^{t} contradict the text; the text's "j+1 < N" and
+ * e^{-t} are taken.  N in [1, 1024], eps > 0 (at eps = 0 the printed
+ * crossing test could never hold), t > 0.  Blocks until done.  *info: rounds = levels run, pushes = (vertex,
+ * level) entries processed, edges = their degrees, support, the cluster;
+ * no residual is reported (r_nnz = 0).  Errors: PLC_E_INVALID (bad seed,
+ * N, eps or t; nothing runs), PLC_E_NOMEM (no room for the result: the
+ * counters are still in *info), PLC_E_HIP.
+ */
+plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int32_t N, double eps,
+                        double t, uint64_t* id, plc_result_info* info);
+
+/*
  * Batched path.  Many queries advance together: every global step runs one
  * PR-Nibble round for all admitted queries in the same kernel launches, and
  * the queries whose frontier emptied are swept together.  Results are the

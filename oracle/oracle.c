@@ -372,7 +372,10 @@ int oracle_sweep_z(int64_t n, const int64_t* off, const int32_t* nbr, const int3
  *
  * Readings: the pseudocode's loop test "j+1 == N" and its e^{t} contradict
  * the text; the text's "j+1 < N" and e^{-t} are taken.  Threshold and
- * crossing test are inclusive (>=), as for PR-Nibble.
+ * crossing test are inclusive (>=), as for PR-Nibble.  eps > 0: at eps = 0
+ * the printed crossing test (r < thr before the update) can never hold and
+ * the sequential procedure would stop at the seed, while the filter of the
+ * figure would push every touched entry; the two agree for every eps > 0.
  * ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -416,7 +419,7 @@ int oracle_hkpr(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x, in
                 double eps, double t, double* p, oracle_hk_stats* st) {
   if (n <= 0 || !off || !nbr || !p || !st || N < 1) return ORACLE_E_INVALID;
   if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
-  if (!(eps >= 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
+  if (!(eps > 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
   double* psi = (double*)malloc(sizeof(double) * (size_t)(N + 1));
   double* r = (double*)calloc((size_t)n, sizeof(double));
   double* rn = (double*)calloc((size_t)n, sizeof(double));
@@ -498,7 +501,7 @@ int oracle_hkpr_queue(int64_t n, const int64_t* off, const int32_t* nbr, int32_t
                       double eps, double t, double* p, oracle_hk_stats* st) {
   if (n <= 0 || !off || !nbr || !p || !st || N < 1) return ORACLE_E_INVALID;
   if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
-  if (!(eps >= 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
+  if (!(eps > 0.0) || !isfinite(eps) || !(t > 0.0) || !isfinite(t)) return ORACLE_E_INVALID;
   const size_t cells = (size_t)(N + 1) * (size_t)n;
   double* psi = (double*)malloc(sizeof(double) * (size_t)(N + 1));
   double* r = (double*)calloc(cells, sizeof(double));

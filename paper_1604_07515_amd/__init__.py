@@ -35,7 +35,7 @@ PLC_STATE_COMPACT = 1
 
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
-           "plc_graph_info_get", "plc_run", "plc_run_set", "plc_result_info_get",
+           "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_result_info_get",
            "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
            "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_wait",
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                      C.POINTER(plc_result_info)], I32),
         "plc_run_set": ([P, P, P, I32, C.c_double, C.c_double, I32, C.POINTER(U64),
                          C.POINTER(plc_result_info)], I32),
+        "plc_run_hkpr": ([P, P, I32, I32, C.c_double, C.c_double, C.POINTER(U64),
+                          C.POINTER(plc_result_info)], I32),
         "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
         "plc_result_copy": ([P, U64, P, P, P, P], I32),
         "plc_release": ([P, U64], I32),
@@ -304,6 +306,17 @@ class Context:
             raise PlcError(rc, "plc_run_set")
         return qid.value, info.as_dict()
 
+    def run_hkpr(self, g: Graph, seed: int, N: int, eps: float, t: float, check: bool = True):
+        """Plain path: deterministic heat-kernel PageRank (Taylor degree N)
+        from seed, then the sweep cut.  Returns (id, info)."""
+        qid = C.c_uint64()
+        info = plc_result_info()
+        rc = self.lib.plc_run_hkpr(self.handle, g.handle, int(seed), int(N), float(eps), float(t),
+                                   C.byref(qid), C.byref(info))
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_run_hkpr")
+        return qid.value, info.as_dict()
+
     # ---- batched path
     def batch_reserve(self, g: Graph, slots: int) -> int:
         got = C.c_int32()
@@ -427,8 +440,8 @@ def batch_arena_bytes(n: int, arcs: int, slots: int, compact: bool = False,
 
 def plain_arena_bytes(n: int, arcs: int) -> int:
     """Arena bytes the plain path needs for one graph, plus 64 MiB for results."""
-    per_vertex = 152          # offsets, state records, frontier, sweep buffers
+    per_vertex = 168          # offsets, state records, frontier, sweep and HK-PR buffers
     per_arc = 4               # neighbour ids
     tiles = 4 * (arcs // 1024 + 2)
     scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
-    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20))
+    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20) + 8 * 1025)

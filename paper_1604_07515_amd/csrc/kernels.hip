@@ -44,6 +44,7 @@ __global__ void k_graph_init(PlainArgs a) {
     rec.rank = 0;
     a.vr[v] = rec;
     a.p[v] = 0.0;
+    a.hk_r1[v] = 0.0;
   }
 }
 
@@ -168,12 +169,35 @@ __device__ __forceinline__ void mark_tiles(int32_t* tile_start, int64_t cap, lon
   for (long long tt = t0; tt <= t1; tt++) tile_start[tt] = i;
 }
 
+// HK-PR residual of vertex v at level k: even levels in the state record,
+// odd levels in hk_r1.
+__device__ __forceinline__ double* hk_res(const PlainArgs& a, int k, int32_t v) {
+  return (k & 1) ? &a.hk_r1[v] : &a.vr[v].r;
+}
+
 // vertexMap(Frontier, UpdateSelf) + degree scan of the frontier.
-__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
+//   PR-Nibble (Figs. alg:pr-nibble / alg:pr-nibble2): p += cs rho, r =
+//     keep rho (-0.0 under the optimized rule), coefficient cn rho / d.
+//   HK-PR level j (Fig. alg:hkpr): p += rho; coefficient t rho / ((j+1) d),
+//     or rho / d on the last level; first, the residuals of level j - 1
+//     (the array level j + 1 fills) are cleared over the vertices that
+//     level touched.
+template <bool HK>
+__device__ __forceinline__ void self_body(const PlainArgs& a) {
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
-  if (t >= c->max_rounds) {
+  if (HK) {
+    if (t >= c->hk_N) return;  // (the last level leaves no frontier)
+    if (t >= 1) {
+      const int lp = (t + 2) % 3;
+      const int np = c->hk_tlc[lp];
+      const int32_t* Lp = a.hk_tl[lp];
+      for (int i = blockIdx.x * kBlock + threadIdx.x; i < np; i += gridDim.x * kBlock)
+        *hk_res(a, t + 1, Lp[i]) = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->hk_tlc[(t + 1) % 3] = 0;
+  } else if (t >= c->max_rounds) {
     if (blockIdx.x == 0 && threadIdx.x == 0) { c->limited = 1; c->status = ST_LIMIT; }
     return;
   }
@@ -181,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
   __shared__ long long s_excl;
   __shared__ int s_tk[2];
   __shared__ int32_t s_sup[kScanBlock];
-  __shared__ int32_t s_stay[kScanBlock];
+  __shared__ int32_t s_stay[HK ? 1 : kScanBlock];
   __shared__ int s_nsup, s_nstay, s_base;
   ScanSite* site = &c->scan[SCAN_FRONTIER];
   scan_clear_prev(site, a.desc[SCAN_FRONTIER], a.desc_cap);
@@ -190,7 +214,9 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
   const double cs = c->cs, cn = c->cn, keep = c->keep, eps = c->eps;
-  const bool opt = c->opt_rule != 0;
+  const bool opt = HK || c->opt_rule != 0;
+  const bool hk_last = HK && t + 1 == c->hk_N;
+  const double hk_t = HK ? c->hk_t : 0.0;
   const int nblk = (nf + kScanBlock - 1) / kScanBlock;
   if (threadIdx.x == 0) { s_nsup = 0; s_nstay = 0; }
   __syncthreads();
@@ -210,17 +236,28 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
       int32_t d = 0;
       if (i < nf) {
         int32_t v = F[i];
-        VRec rec = a.vr[v];
-        double rho = rec.r;
-        d = rec.deg;
+        double rho;
+        if (HK) {
+          rho = *hk_res(a, t, v);
+          d = a.vr[v].deg;
+        } else {
+          VRec rec = a.vr[v];
+          rho = rec.r;
+          d = rec.deg;
+        }
         double pold = a.p[v];
-        a.p[v] = pold + cs * rho;
-        double nr = opt ? -0.0 : keep * rho;
-        a.vr[v].r = nr;
-        a.coef[i] = (cn * rho) / (double)d;
+        if (HK) {
+          a.p[v] = pold + rho;
+          a.coef[i] = hk_last ? rho / (double)d : (hk_t * rho) / ((double)(t + 1) * (double)d);
+        } else {
+          a.p[v] = pold + cs * rho;
+          double nr = opt ? -0.0 : keep * rho;
+          a.vr[v].r = nr;
+          a.coef[i] = (cn * rho) / (double)d;
+          if (!opt && nr >= eps * (double)d) s_stay[atomicAdd(&s_nstay, 1)] = v;
+        }
         a.rowp[i] = a.off[v];
         if (pold == 0.0) s_sup[atomicAdd(&s_nsup, 1)] = v;
-        if (!opt && nr >= eps * (double)d) s_stay[atomicAdd(&s_nstay, 1)] = v;
       }
       dk[k] = d;
       dsum += d;
@@ -252,6 +289,9 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) { self_body<false>(a); }
+__global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<true>(a); }
+
 // Threshold decision for one addition of c to r[w] that returned `old`:
 // crossing appends w to the next frontier, first touch to the touched list.
 __device__ __forceinline__ void decide(double old, double c, double thr, int32_t w, int32_t* s_fn,
@@ -266,11 +306,17 @@ __device__ __forceinline__ void decide(double old, double c, double thr, int32_t
 // highest-degree destinations in LDS, as the batched scatter does, measured
 // slower here: one query's round spreads over few workgroups, and the
 // per-workgroup clear and flush cost more than the contention they save.)
-__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
+//   PR-Nibble: into r, threshold eps d(w), first touches to the touched list.
+//   HK-PR level j: into the level-(j+1) residuals, threshold
+//     ((e^-t eps) d(w)) / (2 N psi_{j+1}), first touches to level j+1's list;
+//     on the last level into p (UpdateNghLast), first touches of p to the
+//     support list, no frontier.
+template <bool HK>
+__device__ __forceinline__ void scatter_body(const PlainArgs& a) {
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
-  if (t >= c->max_rounds) return;
+  if (HK ? t >= c->hk_N : t >= c->max_rounds) return;
   __shared__ int32_t s_start[kEdgeTile + 1];
   __shared__ int64_t s_row[kEdgeTile + 1];
   __shared__ double s_coef[kEdgeTile + 1];
@@ -279,9 +325,14 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
   __shared__ int s_nfn, s_ntv, s_base, s_last;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->etotal;
-  const double eps = c->eps;
+  const bool hk_last = HK && t + 1 == c->hk_N;
+  const double eps = HK ? c->hk_A : c->eps;                   // threshold numerator factor
+  const double den = HK && !hk_last ? a.hk_B[t + 1] : 1.0;    // threshold denominator
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
+  // where first touches go
+  int32_t* tv_list = HK ? (hk_last ? a.support : a.hk_tl[(t + 1) % 3]) : a.touched;
+  int32_t* tv_cnt = HK ? (hk_last ? &c->support_cnt : &c->hk_tlc[(t + 1) % 3]) : &c->touched_cnt;
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = blockIdx.x * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
@@ -329,16 +380,25 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
     }
     int32_t dw[kEdgesPerThread];
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) dw[k] = w[k] >= 0 ? a.vr[w[k]].deg : 0;
+    for (int k = 0; k < kEdgesPerThread; k++) dw[k] = w[k] >= 0 && !hk_last ? a.vr[w[k]].deg : 0;
     double old[kEdgesPerThread];
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++)
-      old[k] = w[k] >= 0 ? unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]) : 0.0;
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      double* dst = nullptr;
+      if (w[k] >= 0) dst = !HK ? &a.vr[w[k]].r : hk_last ? &a.p[w[k]] : hk_res(a, t + 1, w[k]);
+      old[k] = dst ? unsafeAtomicAdd(dst, cf[k]) : 0.0;
+    }
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++)
-      if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dw[k], w[k], s_fn, &s_nfn, s_tv, &s_ntv);
-    block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
-    block_flush(&c->touched_cnt, a.touched, a.n, s_tv, &s_ntv, &s_base, &c->fault);
+    for (int k = 0; k < kEdgesPerThread; k++) {
+      if (w[k] < 0) continue;
+      if (hk_last) {
+        if (__double_as_longlong(old[k]) == 0) s_tv[atomicAdd(&s_ntv, 1)] = w[k];
+      } else {
+        decide(old[k], cf[k], (eps * (double)dw[k]) / den, w[k], s_fn, &s_nfn, s_tv, &s_ntv);
+      }
+    }
+    if (!hk_last) block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
+    block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
   }
   if (last_block(&c->done[DONE_SCATTER], &s_last, false)) {
     if (threadIdx.x == 0) {
@@ -346,6 +406,74 @@ __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) {
       c->edges += E;
       c->cnt[t & 1] = 0;
       c->round = t + 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) { scatter_body<false>(a); }
+__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<true>(a); }
+
+// HK-PR initialisation (Fig. alg:hkpr: r = {(x, 1)}, Frontier = {x},
+// j = 0); level 0 touched only x.
+__global__ void k_hk_init(PlainArgs a, int32_t x, int32_t N, double t, double A) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctl* c = a.ctl;
+  c->cs = 0.0;
+  c->cn = 0.0;
+  c->keep = 0.0;
+  c->eps = 0.0;
+  c->seed = x;
+  c->rule = -1;
+  c->max_rounds = N;
+  c->opt_rule = 1;
+  c->round = 0;
+  c->cnt[0] = 1;
+  c->cnt[1] = 0;
+  c->ntiles = 0;
+  c->etotal = 0;
+  c->pushes = 0;
+  c->edges = 0;
+  c->support_cnt = 0;
+  c->touched_cnt = 0;  // no residual is reported: the sweep gathers none
+  c->fault = 0;
+  c->limited = 0;
+  c->N = 0;
+  c->sort_flip = 0;
+  c->rnnz = 0;
+  c->vol_total = a.vol_total;
+  c->best_cut = 0;
+  c->best_vol = 0;
+  c->best_den = 0;
+  c->kstar = 0;
+  c->phi = 0.0;
+  c->hk_N = N;
+  c->hk_t = t;
+  c->hk_A = A;
+  c->hk_tlc[0] = 1;
+  c->hk_tlc[1] = 0;
+  c->hk_tlc[2] = 0;
+  a.hk_tl[0][0] = x;
+  a.fbuf0[0] = x;
+  a.vr[x].r = 1.0;
+  c->status = ST_PUSH;
+}
+
+// After the last HK-PR level: residuals can remain only on the vertices the
+// last two levels touched (every earlier level was cleared by the self
+// kernel two levels later); clear both arrays there.
+__global__ __launch_bounds__(kBlock) void k_hk_clear(PlainArgs a) {
+  Ctl* c = a.ctl;
+  const int J = c->round;
+  for (int q = 0; q < 2; q++) {
+    const int lv = J - q;
+    if (lv < 0) continue;
+    const int li = lv % 3;
+    const int cnt = c->hk_tlc[li];
+    const int32_t* L = a.hk_tl[li];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+      const int32_t v = L[i];
+      a.vr[v].r = 0.0;
+      a.hk_r1[v] = 0.0;
     }
   }
 }
@@ -710,6 +838,23 @@ hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nsee
   if (grid > 1024) grid = 1024;
   hipLaunchKernelGGL(k_query_init_set, dim3(grid), dim3(kBlock), 0, s, a, nseeds, rule, alpha, eps,
                      max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_hk_init(hipStream_t s, const PlainArgs& a, int32_t x, int32_t N, double t,
+                          double A) {
+  hipLaunchKernelGGL(k_hk_init, dim3(1), dim3(64), 0, s, a, x, N, t, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_hk_level(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter) {
+  hipLaunchKernelGGL(k_hk_self, dim3(grid_self), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_hk_scatter, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hk_clear(hipStream_t s, const PlainArgs& a, int grid) {
+  hipLaunchKernelGGL(k_hk_clear, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

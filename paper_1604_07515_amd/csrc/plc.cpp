@@ -390,6 +390,11 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.hot_ids = hot_ids;
   a.hotcode = hotcode;
   a.out_host = ctx->out_host;
+  a.hk_r1 = static_cast<double*>(take(8 * N));
+  a.hk_tl[0] = a.touched;
+  a.hk_tl[1] = static_cast<int32_t*>(take(4 * N));
+  a.hk_tl[2] = static_cast<int32_t*>(take(4 * N));
+  a.hk_B = static_cast<double*>(take(8 * (size_t)(plc::kHkMaxLevels + 1)));
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -578,6 +583,9 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
   return hipSuccess;
 }
 
+static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
+                                   plc_result_info* info_out);
+
 // One plain query: from q.seed, or, with set non-null, from the nset
 // distinct seeds in set (q.seed is then ignored).
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
@@ -643,6 +651,16 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   ctx->round_hist.push_back(h.round);
   if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
+  return sweep_and_record(ctx, g, id_out, info_out);
+}
+
+// After a plain push (the control block read back into ctx->ctl_host):
+// take the result block, run the sweep into it, record the result.
+static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
+                                   plc_result_info* info_out) {
+  hipStream_t s = ctx->stream;
+  const PlainArgs& a = g->args;
+  Ctl& h = *ctx->ctl_host;
   // The result block, sized from the push's counters (support N; the
   // nonzeros of r are among the T touched vertices), before the sweep: the
   // sweep writes into it directly.  Without room, it writes into the
@@ -774,6 +792,55 @@ extern "C" plc_status plc_run_set(plc_ctx* ctx, plc_graph* g, const int32_t* see
   plc_status st = run_one(ctx, g, q, id, info, set.data(), (int32_t)set.size());
   if (st == PLC_E_HIP) return st;
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  return st;
+}
+
+// psi_k = sum_{m=0}^{N-k} k!/(m+k)! t^m (Sec. 3.4), term by term:
+// term_0 = 1, term_m = term_{m-1} * t / (k + m).
+static double hk_psi(int32_t N, int32_t k, double t) {
+  double term = 1.0, s = 1.0;
+  for (int32_t m = 1; m <= N - k; m++) {
+    term = term * t / (double)(k + m);
+    s += term;
+  }
+  return s;
+}
+
+extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int32_t N,
+                                   double eps, double t, uint64_t* id, plc_result_info* info) {
+  if (!ctx || !g || !ctx->graphs.count(g)) return PLC_E_INVALID;
+  if (seed < 0 || seed >= g->n || g->deg[seed] < 1) return PLC_E_INVALID;
+  if (N < 1 || N > plc::kHkMaxLevels) return PLC_E_INVALID;
+  if (!std::isfinite(eps) || !(eps > 0.0) || !std::isfinite(t) || !(t > 0.0))
+    return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const PlainArgs& a = g->args;
+  // threshold of level k: ((e^-t eps) d(w)) / B_k with B_k = 2 N psi_k
+  std::vector<double> B(N + 1);
+  for (int32_t k = 0; k <= N; k++) B[k] = 2.0 * (double)N * hk_psi(N, k, t);
+  HIPCHK(ctx, hipMemcpyAsync(a.hk_B, B.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice,
+                             s));
+  HIPCHK(ctx, plc::launch_hk_init(s, a, seed, N, t, std::exp(-t) * eps));
+  // at most N levels; levels past an empty frontier exit at once
+  const int gs = shape(g->plain_self, ctx->grid_self);
+  const int gc = shape(g->plain_scatter, ctx->grid_scatter);
+  for (int32_t j = 0; j < N; j++) HIPCHK(ctx, plc::launch_hk_level(s, a, gs, gc));
+  HIPCHK(ctx, plc::launch_hk_clear(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
+  Ctl& h = *ctx->ctl_host;
+  HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (h.status != plc::ST_PUSH || h.cnt[h.round & 1] != 0 || h.fault) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  plc_status st = sweep_and_record(ctx, g, id, info);
+  if (st == PLC_E_HIP) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) {
     ctx->broken = true;
     return PLC_E_HIP;
   }

@@ -82,6 +82,11 @@ struct __align__(64) Ctl {
   long long kstar;
   double phi;
   SweepOut out;           // result destinations of the running sweep
+  // HK-PR (Sec. 3.4): Taylor degree, t, e^-t * eps, and the lengths of the
+  // three rotating per-level touched lists (level k uses list k % 3)
+  int32_t hk_N;
+  int32_t hk_tlc[3];
+  double hk_t, hk_A;
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
@@ -115,6 +120,12 @@ struct PlainArgs {
   int32_t* rid;        // r nonzero ids           } could be allocated
   double* rval;        // r nonzero values        }
   const SweepOut* out_host;  // pinned host memory: this sweep's result destinations
+  // HK-PR: level k's residuals live in vr[].r (k even) or hk_r1 (k odd);
+  // the vertices level k touched are listed in hk_tl[k % 3] (hk_tl[0] is
+  // the touched list); hk_B[k] = 2 N psi_k, the threshold denominator
+  double* hk_r1;
+  int32_t* hk_tl[3];
+  double* hk_B;
   long long* bbest;    // per-block argmin candidates (cut, den, k)
   // hot destinations of the batched scatter (the highest-degree vertices,
   // combined in LDS there), kept with the graph
@@ -128,6 +139,7 @@ constexpr int kScanItems = 4;                    // items per thread in scan-typ
 constexpr int kScanBlock = kBlock * kScanItems;  // items per scan block
 constexpr int kEdgeTile = 1024;                  // edges per scatter / cut tile
 constexpr int kEdgesPerThread = kEdgeTile / kBlock;
+constexpr int kHkMaxLevels = 1024;               // largest HK-PR Taylor degree N
 constexpr int kHot = 2048;                       // hot destinations (batched scatter)
 static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 
@@ -138,6 +150,13 @@ hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, in
 // seed set: the nseeds distinct seeds are already in a.fbuf0
 hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nseeds, int32_t rule,
                                  double alpha, double eps, int32_t max_rounds);
+// HK-PR (Sec. 3.4): init from seed x (a.hk_B[0..N] already uploaded), one
+// level (self + scatter; a level past the end exits at once), and the final
+// clearing of both residual arrays
+hipError_t launch_hk_init(hipStream_t s, const PlainArgs& a, int32_t x, int32_t N, double t,
+                          double A);
+hipError_t launch_hk_level(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter);
+hipError_t launch_hk_clear(hipStream_t s, const PlainArgs& a, int grid);
 // With t0 set, the kernel is launched with start and stop events that take
 // its own dispatch timestamps (hipExtLaunchKernelGGL); not for graph capture.
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,

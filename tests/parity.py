@@ -93,13 +93,25 @@ def check_query(g, res, seed, alpha, eps, rule, orc=None, osw=None) -> dict:
         assert np.array_equal(nz_o, nz_g), "r nonzeros"
         err_r = np.abs(r[nz_o] - orc.r[nz_o]) / orc.r[nz_o]
         assert err_r.max(initial=0) <= RTOL, ("r", err_r.max())
-    # sweep: order, cluster and conductance equal to the oracle's, modulo
-    # near-tie blocks (positions whose keys differ by < TIE may be swapped)
+    tie_sweep = check_sweep(g, res, orc.p, p, tie_push, osw)
+    return {"tie_push": tie_push, "tie_sweep": tie_sweep, "rounds": info["rounds"],
+            "edges": info["edges"], "support": info["support"]}
+
+
+def check_sweep(g, res, p_ref, p, tie_push, osw=None) -> bool:
+    """The sweep of GPU result `res` (p on the GPU: p) against the oracle's
+    sweep of p_ref: order, cluster and conductance equal modulo near-tie
+    blocks (positions whose keys differ by < TIE may be swapped), and the
+    reported cut and vol recounted from the GPU's own cluster.  Returns
+    whether a near-tie block was met."""
+    n = g.n
+    deg = g.deg
+    info = res.info
     if osw is None:
-        osw = oracle.sweep(g.off, g.nbr, orc.p)
+        osw = oracle.sweep(g.off, g.nbr, p_ref)
     tie_sweep = False
     if not tie_push:
-        blk = tie_blocks(osw.order, orc.p, deg, p)
+        blk = tie_blocks(osw.order, p_ref, deg, p)
         tie_sweep = bool(np.any(blk != np.arange(len(blk))))
         assert len(res.sweep_ids) == len(osw.order), "support size"
         if not tie_sweep:
@@ -128,8 +140,31 @@ def check_query(g, res, seed, alpha, eps, rule, orc=None, osw=None) -> dict:
     assert Fraction(cut, den) == Fraction(info["cut"], den)
     assert info["phi"] == cut / den
     np.testing.assert_array_equal(res.sweep_p, p[res.sweep_ids])
-    return {"tie_push": tie_push, "tie_sweep": tie_sweep, "rounds": info["rounds"],
-            "edges": info["edges"], "support": info["support"]}
+    return tie_sweep
+
+
+def check_hkpr(g, res, orc) -> dict:
+    """GPU HK-PR result `res` against the oracle's level-synchronous HK-PR
+    `orc` (oracle.hkpr): p within RTOL with the same support, levels,
+    pushes and edges exactly, no residual reported, and the sweep as for
+    PR-Nibble.  Near-threshold decisions (oracle gap < TIE) may flip under a
+    different summation order: then only the sweep's self-consistency and
+    the bound p <= p(eps = 0) are left to the caller."""
+    info = res.info
+    p = res.dense_p(g.n)
+    assert info["status"] == 0 and info["r_nnz"] == 0
+    tie_push = orc.min_rel_gap < TIE
+    if not tie_push:
+        assert (info["rounds"], info["pushes"], info["edges"]) == (orc.levels, orc.pushes,
+                                                                   orc.edges)
+        sup = orc.p > 0
+        assert np.array_equal(sup, p > 0), "support"
+        assert info["support"] == int(sup.sum())
+        err = np.abs(p[sup] - orc.p[sup]) / orc.p[sup]
+        assert err.max(initial=0) <= RTOL, ("p", err.max())
+    tie_sweep = check_sweep(g, res, orc.p, p, tie_push)
+    return {"tie_push": tie_push, "tie_sweep": tie_sweep, "levels": info["rounds"],
+            "support": info["support"]}
 
 
 def check_same(g, a, b) -> None:

@@ -1,13 +1,13 @@
 """Pins of the HK-PR oracle (Sec. 3.4, Fig. alg:hkpr), CPU only.
 
-  * eps = 0 (nothing is dropped): p equals the polynomial the procedure
+  * eps = 1e-300 (nothing is dropped): p equals the polynomial the procedure
     evaluates, sum_{k<N} t^k/k! P^k s + t^(N-1)/(N-1)! P^N s, from dense
     matrix powers (the last level spreads r/d(v) to the neighbours);
   * the level-synchronous oracle equals the sequential queue procedure
     printed in Sec. 3.4 (an independent formulation);
   * a hand-derived threshold case on a 3-vertex path that tells psi_(j+1)
     from psi_j and psi_(j+2);
-  * a larger eps drops more: p is monotone in eps, p <= p(eps = 0);
+  * a larger eps drops more: p is monotone in eps, p <= p(eps = 1e-300);
   * a huge eps pushes only the seed; N = 1 spreads the seed's unit once.
 """
 import math
@@ -42,10 +42,10 @@ GRAPHS = {"er": lambda: synth.erdos_renyi(40, 0.15, 5), "star": lambda: synth.st
 
 @pytest.mark.parametrize("gname", sorted(GRAPHS))
 @pytest.mark.parametrize("N,t", [(1, 1.0), (2, 0.5), (5, 3.0), (12, 10.0)])
-def test_eps_zero_is_the_polynomial(gname, N, t):
+def test_tiny_eps_is_the_polynomial(gname, N, t):
     g = GRAPHS[gname]()
     x = int(np.argmax(g.deg))
-    res = oracle.hkpr(g.off, g.nbr, x, N, 0.0, t)
+    res = oracle.hkpr(g.off, g.nbr, x, N, 1e-300, t)
     ref = poly(g, x, N, t)
     assert np.max(np.abs(res.p - ref)) <= 1e-12 * np.max(ref)
     assert res.levels == N
@@ -97,7 +97,7 @@ def test_monotone_in_eps():
     g = synth.rmat(8, 8, seed=7)
     x = int(np.argmax(g.deg))
     N, t = 12, 4.0
-    prev = oracle.hkpr(g.off, g.nbr, x, N, 0.0, t).p
+    prev = oracle.hkpr(g.off, g.nbr, x, N, 1e-300, t).p
     for eps in (1e-8, 1e-6, 1e-4, 1e-2, 1.0):
         cur = oracle.hkpr(g.off, g.nbr, x, N, eps, t).p
         assert np.all(cur <= prev * (1 + 1e-12) + 1e-300)
@@ -114,6 +114,7 @@ def test_huge_eps_and_single_level():
 
 def test_invalid_inputs():
     g = synth.path(4)
-    for args in ((0, 0, 1e-3, 1.0), (-1, 3, 1e-3, 1.0), (0, 3, -1.0, 1.0), (0, 3, 1e-3, 0.0)):
+    for args in ((0, 0, 1e-3, 1.0), (-1, 3, 1e-3, 1.0), (0, 3, -1.0, 1.0), (0, 3, 0.0, 1.0),
+                 (0, 3, 1e-3, 0.0)):
         with pytest.raises(ValueError):
             oracle.hkpr(g.off, g.nbr, *args)
