@@ -57,6 +57,11 @@ class _HkStats(C.Structure):
                 ("support", C.c_int64), ("min_rel_gap", C.c_double)]
 
 
+class _NbStats(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("pushes", C.c_int64), ("edges", C.c_int64),
+                ("support", C.c_int64), ("min_rel_gap", C.c_double)]
+
+
 _lib = None
 
 
@@ -79,6 +84,9 @@ def _load():
         lib.oracle_sweep_bruteforce.restype = C.c_int
         lib.oracle_sweep_z.argtypes = [C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]
         lib.oracle_sweep_z.restype = C.c_int
+        lib.oracle_nibble.argtypes = [C.c_int64, P, P, C.c_int32, C.c_double, C.c_int32, P,
+                                      C.POINTER(_NbStats)]
+        lib.oracle_nibble.restype = C.c_int
         for fn in (lib.oracle_hkpr, lib.oracle_hkpr_queue):
             fn.argtypes = [C.c_int64, P, P, C.c_int32, C.c_int32, C.c_double, C.c_double, P,
                            C.POINTER(_HkStats)]
@@ -248,3 +256,25 @@ def hkpr_queue(off, nbr, seed, N: int, eps: float, t: float) -> HkResult:
     """Deterministic HK-PR, the sequential queue procedure of Sec. 3.4
     (dense (N+1) x n residual table: small graphs only)."""
     return _hk(_load().oracle_hkpr_queue, off, nbr, seed, N, eps, t)
+
+
+@dataclass
+class NibbleResult:
+    p: np.ndarray          # the returned vector, dense float64
+    iterations: int        # iterations whose next vector was computed
+    pushes: int
+    edges: int
+    support: int
+    min_rel_gap: float
+
+
+def nibble(off, nbr, seed, eps: float, T: int) -> NibbleResult:
+    """Nibble, the truncated lazy random walk (Sec. 3.2, Fig. alg:nibble)."""
+    off, nbr, n = _csr(off, nbr)
+    p = np.zeros(n, np.float64)
+    st = _NbStats()
+    rc = _load().oracle_nibble(n, _ptr(off), _ptr(nbr), int(seed), float(eps), int(T), _ptr(p),
+                               C.byref(st))
+    if rc < 0:
+        raise ValueError("oracle_nibble rejected its input (code %d)" % rc)
+    return NibbleResult(p, st.iterations, st.pushes, st.edges, st.support, st.min_rel_gap)

@@ -543,3 +543,92 @@ int oracle_hkpr_queue(int64_t n, const int64_t* off, const int32_t* nbr, int32_t
   free(psi); free(r); free(qv);
   return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Nibble (Sec. 3.2, Fig. alg:nibble): the truncated lazy random walk from
+ * seed x for up to T iterations.  Iteration t builds p' from p: every
+ * frontier vertex v keeps p[v]/2 and sends p[v]/(2 d(v)) to each neighbour
+ * (fetch-and-add, here in edge order); the next frontier is every vertex
+ * with p'[v] >= eps d(v).  If it is empty the loop stops and p (the previous
+ * vector) is returned; otherwise p = p'.  After T iterations p_T is
+ * returned.  Readings: the first frontier is {x} whatever its threshold;
+ * the returned vector is returned whole (entries below eps d(v) are only
+ * not propagated).  p dense, length n, overwritten.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t iterations;  /* iterations whose p' was computed */
+  int64_t pushes;      /* frontier entries processed */
+  int64_t edges;       /* sum of d(v) over them */
+  int64_t support;     /* vertices with p > 0 in the returned vector */
+  double min_rel_gap;  /* closest approach of a threshold decision to its threshold */
+} oracle_nb_stats;
+
+int oracle_nibble(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x, double eps,
+                  int32_t T, double* p, oracle_nb_stats* st) {
+  if (n <= 0 || !off || !nbr || !p || !st || T < 0) return ORACLE_E_INVALID;
+  if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
+  if (!(eps > 0.0) || !isfinite(eps)) return ORACLE_E_INVALID;
+  double* pn = (double*)calloc((size_t)n, sizeof(double));
+  int32_t* F = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* frontier of p */
+  int32_t* S = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* support of p */
+  int32_t* G = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);  /* support of p' */
+  uint8_t* mark = (uint8_t*)calloc((size_t)n, 1);
+  if (!pn || !F || !S || !G || !mark) {
+    free(pn); free(F); free(S); free(G); free(mark);
+    return ORACLE_E_NOMEM;
+  }
+  memset(st, 0, sizeof(*st));
+  st->min_rel_gap = INFINITY;
+  for (int64_t v = 0; v < n; v++) p[v] = 0.0;
+  p[x] = 1.0;
+  int64_t nf = 1, ns = 1;
+  F[0] = x;
+  S[0] = x;
+  for (int32_t t = 1; t <= T; t++) {
+    st->iterations++;
+    st->pushes += nf;
+    /* p' = {}; vertexMap(Frontier, UpdateSelf); edgeMap(G, Frontier, UpdateNgh) */
+    int64_t ng = 0;
+    for (int64_t i = 0; i < nf; i++) {
+      const int32_t v = F[i];
+      pn[v] = p[v] / 2.0;
+      if (!mark[v]) { mark[v] = 1; G[ng++] = v; }
+    }
+    for (int64_t i = 0; i < nf; i++) {
+      const int32_t v = F[i];
+      const int64_t d = deg_of(off, v);
+      st->edges += d;
+      const double c = p[v] / (2.0 * (double)d);
+      for (int64_t e = off[v]; e < off[v + 1]; e++) {
+        const int32_t w = nbr[e];
+        pn[w] += c;
+        if (!mark[w]) { mark[w] = 1; G[ng++] = w; }
+      }
+    }
+    /* Frontier = {v | p'[v] >= d(v) eps} (filter) */
+    int64_t k = 0;
+    for (int64_t i = 0; i < ng; i++) {
+      const int32_t w = G[i];
+      mark[w] = 0;
+      const double thr = eps * (double)deg_of(off, w);
+      const double gap = fabs(pn[w] - thr) / thr;
+      if (gap < st->min_rel_gap) st->min_rel_gap = gap;
+      if (pn[w] >= thr) F[k++] = w;
+    }
+    if (k == 0) {  /* return the previous vector */
+      for (int64_t i = 0; i < ng; i++) pn[G[i]] = 0.0;
+      break;
+    }
+    /* p = p' */
+    for (int64_t i = 0; i < ns; i++) p[S[i]] = 0.0;
+    for (int64_t i = 0; i < ng; i++) { p[G[i]] = pn[G[i]]; pn[G[i]] = 0.0; }
+    qsort(F, (size_t)k, sizeof(int32_t), cmp_i32);
+    nf = k;
+    int32_t* tmp = S; S = G; G = tmp;
+    ns = ng;
+  }
+  for (int64_t v = 0; v < n; v++) st->support += p[v] > 0.0;
+  free(pn); free(F); free(S); free(G); free(mark);
+  return ORACLE_OK;
+}
