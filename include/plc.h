@@ -214,6 +214,23 @@ plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int32_t N, dou
                         double t, uint64_t* id, plc_result_info* info);
 
 /*
+ * Plain path, Nibble from seed x (Sec. 3.2, Fig. alg:nibble: the truncated
+ * lazy random walk) followed by the sweep cut.  p_0 is x's indicator and
+ * the first frontier is {x}; step t (1..T) forms p_t from the frontier of
+ * p_{t-1}: each frontier vertex v keeps p_{t-1}[v]/2 and sends
+ * p_{t-1}[v]/(2 d(v)) to every neighbour; the next frontier is every v with
+ * p_t[v] >= eps d(v).  If it is empty, p_{t-1} is returned; else after T
+ * steps p_T is.  The returned vector is swept whole (entries below eps d(v)
+ * only stop propagating).  eps > 0, T in [0, 1024].  Blocks until done.
+ * *info: rounds = steps computed, pushes = frontier entries processed,
+ * edges = their degrees, support, the cluster; no residual (r_nnz = 0).
+ * Errors: PLC_E_INVALID (bad seed, eps or T; nothing runs), PLC_E_NOMEM (no
+ * room for the result: the counters are still in *info), PLC_E_HIP.
+ */
+plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, double eps, int32_t T,
+                          uint64_t* id, plc_result_info* info);
+
+/*
  * Batched path.  Many queries advance together: every global step runs one
  * PR-Nibble round for all admitted queries in the same kernel launches, and
  * the queries whose frontier emptied are swept together.  Results are the

@@ -35,7 +35,8 @@ PLC_STATE_COMPACT = 1
 
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
-           "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_result_info_get",
+           "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_run_nibble",
+           "plc_result_info_get",
            "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
            "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_wait",
@@ -125,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                          C.POINTER(plc_result_info)], I32),
         "plc_run_hkpr": ([P, P, I32, I32, C.c_double, C.c_double, C.POINTER(U64),
                           C.POINTER(plc_result_info)], I32),
+        "plc_run_nibble": ([P, P, I32, C.c_double, I32, C.POINTER(U64),
+                            C.POINTER(plc_result_info)], I32),
         "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
         "plc_result_copy": ([P, U64, P, P, P, P], I32),
         "plc_release": ([P, U64], I32),
@@ -315,6 +318,17 @@ class Context:
                                    C.byref(qid), C.byref(info))
         if check and rc != PLC_OK:
             raise PlcError(rc, "plc_run_hkpr")
+        return qid.value, info.as_dict()
+
+    def run_nibble(self, g: Graph, seed: int, eps: float, T: int, check: bool = True):
+        """Plain path: Nibble (truncated lazy walk, at most T steps) from
+        seed, then the sweep cut.  Returns (id, info)."""
+        qid = C.c_uint64()
+        info = plc_result_info()
+        rc = self.lib.plc_run_nibble(self.handle, g.handle, int(seed), float(eps), int(T),
+                                     C.byref(qid), C.byref(info))
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_run_nibble")
         return qid.value, info.as_dict()
 
     # ---- batched path

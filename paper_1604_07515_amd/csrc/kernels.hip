@@ -169,8 +169,11 @@ __device__ __forceinline__ void mark_tiles(int32_t* tile_start, int64_t cap, lon
   for (long long tt = t0; tt <= t1; tt++) tile_start[tt] = i;
 }
 
-// HK-PR residual of vertex v at level k: even levels in the state record,
-// odd levels in hk_r1.
+// Round rules sharing the round kernels.
+enum : int { kModePR = 0, kModeHK = 1, kModeNB = 2 };
+
+// HK-PR residual (Nibble vector) of vertex v at level (iteration) k: even
+// levels in the state record, odd levels in hk_r1.
 __device__ __forceinline__ double* hk_res(const PlainArgs& a, int k, int32_t v) {
   return (k & 1) ? &a.hk_r1[v] : &a.vr[v].r;
 }
@@ -182,13 +185,18 @@ __device__ __forceinline__ double* hk_res(const PlainArgs& a, int k, int32_t v) 
 //     or rho / d on the last level; first, the residuals of level j - 1
 //     (the array level j + 1 fills) are cleared over the vertices that
 //     level touched.
-template <bool HK>
+//   Nibble step j -> j+1 (Fig. alg:nibble): coefficient rho / (2 d), and
+//     rho / 2 kept per entry for the scatter, which adds it to the vertex's
+//     own next value; the same clearing as HK-PR.
+template <int MODE>
 __device__ __forceinline__ void self_body(const PlainArgs& a) {
+  constexpr bool HK = MODE == kModeHK;
+  constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
-  if (HK) {
-    if (t >= c->hk_N) return;  // (the last level leaves no frontier)
+  if (LEVELS) {
+    if (t >= (HK ? c->hk_N : c->max_rounds)) return;  // (the host queues no more)
     if (t >= 1) {
       const int lp = (t + 2) % 3;
       const int np = c->hk_tlc[lp];
@@ -205,7 +213,7 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
   __shared__ long long s_excl;
   __shared__ int s_tk[2];
   __shared__ int32_t s_sup[kScanBlock];
-  __shared__ int32_t s_stay[HK ? 1 : kScanBlock];
+  __shared__ int32_t s_stay[LEVELS ? 1 : kScanBlock];
   __shared__ int s_nsup, s_nstay, s_base;
   ScanSite* site = &c->scan[SCAN_FRONTIER];
   scan_clear_prev(site, a.desc[SCAN_FRONTIER], a.desc_cap);
@@ -214,7 +222,7 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
   const double cs = c->cs, cn = c->cn, keep = c->keep, eps = c->eps;
-  const bool opt = HK || c->opt_rule != 0;
+  const bool opt = LEVELS || c->opt_rule != 0;
   const bool hk_last = HK && t + 1 == c->hk_N;
   const double hk_t = HK ? c->hk_t : 0.0;
   const int nblk = (nf + kScanBlock - 1) / kScanBlock;
@@ -237,7 +245,7 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
       if (i < nf) {
         int32_t v = F[i];
         double rho;
-        if (HK) {
+        if (LEVELS) {
           rho = *hk_res(a, t, v);
           d = a.vr[v].deg;
         } else {
@@ -245,8 +253,11 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
           rho = rec.r;
           d = rec.deg;
         }
-        double pold = a.p[v];
-        if (HK) {
+        double pold = MODE == kModeNB ? 1.0 : a.p[v];
+        if (MODE == kModeNB) {
+          a.coef[i] = rho / (2.0 * (double)d);
+          a.sp[i] = rho / 2.0;
+        } else if (HK) {
           a.p[v] = pold + rho;
           a.coef[i] = hk_last ? rho / (double)d : (hk_t * rho) / ((double)(t + 1) * (double)d);
         } else {
@@ -284,13 +295,15 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
       c->etotal = tot;
       c->ntiles = (int)((tot + kEdgeTile - 1) / kEdgeTile);
     }
-    block_flush(&c->support_cnt, a.support, a.n, s_sup, &s_nsup, &s_base, &c->fault);
+    if (MODE != kModeNB)
+      block_flush(&c->support_cnt, a.support, a.n, s_sup, &s_nsup, &s_base, &c->fault);
     if (!opt) block_flush(cntn, Fn, a.n, s_stay, &s_nstay, &s_base, &c->fault);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) { self_body<false>(a); }
-__global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<true>(a); }
+__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) { self_body<kModePR>(a); }
+__global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<kModeHK>(a); }
+__global__ __launch_bounds__(kBlock) void k_nb_self(PlainArgs a) { self_body<kModeNB>(a); }
 
 // Threshold decision for one addition of c to r[w] that returned `old`:
 // crossing appends w to the next frontier, first touch to the touched list.
@@ -311,8 +324,13 @@ __device__ __forceinline__ void decide(double old, double c, double thr, int32_t
 //     ((e^-t eps) d(w)) / (2 N psi_{j+1}), first touches to level j+1's list;
 //     on the last level into p (UpdateNghLast), first touches of p to the
 //     support list, no frontier.
-template <bool HK>
+//   Nibble step j -> j+1: into vector j+1, threshold eps d(w), first touches
+//     to list j+1; each entry's own rho / 2 is added by the workgroup whose
+//     tile holds the entry's first edge.
+template <int MODE>
 __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
+  constexpr bool HK = MODE == kModeHK;
+  constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
@@ -327,12 +345,14 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
   const long long E = c->etotal;
   const bool hk_last = HK && t + 1 == c->hk_N;
   const double eps = HK ? c->hk_A : c->eps;                   // threshold numerator factor
+  const int32_t* Fc = (t & 1) ? a.fbuf1 : a.fbuf0;            // this round's frontier
   const double den = HK && !hk_last ? a.hk_B[t + 1] : 1.0;    // threshold denominator
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
   // where first touches go
-  int32_t* tv_list = HK ? (hk_last ? a.support : a.hk_tl[(t + 1) % 3]) : a.touched;
-  int32_t* tv_cnt = HK ? (hk_last ? &c->support_cnt : &c->hk_tlc[(t + 1) % 3]) : &c->touched_cnt;
+  int32_t* tv_list = LEVELS ? (hk_last ? a.support : a.hk_tl[(t + 1) % 3]) : a.touched;
+  int32_t* tv_cnt =
+      LEVELS ? (hk_last ? &c->support_cnt : &c->hk_tlc[(t + 1) % 3]) : &c->touched_cnt;
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = blockIdx.x * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
@@ -385,7 +405,7 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       double* dst = nullptr;
-      if (w[k] >= 0) dst = !HK ? &a.vr[w[k]].r : hk_last ? &a.p[w[k]] : hk_res(a, t + 1, w[k]);
+      if (w[k] >= 0) dst = !LEVELS ? &a.vr[w[k]].r : hk_last ? &a.p[w[k]] : hk_res(a, t + 1, w[k]);
       old[k] = dst ? unsafeAtomicAdd(dst, cf[k]) : 0.0;
     }
 #pragma unroll
@@ -399,6 +419,20 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
     }
     if (!hk_last) block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
     block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
+    if (MODE == kModeNB) {
+      // the kept halves of the entries whose first edge is in this tile
+      for (int jj = threadIdx.x; jj < cnt; jj += kBlock) {
+        const int st = s_start[jj];
+        if (st < 0 || e0 + st >= e1) continue;
+        const int i = i0 + jj;
+        const int32_t v = Fc[i];
+        const double h = a.sp[i];
+        const double o = unsafeAtomicAdd(hk_res(a, t + 1, v), h);
+        decide(o, h, eps * (double)a.vr[v].deg, v, s_fn, &s_nfn, s_tv, &s_ntv);
+      }
+      block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
+      block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
+    }
   }
   if (last_block(&c->done[DONE_SCATTER], &s_last, false)) {
     if (threadIdx.x == 0) {
@@ -410,8 +444,9 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) { scatter_body<false>(a); }
-__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<true>(a); }
+__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) { scatter_body<kModePR>(a); }
+__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<kModeHK>(a); }
+__global__ __launch_bounds__(kBlock) void k_nb_scatter(PlainArgs a) { scatter_body<kModeNB>(a); }
 
 // HK-PR initialisation (Fig. alg:hkpr: r = {(x, 1)}, Frontier = {x},
 // j = 0); level 0 touched only x.
@@ -456,6 +491,80 @@ __global__ void k_hk_init(PlainArgs a, int32_t x, int32_t N, double t, double A)
   a.fbuf0[0] = x;
   a.vr[x].r = 1.0;
   c->status = ST_PUSH;
+}
+
+// Nibble initialisation (Fig. alg:nibble: p = {(x, 1)}, Frontier = {x});
+// vector 0 is the seed's indicator, its support list holds x.
+__global__ void k_nb_init(PlainArgs a, int32_t x, double eps, int32_t T) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctl* c = a.ctl;
+  c->cs = 0.0;
+  c->cn = 0.0;
+  c->keep = 0.0;
+  c->eps = eps;
+  c->seed = x;
+  c->rule = -2;
+  c->max_rounds = T;
+  c->opt_rule = 1;
+  c->round = 0;
+  c->cnt[0] = 1;
+  c->cnt[1] = 0;
+  c->ntiles = 0;
+  c->etotal = 0;
+  c->pushes = 0;
+  c->edges = 0;
+  c->support_cnt = 0;
+  c->touched_cnt = 0;
+  c->fault = 0;
+  c->limited = 0;
+  c->N = 0;
+  c->sort_flip = 0;
+  c->rnnz = 0;
+  c->vol_total = a.vol_total;
+  c->best_cut = 0;
+  c->best_vol = 0;
+  c->best_den = 0;
+  c->kstar = 0;
+  c->phi = 0.0;
+  c->hk_N = 0;
+  c->hk_tlc[0] = 1;
+  c->hk_tlc[1] = 0;
+  c->hk_tlc[2] = 0;
+  a.hk_tl[0][0] = x;
+  a.fbuf0[0] = x;
+  a.vr[x].r = 1.0;
+  c->status = ST_PUSH;
+}
+
+// End of Nibble after J steps, returning vector R (J, or J - 1 when step J
+// left an empty frontier): p and the support list take vector R over the
+// vertices it touched, and both vector arrays are cleared (vector J over
+// list J, vector J - 1 over list J - 1: every earlier one was cleared by
+// the self kernel two steps later; each entry of vector R is read and
+// cleared by the same thread).  The frontier count is zeroed so that the
+// sweep may start.
+__global__ __launch_bounds__(kBlock) void k_nb_finish(PlainArgs a, int32_t R, int32_t J) {
+  Ctl* c = a.ctl;
+  for (int q = 0; q < 2; q++) {
+    const int lv = J - q;
+    if (lv < 0) continue;
+    const int li = lv % 3;
+    const int cnt = c->hk_tlc[li];
+    const int32_t* L = a.hk_tl[li];
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < cnt; i += gridDim.x * kBlock) {
+      const int32_t v = L[i];
+      double* x = hk_res(a, lv, v);
+      if (lv == R) {
+        a.p[v] = *x;
+        a.support[i] = v;
+      }
+      *x = 0.0;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->support_cnt = c->hk_tlc[R % 3];
+    c->cnt[J & 1] = 0;
+  }
 }
 
 // After the last HK-PR level: residuals can remain only on the vertices the
@@ -850,6 +959,22 @@ hipError_t launch_hk_init(hipStream_t s, const PlainArgs& a, int32_t x, int32_t 
 hipError_t launch_hk_level(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter) {
   hipLaunchKernelGGL(k_hk_self, dim3(grid_self), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_hk_scatter, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_init(hipStream_t s, const PlainArgs& a, int32_t x, double eps, int32_t T) {
+  hipLaunchKernelGGL(k_nb_init, dim3(1), dim3(64), 0, s, a, x, eps, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_step(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter) {
+  hipLaunchKernelGGL(k_nb_self, dim3(grid_self), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_nb_scatter, dim3(grid_scatter), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_nb_finish(hipStream_t s, const PlainArgs& a, int32_t R, int32_t J, int grid) {
+  hipLaunchKernelGGL(k_nb_finish, dim3(grid), dim3(kBlock), 0, s, a, R, J);
   return hipGetLastError();
 }
 

@@ -847,6 +847,42 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
   return st;
 }
 
+extern "C" plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, double eps,
+                                     int32_t T, uint64_t* id, plc_result_info* info) {
+  if (!ctx || !g || !ctx->graphs.count(g)) return PLC_E_INVALID;
+  if (seed < 0 || seed >= g->n || g->deg[seed] < 1) return PLC_E_INVALID;
+  if (T < 0 || T > plc::kNbMaxSteps || !std::isfinite(eps) || !(eps > 0.0)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const PlainArgs& a = g->args;
+  HIPCHK(ctx, plc::launch_nb_init(s, a, seed, eps, T));
+  const int gs = shape(g->plain_self, ctx->grid_self);
+  const int gc = shape(g->plain_scatter, ctx->grid_scatter);
+  for (int32_t j = 0; j < T; j++) HIPCHK(ctx, plc::launch_nb_step(s, a, gs, gc));
+  Ctl& h = *ctx->ctl_host;
+  HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  if (h.status != plc::ST_PUSH || h.fault || h.round < 0 || h.round > T) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  // the returned vector: the last step's, unless that step's frontier was
+  // empty, then the one before it
+  const int32_t J = h.round;
+  const int32_t R = h.cnt[J & 1] > 0 ? J : J - 1;
+  HIPCHK(ctx, plc::launch_nb_finish(s, a, R, J, shape(g->plain_sweep, ctx->grid_sweep)));
+  h.support_cnt = h.hk_tlc[R % 3];
+  h.touched_cnt = 0;
+  plc_status st = sweep_and_record(ctx, g, id, info);
+  if (st == PLC_E_HIP) return st;
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  return st;
+}
+
 extern "C" plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out) {
   if (!ctx || !out) return PLC_E_INVALID;
   auto it = ctx->results.find(id);

@@ -83,7 +83,8 @@ struct __align__(64) Ctl {
   double phi;
   SweepOut out;           // result destinations of the running sweep
   // HK-PR (Sec. 3.4): Taylor degree, t, e^-t * eps, and the lengths of the
-  // three rotating per-level touched lists (level k uses list k % 3)
+  // three rotating per-level touched lists (level k uses list k % 3; Nibble
+  // uses the same lists and arrays for its vectors)
   int32_t hk_N;
   int32_t hk_tlc[3];
   double hk_t, hk_A;
@@ -140,6 +141,7 @@ constexpr int kScanBlock = kBlock * kScanItems;  // items per scan block
 constexpr int kEdgeTile = 1024;                  // edges per scatter / cut tile
 constexpr int kEdgesPerThread = kEdgeTile / kBlock;
 constexpr int kHkMaxLevels = 1024;               // largest HK-PR Taylor degree N
+constexpr int kNbMaxSteps = 1024;                // largest Nibble step count T
 constexpr int kHot = 2048;                       // hot destinations (batched scatter)
 static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 
@@ -157,6 +159,12 @@ hipError_t launch_hk_init(hipStream_t s, const PlainArgs& a, int32_t x, int32_t 
                           double A);
 hipError_t launch_hk_level(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter);
 hipError_t launch_hk_clear(hipStream_t s, const PlainArgs& a, int grid);
+// Nibble (Sec. 3.2): init from seed x, one step (self + scatter; steps past
+// an empty frontier or T exit at once), and the end (vector R of J steps
+// into p and the support list, both vector arrays cleared)
+hipError_t launch_nb_init(hipStream_t s, const PlainArgs& a, int32_t x, double eps, int32_t T);
+hipError_t launch_nb_step(hipStream_t s, const PlainArgs& a, int grid_self, int grid_scatter);
+hipError_t launch_nb_finish(hipStream_t s, const PlainArgs& a, int32_t R, int32_t J, int grid);
 // With t0 set, the kernel is launched with start and stop events that take
 // its own dispatch timestamps (hipExtLaunchKernelGGL); not for graph capture.
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,

@@ -206,3 +206,24 @@ def check_properties(g, res, eps):
     assert info["vol"] == int(g.deg[cl].sum())
     assert info["cut"] == int(np.count_nonzero(~inset[cluster_arcs(g, cl)]))
     assert info["phi"] == info["cut"] / min(info["vol"], g.arcs - info["vol"])
+
+
+def check_nibble(g, res, orc) -> dict:
+    """GPU Nibble result against the oracle's (oracle.nibble): the returned
+    vector within RTOL with the same support, steps, pushes and edges
+    exactly, no residual reported, and the sweep as for PR-Nibble; near
+    threshold decisions (oracle gap < TIE) relax the first part."""
+    info = res.info
+    p = res.dense_p(g.n)
+    assert info["status"] == 0 and info["r_nnz"] == 0
+    tie_push = orc.min_rel_gap < TIE
+    if not tie_push:
+        assert (info["rounds"], info["pushes"], info["edges"]) == (orc.iterations, orc.pushes,
+                                                                   orc.edges)
+        sup = orc.p > 0
+        assert np.array_equal(sup, p > 0), "support"
+        err = np.abs(p[sup] - orc.p[sup]) / orc.p[sup]
+        assert err.max(initial=0) <= RTOL, ("p", err.max())
+    tie_sweep = check_sweep(g, res, orc.p, p, tie_push)
+    return {"tie_push": tie_push, "tie_sweep": tie_sweep, "steps": info["rounds"],
+            "support": info["support"]}
