@@ -337,10 +337,9 @@ def bench_rules(plc, synth, g, seeds):
             "paper": "sequential, optimized rule 1.4-6.4x faster at the same conductance"}
 
 
-def hkpr_timed(ctx, hg, seeds, N=20, eps=1e-7, t=10.0):
-    """Deterministic HK-PR + sweep (Sec. 3.4) with the paper's experiment
-    parameters (t = 10, N = 20, eps = 1e-7), one query at a time: one warm
-    pass over the seeds, then one timed pass."""
+def algo_timed(run, seeds, params):
+    """One query at a time through `run(seed) -> (id, info)` (which releases
+    its result): one warm pass over the seeds, then one timed pass."""
     import numpy as np
     import torch
     for timed in (False, True):
@@ -348,29 +347,54 @@ def hkpr_timed(ctx, hg, seeds, N=20, eps=1e-7, t=10.0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for x in seeds:
-            qid, info = ctx.run_hkpr(hg, int(x), N, eps, t)
-            ctx.release(qid)
-            rows.append(info)
+            qid, info = run(int(x))
+            rows.append((qid, info))
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+    infos = [r for _, r in rows]
     nq = len(seeds)
-    edges = sum(r["edges"] for r in rows)
-    return {"N": N, "eps": eps, "t": t, "queries": nq, "seconds_per_query": el / nq,
-            "queries_per_s": nq / el, "edges_per_s": edges / el,
-            "per_query": {"levels": float(np.mean([r["rounds"] for r in rows])),
-                          "pushes": float(np.mean([r["pushes"] for r in rows])),
-                          "edges": edges / nq,
-                          "support": float(np.mean([r["support"] for r in rows]))}}
+    edges = sum(r["edges"] for r in infos)
+    out = dict(params)
+    out.update({"queries": nq, "seconds_per_query": el / nq, "queries_per_s": nq / el,
+                "edges_per_s": edges / el,
+                "per_query": {"rounds": float(np.mean([r["rounds"] for r in infos])),
+                              "pushes": float(np.mean([r["pushes"] for r in infos])),
+                              "edges": edges / nq,
+                              "support": float(np.mean([r["support"] for r in infos]))}})
+    return out
+
+
+def hkpr_timed(ctx, hg, seeds, N=20, eps=1e-7, t=10.0):
+    """Deterministic HK-PR + sweep (Sec. 3.4) with the paper's experiment
+    parameters (t = 10, N = 20, eps = 1e-7)."""
+    def run(x):
+        qid, info = ctx.run_hkpr(hg, x, N, eps, t)
+        ctx.release(qid)
+        return qid, info
+    return algo_timed(run, seeds, {"algorithm": "HK-PR", "N": N, "eps": eps, "t": t})
+
+
+def nibble_timed(ctx, hg, seeds, T=20, eps=1e-8):
+    """Nibble + sweep (Sec. 3.2) with the paper's experiment parameters
+    (T = 20, eps = 1e-8)."""
+    def run(x):
+        qid, info = ctx.run_nibble(hg, x, eps, T)
+        ctx.release(qid)
+        return qid, info
+    return algo_timed(run, seeds, {"algorithm": "Nibble", "T": T, "eps": eps})
 
 
 def bench_hkpr(plc, synth, g, seeds):
+    """HK-PR and Nibble with the paper's parameters on the 16 plain seeds."""
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
     ctx.autotune(hg, seeds[:4], 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
     out = hkpr_timed(ctx, hg, seeds)
-    ctx.close()
     out["workload"] = "rmat22_ef16_hkpr_16seeds"
-    return out
+    nb = nibble_timed(ctx, hg, seeds)
+    nb["workload"] = "rmat22_ef16_nibble_16seeds"
+    ctx.close()
+    return out, nb
 
 
 def bench_grid3d(plc, synth, side=215, nq=8):
@@ -402,11 +426,15 @@ def bench_grid3d(plc, synth, side=215, nq=8):
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     hk = hkpr_timed(ctx, hg, seeds)
+    nb = nibble_timed(ctx, hg, seeds)
     ctx.close()
     per = el / nq
     hk["paper_40core_seconds_per_query"] = 0.049
     hk["paper_1thread_seconds_per_query"] = 0.01
+    nb["paper_40core_seconds_per_query"] = 0.040
+    nb["paper_1thread_seconds_per_query"] = 0.01
     return {"workload": "torus%d_3dgrid_plain" % side, "n": g.n, "arcs": g.arcs, "hkpr": hk,
+            "nibble": nb,
             "alpha": 0.01, "eps": 1e-7, "queries": nq, "seconds_per_query": per,
             "queries_per_s": nq / el, "edges_per_s": acc["edges"] / el,
             "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
@@ -524,15 +552,17 @@ def main():
         log("rules: optimized %.2f ms/query, original %.2f ms/query (%.2fx), pushes x%.2f" % (
             rules["optimized"]["ms_per_query"], rules["original"]["ms_per_query"],
             rules["speedup_optimized"], rules["push_ratio"]))
-    hkpr = bench_hkpr(plc, synth, g, plain["seeds"]) if plain else None
+    hkpr, nibble = bench_hkpr(plc, synth, g, plain["seeds"]) if plain else (None, None)
     if hkpr:
-        log("hkpr: %.2f ms/query, %.3g edges/s" % (hkpr["seconds_per_query"] * 1e3,
-                                                  hkpr["edges_per_s"]))
+        log("hkpr: %.2f ms/query, %.3g edges/s; nibble: %.2f ms/query, %.3g edges/s" % (
+            hkpr["seconds_per_query"] * 1e3, hkpr["edges_per_s"],
+            nibble["seconds_per_query"] * 1e3, nibble["edges_per_s"]))
     grid = bench_grid3d(plc, synth) if want("grid3d") else None
     if grid:
-        log("grid3d: %.2f ms per query (%.0fx the paper's 40-core time); HK-PR %.2f ms" % (
-            grid["seconds_per_query"] * 1e3, grid["speedup_vs_paper_40core"],
-            grid["hkpr"]["seconds_per_query"] * 1e3))
+        log("grid3d: %.2f ms per query (%.0fx the paper's 40-core time); HK-PR %.2f ms; "
+            "Nibble %.2f ms" % (grid["seconds_per_query"] * 1e3, grid["speedup_vs_paper_40core"],
+                                grid["hkpr"]["seconds_per_query"] * 1e3,
+                                grid["nibble"]["seconds_per_query"] * 1e3))
     big = bench_large(plc, synth) if args.only == "large" else None
     if big:
         log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
@@ -578,6 +608,7 @@ def main():
         out["rules"] = rules
     if hkpr:
         out["hkpr"] = hkpr
+        out["nibble"] = nibble
     if srv:
         out["serving"] = srv
     work = []
