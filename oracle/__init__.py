@@ -84,6 +84,10 @@ def _load():
         lib.oracle_sweep_bruteforce.restype = C.c_int
         lib.oracle_sweep_z.argtypes = [C.c_int64, P, P, P, C.c_int64, P, P, P, P, P, P]
         lib.oracle_sweep_z.restype = C.c_int
+        lib.oracle_prnibble_beta.argtypes = [C.c_int64, P, P, C.c_int32, C.c_double, C.c_double,
+                                             C.c_int32, C.c_double, C.c_int64, P, P,
+                                             C.POINTER(_PushStats), C.POINTER(C.c_double)]
+        lib.oracle_prnibble_beta.restype = C.c_int
         lib.oracle_nibble.argtypes = [C.c_int64, P, P, C.c_int32, C.c_double, C.c_int32, P,
                                       C.POINTER(_NbStats)]
         lib.oracle_nibble.restype = C.c_int
@@ -278,3 +282,34 @@ def nibble(off, nbr, seed, eps: float, T: int) -> NibbleResult:
     if rc < 0:
         raise ValueError("oracle_nibble rejected its input (code %d)" % rc)
     return NibbleResult(p, st.iterations, st.pushes, st.edges, st.support, st.min_rel_gap)
+
+
+@dataclass
+class BetaResult:
+    p: np.ndarray
+    r: np.ndarray
+    rounds: int
+    pushes: int
+    edges: int
+    support: int
+    min_rel_gap: float     # closest approach of a threshold decision to its threshold
+    min_sel_gap: float     # closest relative gap between the last chosen and first unchosen key
+    status: int
+
+
+def prnibble_beta(off, nbr, seed, alpha: float, eps: float, beta: float, rule: int = RULE_OPT,
+                  max_rounds: int = 1 << 30) -> BetaResult:
+    """PR-Nibble pushing only the top beta fraction of the active set by r/d
+    each round (end of Sec. 3.3)."""
+    off, nbr, n = _csr(off, nbr)
+    p = np.zeros(n, np.float64)
+    r = np.zeros(n, np.float64)
+    st = _PushStats()
+    gap = C.c_double()
+    rc = _load().oracle_prnibble_beta(n, _ptr(off), _ptr(nbr), int(seed), float(alpha), float(eps),
+                                      int(rule), float(beta), int(max_rounds), _ptr(p), _ptr(r),
+                                      C.byref(st), C.byref(gap))
+    if rc < 0:
+        raise ValueError("oracle_prnibble_beta rejected its input (code %d)" % rc)
+    return BetaResult(p, r, st.rounds, st.pushes, st.edges, st.support, st.min_rel_gap, gap.value,
+                      rc)

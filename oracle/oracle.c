@@ -632,3 +632,110 @@ int oracle_nibble(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x, 
   free(pn); free(F); free(S); free(G); free(mark);
   return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * PR-Nibble, beta variant (end of Sec. 3.3): each round pushes only the
+ * ceil(beta |S|) vertices of the active set S = {v : r[v] >= eps d(v)} with
+ * the largest r[v]/d(v) (ties by ascending id), with the round-synchronous
+ * updates of Fig. alg:pr-nibble2 among them; every vertex still at or above
+ * its threshold afterwards is active in the next round.  beta = 1 is
+ * PR-Nibble itself.
+ * ------------------------------------------------------------------------ */
+
+typedef struct { double key; int32_t id; } beta_item;
+
+static int cmp_beta(const void* a, const void* b) {
+  const beta_item* x = (const beta_item*)a;
+  const beta_item* y = (const beta_item*)b;
+  if (x->key > y->key) return -1;
+  if (x->key < y->key) return 1;
+  return x->id < y->id ? -1 : (x->id > y->id);
+}
+
+int oracle_prnibble_beta(int64_t n, const int64_t* off, const int32_t* nbr, int32_t x,
+                         double alpha, double eps, int32_t rule, double beta, int64_t max_rounds,
+                         double* p, double* r, oracle_push_stats* st, double* min_sel_gap) {
+  if (n <= 0 || !off || !nbr || !p || !r || !st || !min_sel_gap) return ORACLE_E_INVALID;
+  if (x < 0 || x >= n || deg_of(off, x) <= 0) return ORACLE_E_INVALID;
+  if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0) || !isfinite(eps)) return ORACLE_E_INVALID;
+  if (!(beta > 0.0 && beta <= 1.0)) return ORACLE_E_INVALID;
+  if (rule != ORACLE_RULE_OPT && rule != ORACLE_RULE_ORIG) return ORACLE_E_INVALID;
+  double cs, cn, keep;
+  rule_constants(rule, alpha, &cs, &cn, &keep);
+  beta_item* S = (beta_item*)malloc(sizeof(beta_item) * (size_t)n);
+  double* rho = (double*)malloc(sizeof(double) * (size_t)n);
+  int32_t* act = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);   /* active set */
+  int32_t* cand = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  uint8_t* mark = (uint8_t*)calloc((size_t)n, 1);
+  if (!S || !rho || !act || !cand || !mark) {
+    free(S); free(rho); free(act); free(cand); free(mark);
+    return ORACLE_E_NOMEM;
+  }
+  memset(st, 0, sizeof(*st));
+  st->min_rel_gap = INFINITY;
+  *min_sel_gap = INFINITY;
+  for (int64_t v = 0; v < n; v++) { p[v] = 0.0; r[v] = 0.0; }
+  r[x] = 1.0;
+  int64_t na = 1;
+  act[0] = x;   /* the seed is active in the first round whatever its threshold */
+  int status = ORACLE_OK;
+  while (na > 0) {
+    if (st->rounds >= max_rounds) { status = ORACLE_LIMIT; break; }
+    /* rank the active set by r/d, take the top ceil(beta |S|) */
+    for (int64_t i = 0; i < na; i++) {
+      S[i].key = r[act[i]] / (double)deg_of(off, act[i]);
+      S[i].id = act[i];
+    }
+    qsort(S, (size_t)na, sizeof(beta_item), cmp_beta);
+    int64_t k = (int64_t)ceil(beta * (double)na);
+    if (k < 1) k = 1;
+    if (k > na) k = na;
+    if (k < na && S[k - 1].key > 0.0) {
+      const double g = (S[k - 1].key - S[k].key) / S[k - 1].key;
+      if (g < *min_sel_gap) *min_sel_gap = g;
+    }
+    if (k > st->max_frontier) st->max_frontier = (int32_t)k;
+    /* round-synchronous push of the chosen k */
+    for (int64_t i = 0; i < k; i++) rho[i] = r[S[i].id];
+    int64_t nc = 0;
+    for (int64_t i = 0; i < k; i++) {
+      const int32_t v = S[i].id;
+      if (p[v] == 0.0) st->support++;
+      p[v] = p[v] + cs * rho[i];
+      r[v] = keep * rho[i];
+      if (!mark[v]) { mark[v] = 1; cand[nc++] = v; }
+    }
+    for (int64_t i = 0; i < k; i++) {
+      const int32_t v = S[i].id;
+      const int64_t d = deg_of(off, v);
+      st->edges += d;
+      const double c = (cn * rho[i]) / (double)d;
+      for (int64_t e = off[v]; e < off[v + 1]; e++) {
+        const int32_t w = nbr[e];
+        r[w] = r[w] + c;
+        if (!mark[w]) { mark[w] = 1; cand[nc++] = w; }
+      }
+    }
+    st->pushes += k;
+    st->rounds++;
+    /* next active set: the unchosen active vertices (still above threshold)
+       and every touched vertex at or above its threshold */
+    for (int64_t i = k; i < na; i++) {
+      const int32_t v = S[i].id;
+      if (!mark[v]) { mark[v] = 1; cand[nc++] = v; }
+    }
+    int64_t m = 0;
+    for (int64_t i = 0; i < nc; i++) {
+      const int32_t w = cand[i];
+      mark[w] = 0;
+      const double thr = eps * (double)deg_of(off, w);
+      const double gap = fabs(r[w] - thr) / thr;
+      if (gap < st->min_rel_gap) st->min_rel_gap = gap;
+      if (r[w] >= thr) act[m++] = w;
+    }
+    na = m;
+  }
+  st->status = status;
+  free(S); free(rho); free(act); free(cand); free(mark);
+  return status;
+}
