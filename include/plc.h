@@ -231,6 +231,20 @@ plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, double eps, 
                           uint64_t* id, plc_result_info* info);
 
 /*
+ * Plain path, the beta variant of PR-Nibble (end of Sec. 3.3): every round
+ * pushes only the ceil(beta |S|) vertices of the active set S = {v : r[v] >=
+ * eps d(v)} with the largest r[v]/d(v) (ties by ascending id), with the
+ * round-synchronous updates of *q's rule among them; the others stay active.
+ * beta in (0, 1]; beta = 1 is plc_run's algorithm.  *q as for plc_run (one
+ * query); *id, *info as for plc_run.  Rounds are launched directly (not
+ * replayed as graphs).  Returns PLC_OK (also when max_rounds stopped the
+ * push: info->status is then PLC_E_LIMIT), PLC_E_INVALID (bad query or
+ * beta; nothing runs), PLC_E_NOMEM (no room for the result) or PLC_E_HIP.
+ */
+plc_status plc_run_beta(plc_ctx* ctx, plc_graph* g, const plc_query* q, double beta,
+                        uint64_t* id, plc_result_info* info);
+
+/*
  * Batched path.  Many queries advance together: every global step runs one
  * PR-Nibble round for all admitted queries in the same kernel launches, and
  * the queries whose frontier emptied are swept together.  Results are the

@@ -36,6 +36,7 @@ PLC_STATE_COMPACT = 1
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
            "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_run_nibble",
+           "plc_run_beta",
            "plc_result_info_get",
            "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                           C.POINTER(plc_result_info)], I32),
         "plc_run_nibble": ([P, P, I32, C.c_double, I32, C.POINTER(U64),
                             C.POINTER(plc_result_info)], I32),
+        "plc_run_beta": ([P, P, C.POINTER(plc_query), C.c_double, C.POINTER(U64),
+                          C.POINTER(plc_result_info)], I32),
         "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
         "plc_result_copy": ([P, U64, P, P, P, P], I32),
         "plc_release": ([P, U64], I32),
@@ -329,6 +332,19 @@ class Context:
                                      C.byref(qid), C.byref(info))
         if check and rc != PLC_OK:
             raise PlcError(rc, "plc_run_nibble")
+        return qid.value, info.as_dict()
+
+    def run_beta(self, g: Graph, seed: int, alpha: float, eps: float, beta: float,
+                 rule=PLC_RULE_OPT, check: bool = True):
+        """Plain path: PR-Nibble pushing the top beta fraction of the active
+        set by r/d each round.  Returns (id, info)."""
+        qa = self.queries([int(seed)], alpha, eps, rule)
+        qid = C.c_uint64()
+        info = plc_result_info()
+        rc = self.lib.plc_run_beta(self.handle, g.handle, qa, float(beta), C.byref(qid),
+                                   C.byref(info))
+        if check and rc != PLC_OK:
+            raise PlcError(rc, "plc_run_beta")
         return qid.value, info.as_dict()
 
     # ---- batched path

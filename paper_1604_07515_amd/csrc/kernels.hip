@@ -50,7 +50,7 @@ __global__ void k_graph_init(PlainArgs a) {
 
 // Seed initialisation (Fig. alg:pr-nibble: r = {(x,1)}, Frontier = {x}).
 __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alpha, double eps,
-                             int32_t max_rounds) {
+                             int32_t max_rounds, double beta) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Ctl* c = a.ctl;
   if (rule == 1) {  // original rule
@@ -68,6 +68,9 @@ __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alp
   c->seed = seed;
   c->rule = rule;
   c->max_rounds = max_rounds;
+  c->beta = beta;
+  c->beta_nf = 0;
+  c->beta_k = 0;
   c->round = 0;
   c->cnt[0] = 1;
   c->cnt[1] = 0;
@@ -116,6 +119,9 @@ __global__ void k_query_init_set(PlainArgs a, int32_t nseeds, int32_t rule, doub
     c->seed = a.fbuf0[0];
     c->rule = rule;
     c->max_rounds = max_rounds;
+    c->beta = 1.0;
+    c->beta_nf = 0;
+    c->beta_k = 0;
     c->round = 0;
     c->cnt[0] = nseeds;
     c->cnt[1] = 0;
@@ -587,6 +593,80 @@ __global__ __launch_bounds__(kBlock) void k_hk_clear(PlainArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- beta variant
+// PR-Nibble pushing the top beta fraction of the active set by r/d per round
+// (end of Sec. 3.3).  The frontier holds the whole active set; before the
+// round it is ranked with the sweep's sort (keys: bit-inverted r/d, ties by
+// ascending id) and the top k = ceil(beta |F|) move to its front as the
+// round's frontier; after the round the other |F| - k, still at or above
+// their thresholds (their r only grew), join the next frontier.
+
+// Sort keys of the active set (count in N; 0 when the push has ended).
+__global__ __launch_bounds__(kBlock) void k_beta_keys(PlainArgs a) {
+  Ctl* c = a.ctl;
+  int t, nf;
+  if (!push_active(c, a.n, &t, &nf) || t >= c->max_rounds) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { c->N = 0; c->beta_nf = 0; }
+    return;
+  }
+  const int32_t* F = (t & 1) ? a.fbuf1 : a.fbuf0;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nf; i += gridDim.x * kBlock) {
+    const int32_t v = F[i];
+    const VRec rec = a.vr[v];
+    SortElem e;
+    e.key = ~(unsigned long long)__double_as_longlong(rec.r / (double)rec.deg);
+    e.id = v;
+    e.seg = 0;
+    a.sbuf[0][i] = e;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->N = nf;
+    c->sort_flip = 0;
+    c->beta_nf = nf;
+  }
+}
+
+// Ranked active set back into the frontier buffer; the round's frontier is
+// its first k entries.
+__global__ __launch_bounds__(kBlock) void k_beta_select(PlainArgs a) {
+  Ctl* c = a.ctl;
+  const int nf = c->beta_nf;
+  if (nf <= 0) return;
+  const int t = c->round;
+  int32_t* F = (t & 1) ? a.fbuf1 : a.fbuf0;
+  const SortElem* el = a.sbuf[c->sort_flip & 1];
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < nf; i += gridDim.x * kBlock) F[i] = el[i].id;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    long long k = (long long)ceil(c->beta * (double)nf);
+    if (k < 1) k = 1;
+    if (k > nf) k = nf;
+    c->beta_k = (int32_t)k;
+    c->cnt[t & 1] = (int32_t)k;
+  }
+}
+
+// After the round: the unpushed part of the ranked set joins the next
+// frontier (one counter atomic per workgroup step).
+__global__ __launch_bounds__(kBlock) void k_beta_carry(PlainArgs a) {
+  Ctl* c = a.ctl;
+  const int nf = c->beta_nf, k = c->beta_k;
+  if (nf <= k) return;
+  const int t = c->round;              // the round just closed was t - 1
+  const int32_t* F = ((t - 1) & 1) ? a.fbuf1 : a.fbuf0;
+  int32_t* Fn = (t & 1) ? a.fbuf1 : a.fbuf0;
+  __shared__ int s_base;
+  for (int i0 = k + blockIdx.x * kBlock; i0 < nf; i0 += gridDim.x * kBlock) {
+    const int m = nf - i0 < kBlock ? nf - i0 : kBlock;
+    if (threadIdx.x == 0) s_base = atomicAdd(&c->cnt[t & 1], m);
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      const long long slot = (long long)s_base + threadIdx.x;
+      if (slot < a.n) Fn[slot] = F[i0 + threadIdx.x]; else c->fault = 1;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- sweep
 
 // The sweep may start once the frontier is empty (or the watchdog fired).
@@ -935,9 +1015,9 @@ hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a) {
 }
 
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
-                             double alpha, double eps, int32_t max_rounds) {
+                             double alpha, double eps, int32_t max_rounds, double beta) {
   hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, a, seed, rule, alpha, eps,
-                     max_rounds);
+                     max_rounds, beta);
   return hipGetLastError();
 }
 
@@ -947,6 +1027,27 @@ hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nsee
   if (grid > 1024) grid = 1024;
   hipLaunchKernelGGL(k_query_init_set, dim3(grid), dim3(kBlock), 0, s, a, nseeds, rule, alpha, eps,
                      max_rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_beta_pre(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count) {
+  hipLaunchKernelGGL(k_beta_keys, dim3(grid), dim3(kBlock), 0, s, a);
+  SortArgs sa;
+  sa.buf[0] = a.sbuf[0];
+  sa.buf[1] = a.sbuf[1];
+  sa.count = &a.ctl->N;
+  sa.flip = &a.ctl->sort_flip;
+  sa.done = &a.ctl->done[DONE_SORT];
+  sa.active = nullptr;
+  sa.active_value = 0;
+  hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_beta_select, dim3(grid), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_beta_post(hipStream_t s, const PlainArgs& a, int grid) {
+  hipLaunchKernelGGL(k_beta_carry, dim3(grid), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -557,13 +557,15 @@ static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count
 // carries start and stop events on its own dispatch timestamps
 // (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk).
 
-static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
+static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, bool beta) {
   const PlainArgs& a = g->args;
   hipStream_t s = ctx->stream;
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
+  const int gw = shape(g->plain_sweep, ctx->grid_sweep);
   for (int i = 0; i < rounds; i++) {
     hipError_t r;
+    if (beta && (r = plc::launch_beta_pre(s, a, gw, g->n)) != hipSuccess) return r;
     if (ctx->timing) {
       size_t k = (size_t)i;
       while (ctx->ev_self.size() <= k) ctx->ev_self.emplace_back();
@@ -579,6 +581,7 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds) {
       if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
       if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
     }
+    if (beta && (r = plc::launch_beta_post(s, a, gw)) != hipSuccess) return r;
   }
   return hipSuccess;
 }
@@ -590,7 +593,7 @@ static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
 // distinct seeds in set (q.seed is then ignored).
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
                           plc_result_info* info_out, const int32_t* set = nullptr,
-                          int32_t nset = 0) {
+                          int32_t nset = 0, double beta = 1.0) {
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   if (set) {
@@ -599,8 +602,9 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
                                            ctx->opt.max_rounds));
   } else {
     HIPCHK(ctx, plc::launch_query_init(s, a, q.seed, (int32_t)q.rule, q.alpha, q.eps,
-                                       ctx->opt.max_rounds));
+                                       ctx->opt.max_rounds, beta));
   }
+  const bool use_beta = beta < 1.0;
   // Push: chunks of rounds, each followed by a read-back of the control
   // block.  Rounds queued past the end of the push exit at once but still
   // cost a dispatch each, so the first chunk is the lower quartile of the
@@ -617,11 +621,13 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   for (;;) {
     const int R = chunk;
     // while timing is on, rounds are launched directly (graphs carry no events)
-    Captured* cg = ctx->use_graphs && !ctx->timing ? plain_chunk_graph(ctx, g, R) : nullptr;
+    // (the beta variant's rounds are launched directly too)
+    Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta ? plain_chunk_graph(ctx, g, R)
+                                                                : nullptr;
     if (cg)
       HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
     else
-      HIPCHK(ctx, queue_rounds(ctx, g, R));
+      HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta));
     const EventPair* ev_s = ctx->ev_self.data();
     const EventPair* ev_c = ctx->ev_scatter.data();
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -841,6 +847,21 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
   plc_status st = sweep_and_record(ctx, g, id, info);
   if (st == PLC_E_HIP) return st;
   if (hipStreamSynchronize(s) != hipSuccess) {
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  return st;
+}
+
+extern "C" plc_status plc_run_beta(plc_ctx* ctx, plc_graph* g, const plc_query* q, double beta,
+                                   uint64_t* id, plc_result_info* info) {
+  if (!ctx || !g || !ctx->graphs.count(g) || !q) return PLC_E_INVALID;
+  if (!query_ok(g, *q) || !(beta > 0.0 && beta <= 1.0)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  (void)hipSetDevice(ctx->device);
+  plc_status st = run_one(ctx, g, *q, id, info, nullptr, 0, beta);
+  if (st == PLC_E_HIP) return st;
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
     ctx->broken = true;
     return PLC_E_HIP;
   }

@@ -88,6 +88,10 @@ struct __align__(64) Ctl {
   int32_t hk_N;
   int32_t hk_tlc[3];
   double hk_t, hk_A;
+  // beta variant of PR-Nibble (end of Sec. 3.3): the fraction of the active
+  // set pushed per round, and this round's active count and pushed count
+  double beta;
+  int32_t beta_nf, beta_k;
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
@@ -148,7 +152,12 @@ static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
-                             double alpha, double eps, int32_t max_rounds);
+                             double alpha, double eps, int32_t max_rounds, double beta = 1.0);
+// beta variant: before a round, rank the active frontier by r/d and keep the
+// top ceil(beta |F|) in front as the round's frontier; after it, append the
+// rest to the next frontier (max_count bounds the frontier for the sort)
+hipError_t launch_beta_pre(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count);
+hipError_t launch_beta_post(hipStream_t s, const PlainArgs& a, int grid);
 // seed set: the nseeds distinct seeds are already in a.fbuf0
 hipError_t launch_query_init_set(hipStream_t s, const PlainArgs& a, int32_t nseeds, int32_t rule,
                                  double alpha, double eps, int32_t max_rounds);
