@@ -324,6 +324,23 @@ def bench_rules(plc, synth, g, seeds):
                      "edges_per_query": float(np.mean([r["edges"] for r in rows])),
                      "rounds_per_query": float(np.mean([r["rounds"] for r in rows])),
                      "phi": [r["phi"] for r in rows]}
+    # the beta variant (end of Sec. 3.3): only the top fraction of the active
+    # set by r/d is pushed per round (rounds launched directly)
+    for beta in (0.5, 0.25):
+        for timed in (False, True):
+            rows = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for x in seeds:
+                qid, info = ctx.run_beta(hg, int(x), 0.01, 1e-7, beta)
+                ctx.release(qid)
+                rows.append(info)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        out["beta_%g" % beta] = {"ms_per_query": el * 1e3 / len(seeds),
+                                  "pushes_per_query": float(np.mean([r["pushes"] for r in rows])),
+                                  "rounds_per_query": float(np.mean([r["rounds"] for r in rows])),
+                                  "phi": [r["phi"] for r in rows]}
     ctx.close()
     po, pr = np.array(out["optimized"]["phi"]), np.array(out["original"]["phi"])
     return {"workload": "rmat22_ef16_plain_16seeds", "alpha": 0.01, "eps": 1e-7,
@@ -334,7 +351,13 @@ def bench_rules(plc, synth, g, seeds):
             "phi_optimized_over_original": {"median": float(np.median(po / pr)),
                                             "min": float(np.min(po / pr)),
                                             "max": float(np.max(po / pr))},
-            "paper": "sequential, optimized rule 1.4-6.4x faster at the same conductance"}
+            "paper": "sequential, optimized rule 1.4-6.4x faster at the same conductance",
+            "beta": {("%g" % b): {"ms_per_query": out["beta_%g" % b]["ms_per_query"],
+                                  "pushes_per_query": out["beta_%g" % b]["pushes_per_query"],
+                                  "rounds_per_query": out["beta_%g" % b]["rounds_per_query"],
+                                  "phi_median_over_beta1": float(np.median(
+                                      np.array(out["beta_%g" % b]["phi"]) / po))}
+                     for b in (0.5, 0.25)}}
 
 
 def algo_timed(run, seeds, params):
