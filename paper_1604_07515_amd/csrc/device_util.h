@@ -160,6 +160,27 @@ __device__ __forceinline__ int scan_ticket(ScanSite* site, int nblk, int* sh, bo
 // Last-workgroup detection: true in exactly one workgroup, after all others
 // of the launch called it.  with_acquire makes the other workgroups' global
 // writes visible to the last one (device-scope fences).
+// last_block_of: the same among the first `members` workgroups only (the
+// others must not call it).
+__device__ __forceinline__ bool last_block_of(unsigned* done, int* sh, bool with_acquire,
+                                              unsigned members) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (with_acquire) __threadfence();
+    unsigned prev = atomicAdd(done, 1u);
+    int last = prev == members - 1;
+    if (last) {
+      if (with_acquire) __threadfence();
+      *done = 0;
+    }
+    *sh = last;
+  }
+  __syncthreads();
+  int l = *sh;
+  __syncthreads();
+  return l != 0;
+}
+
 __device__ __forceinline__ bool last_block(unsigned* done, int* sh, bool with_acquire) {
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -232,13 +232,24 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
   const bool hk_last = HK && t + 1 == c->hk_N;
   const double hk_t = HK ? c->hk_t : 0.0;
   const int nblk = (nf + kScanBlock - 1) / kScanBlock;
+  // a frontier of one scan block is handled by workgroup 0 alone, with no
+  // ticket and no look-back (its exclusive prefix is 0; no descriptor is
+  // published and the scan site is left as it was)
+  const bool solo = nblk == 1;
+  if (solo && blockIdx.x != 0) return;
   if (threadIdx.x == 0) { s_nsup = 0; s_nstay = 0; }
   __syncthreads();
 
-  for (;;) {
-    bool last;
-    int b = scan_ticket(site, nblk, s_tk, &last);
-    if (b >= nblk) break;
+  for (int pass = 0;; pass++) {
+    int b;
+    if (solo) {
+      if (pass > 0) break;
+      b = 0;
+    } else {
+      bool last;
+      b = scan_ticket(site, nblk, s_tk, &last);
+      if (b >= nblk) break;
+    }
     // each thread takes kScanItems consecutive entries: one workgroup scan
     // of the per-thread sums, then a serial prefix inside the thread
     const int i0 = b * kScanBlock + (int)threadIdx.x * kScanItems;
@@ -281,7 +292,9 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
     }
     long long agg;
     const long long ex = block_excl_scan<kBlock>(dsum, &agg, sh);
-    if (threadIdx.x < 64) {
+    if (solo) {
+      if (threadIdx.x == 0) s_excl = 0;
+    } else if (threadIdx.x < 64) {
       const long long ex0 = scan_lookback(desc, b, agg, &c->fault);
       if (threadIdx.x == 0) s_excl = ex0;
     }
@@ -362,12 +375,12 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = blockIdx.x * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
-  // a workgroup without tiles (large grids, small rounds) only takes part in
-  // the round's closing count
-  if (tb < te) {
-    if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
-    __syncthreads();
-  }
+  // workgroups without tiles (large grids, small rounds) leave at once; the
+  // round is closed by the last of the `busy` ones (at least workgroup 0)
+  const int busy = per > 0 ? (ntiles + per - 1) / per : 1;
+  if ((int)blockIdx.x >= busy) return;
+  if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
+  __syncthreads();
 
   for (int tile = tb; tile < te; tile++) {
     const long long e0 = (long long)tile * kEdgeTile;
@@ -440,7 +453,7 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
       block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
     }
   }
-  if (last_block(&c->done[DONE_SCATTER], &s_last, false)) {
+  if (last_block_of(&c->done[DONE_SCATTER], &s_last, false, (unsigned)busy)) {
     if (threadIdx.x == 0) {
       c->pushes += nf;
       c->edges += E;
