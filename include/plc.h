@@ -124,6 +124,12 @@ typedef struct {
   int64_t vol;        /* vol(S_kstar)                                   */
   double phi;         /* conductance of S_kstar                         */
   int64_t r_nnz;      /* nonzeros of r at exit                          */
+  /* plain path only (0 elsewhere): self launches that did work, and the
+   * rounds and edges among `rounds` and `edges` that a self launch ran on
+   * its own (small frontiers, one workgroup, no scatter launch) */
+  int32_t launches;
+  int32_t loop_rounds;
+  int64_t loop_edges;
 } plc_result_info;
 
 /* Status code to a static string. */

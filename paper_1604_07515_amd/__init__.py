@@ -70,7 +70,8 @@ class plc_result_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("rounds", C.c_int32), ("pushes", C.c_int64),
                 ("edges", C.c_int64), ("support", C.c_int64), ("kstar", C.c_int64),
                 ("cut", C.c_int64), ("vol", C.c_int64), ("phi", C.c_double),
-                ("r_nnz", C.c_int64)]
+                ("r_nnz", C.c_int64), ("launches", C.c_int32), ("loop_rounds", C.c_int32),
+                ("loop_edges", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -474,4 +475,4 @@ def plain_arena_bytes(n: int, arcs: int) -> int:
     per_arc = 4               # neighbour ids
     tiles = 4 * (arcs // 1024 + 2)
     scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
-    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20) + 8 * 1025)
+    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20) + 8 * 1025 + 2048)

@@ -48,6 +48,14 @@ __global__ void k_graph_init(PlainArgs a) {
   }
 }
 
+__device__ __forceinline__ void reset_round_book(Ctl* c) {
+  c->selfed = -1;
+  c->steps = 0;
+  c->loop_rounds = 0;
+  c->loop_pushes = 0;
+  c->loop_edges = 0;
+}
+
 // Seed initialisation (Fig. alg:pr-nibble: r = {(x,1)}, Frontier = {x}).
 __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alpha, double eps,
                              int32_t max_rounds, double beta) {
@@ -91,6 +99,7 @@ __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alp
   c->best_den = 0;
   c->kstar = 0;
   c->phi = 0.0;
+  reset_round_book(c);
   a.fbuf0[0] = seed;
   a.touched[0] = seed;
   a.vr[seed].r = 1.0;
@@ -142,6 +151,8 @@ __global__ void k_query_init_set(PlainArgs a, int32_t nseeds, int32_t rule, doub
     c->best_den = 0;
     c->kstar = 0;
     c->phi = 0.0;
+    reset_round_book(c);
+  reset_round_book(c);
     c->status = ST_PUSH;
   }
   const double share = 1.0 / (double)nseeds;
@@ -195,7 +206,7 @@ __device__ __forceinline__ double* hk_res(const PlainArgs& a, int k, int32_t v) 
 //     rho / 2 kept per entry for the scatter, which adds it to the vertex's
 //     own next value; the same clearing as HK-PR.
 template <int MODE>
-__device__ __forceinline__ void self_body(const PlainArgs& a) {
+__device__ __forceinline__ void self_body(const PlainArgs& a, int slot) {
   constexpr bool HK = MODE == kModeHK;
   constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
@@ -313,16 +324,15 @@ __device__ __forceinline__ void self_body(const PlainArgs& a) {
       const long long tot = s_excl + agg;
       c->etotal = tot;
       c->ntiles = (int)((tot + kEdgeTile - 1) / kEdgeTile);
+      c->selfed = t;
+      c->steps += 1;
+      if (slot >= 0) a.work_log[2 * slot] = 1;
     }
     if (MODE != kModeNB)
       block_flush(&c->support_cnt, a.support, a.n, s_sup, &s_nsup, &s_base, &c->fault);
     if (!opt) block_flush(cntn, Fn, a.n, s_stay, &s_nstay, &s_base, &c->fault);
   }
 }
-
-__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a) { self_body<kModePR>(a); }
-__global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<kModeHK>(a); }
-__global__ __launch_bounds__(kBlock) void k_nb_self(PlainArgs a) { self_body<kModeNB>(a); }
 
 // Threshold decision for one addition of c to r[w] that returned `old`:
 // crossing appends w to the next frontier, first touch to the touched list.
@@ -331,6 +341,230 @@ __device__ __forceinline__ void decide(double old, double c, double thr, int32_t
   if (old < thr && old + c >= thr) s_fn[atomicAdd(s_nfn, 1)] = w;
   if (__double_as_longlong(old) == 0) s_tv[atomicAdd(s_ntv, 1)] = w;
 }
+
+template <typename T>
+__device__ __forceinline__ T ld_agent(T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Append the n values of buf at dst[base..] (capacity cap) and, where
+// mirror is set, at mirror[base..] below kScanBlock.  The caller's
+// workgroup is the only writer of the list, so the base is its own count.
+__device__ __forceinline__ void local_append(int32_t* dst, int64_t cap, int32_t* mirror,
+                                             const int32_t* buf, int n, int base, int* fault) {
+  for (int j = threadIdx.x; j < n; j += kBlock) {
+    const long long slot = (long long)base + j;
+    if (slot < cap) dst[slot] = buf[j]; else *fault = 1;
+    if (mirror && slot < kScanBlock) mirror[slot] = buf[j];
+  }
+}
+
+// Rounds with small frontiers (Figs. alg:pr-nibble / alg:pr-nibble2, the
+// same updates and arithmetic as k_self + k_scatter), run back to back by
+// workgroup 0 alone: the frontier (at most kScanBlock vertices) and its
+// entries stay in LDS, list lengths are kept locally, and only the FP64
+// additions into r go to memory as device-scope atomics.  r of the frontier
+// is read and written with device-scope atomic accesses too, so that within
+// the launch they are ordered with those additions.  It stops when the
+// frontier empties or outgrows a scan block, when a round has more than
+// kLoopEdges edges (that round's entries are then built in memory for the
+// next scatter launch, exactly as k_self builds them), at the round limit, or
+// after kLoopMaxRounds rounds.
+__device__ void loop_rounds(const PlainArgs& a, int slot, int t, int nf) {
+  Ctl* c = a.ctl;
+  __shared__ int32_t s_F[2][kScanBlock];  // this round's and the next round's frontier
+  __shared__ int32_t s_est[kScanBlock];   // entry i: first edge in the round's edge sequence
+  __shared__ int64_t s_row[kScanBlock];   //          off[v]
+  __shared__ double s_cf[kScanBlock];     //          cn rho / d(v)
+  __shared__ int32_t s_fn[kLoopPass];     // crossings of one pass
+  __shared__ int32_t s_tv[kLoopPass];     // first touches of one pass
+  __shared__ int32_t s_sup[kScanBlock];
+  __shared__ int32_t s_stay[kScanBlock];
+  __shared__ long long sh[kBlock / 64 + 1];
+  __shared__ int s_nfn, s_ntv, s_nsup, s_nstay;
+  if (threadIdx.x == 0) {
+    s_nfn = 0;
+    s_ntv = 0;
+    s_nsup = 0;
+    s_nstay = 0;
+  }
+  __syncthreads();
+  const double cs = c->cs, cn = c->cn, keep = c->keep, eps = c->eps;
+  const bool opt = c->opt_rule != 0;
+  const int max_rounds = c->max_rounds;
+  const int64_t cap = a.n;
+  int tcnt = c->touched_cnt, scnt = c->support_cnt;
+  long long pushes = 0, edges = 0, E = 0;
+  int nnext = 0, cur = 0, rounds = 0;
+  bool selfed = false;
+  for (int it = 0;; it++) {
+    const int32_t* F = it > 0 ? s_F[cur] : (t & 1) ? a.fbuf1 : a.fbuf0;
+    int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
+    // vertexMap(Frontier, UpdateSelf) and the degree scan
+    const int i0 = (int)threadIdx.x * kScanItems;
+    int32_t dk[kScanItems];
+    double ck[kScanItems];
+    int64_t rk[kScanItems];
+    long long dsum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const int i = i0 + k;
+      int32_t d = 0;
+      ck[k] = 0.0;
+      rk[k] = 0;
+      if (i < nf) {
+        const int32_t v = F[i];
+        d = a.vr[v].deg;
+        double* rp = &a.vr[v].r;
+        const double rho = ld_agent(rp);
+        const double pold = a.p[v];
+        a.p[v] = pold + cs * rho;
+        const double nr = opt ? -0.0 : keep * rho;
+        st_agent(rp, nr);
+        ck[k] = (cn * rho) / (double)d;
+        rk[k] = a.off[v];
+        if (!opt && nr >= eps * (double)d) s_stay[atomicAdd(&s_nstay, 1)] = v;
+        if (pold == 0.0) s_sup[atomicAdd(&s_nsup, 1)] = v;
+      }
+      dk[k] = d;
+      dsum += d;
+    }
+    long long agg;
+    const long long ex = block_excl_scan<kBlock>(dsum, &agg, sh);
+    E = agg;
+    const int nstay = s_nstay, nsup = s_nsup;
+    local_append(a.support, cap, nullptr, s_sup, nsup, scnt, &c->fault);
+    local_append(Fn, cap, s_F[cur ^ 1], s_stay, nstay, 0, &c->fault);
+    scnt += nsup;
+    nnext = nstay;
+    if (E > kLoopEdges) {
+      // too large for one workgroup: entries in memory for the scatter launch
+      long long s = ex;
+#pragma unroll
+      for (int k = 0; k < kScanItems; k++) {
+        const int i = i0 + k;
+        if (i < nf) {
+          a.estart[i] = s;
+          a.rowp[i] = rk[k];
+          a.coef[i] = ck[k];
+          mark_tiles(a.tile_start, a.tile_cap, s, dk[k], i, &c->fault);
+        }
+        s += dk[k];
+      }
+      selfed = true;
+      break;
+    }
+    {
+      long long s = ex;
+#pragma unroll
+      for (int k = 0; k < kScanItems; k++) {
+        const int i = i0 + k;
+        if (i < nf) {
+          s_est[i] = (int32_t)s;
+          s_row[i] = rk[k];
+          s_cf[i] = ck[k];
+        }
+        s += dk[k];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) { s_nstay = 0; s_nsup = 0; }
+    // edgeMap(G, Frontier, UpdateNgh), kLoopPass edges per pass
+    constexpr int kPer = kLoopPass / kBlock;
+    for (long long base = 0; base < E; base += kLoopPass) {
+      int32_t w[kPer];
+      double cf[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; k++) {
+        const int rel = (int)base + k * kBlock + (int)threadIdx.x;
+        w[k] = -1;
+        cf[k] = 0.0;
+        if (rel < E) {
+          int lo = 0, hi = nf - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_est[mid] <= rel) lo = mid; else hi = mid - 1;
+          }
+          w[k] = a.nbr[s_row[lo] + (rel - s_est[lo])];
+          cf[k] = s_cf[lo];
+        }
+      }
+      int32_t dw[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; k++) dw[k] = w[k] >= 0 ? a.vr[w[k]].deg : 0;
+      double old[kPer];
+#pragma unroll
+      for (int k = 0; k < kPer; k++) old[k] = w[k] >= 0 ? unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]) : 0.0;
+#pragma unroll
+      for (int k = 0; k < kPer; k++)
+        if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dw[k], w[k], s_fn, &s_nfn, s_tv, &s_ntv);
+      __syncthreads();
+      const int nfn = s_nfn, ntv = s_ntv;
+      local_append(Fn, cap, s_F[cur ^ 1], s_fn, nfn, nnext, &c->fault);
+      local_append(a.touched, cap, nullptr, s_tv, ntv, tcnt, &c->fault);
+      nnext += nfn;
+      tcnt += ntv;
+      __syncthreads();
+      if (threadIdx.x == 0) { s_nfn = 0; s_ntv = 0; }
+      __syncthreads();
+    }
+    // the round is over (the barrier orders this round's LDS appends and
+    // count resets before the next round's, also when E is 0)
+    __syncthreads();
+    pushes += nf;
+    edges += E;
+    rounds += 1;
+    t += 1;
+    nf = nnext;
+    nnext = 0;
+    cur ^= 1;
+    if (nf == 0 || nf > kScanBlock || t >= max_rounds || it + 1 >= kLoopMaxRounds) break;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    c->touched_cnt = tcnt;
+    c->support_cnt = scnt;
+    c->pushes += pushes;
+    c->edges += edges;
+    c->loop_rounds += rounds;
+    c->loop_pushes += pushes;
+    c->loop_edges += edges;
+    c->steps += 1;
+    if (selfed) {
+      c->etotal = E;
+      c->ntiles = (int)((E + kEdgeTile - 1) / kEdgeTile);
+    }
+    c->cnt[(t + 1) & 1] = nnext;  // stays of a round left to the scatter launch
+    c->cnt[t & 1] = nf;
+    c->selfed = selfed ? t : -1;
+    c->round = t;
+    if (slot >= 0) a.work_log[2 * slot] = 1;
+  }
+}
+
+// The self launch of PR-Nibble.  A frontier of at most one scan block goes
+// to loop_rounds, run by the workgroup that arrives last: the loop rewrites
+// the control block, and by then every other workgroup has read the state
+// it decided on (the same as the loop's) and left.
+__global__ __launch_bounds__(kBlock) void k_self(PlainArgs a, int slot) {
+  Ctl* c = a.ctl;
+  const int32_t st = c->status;
+  const int32_t t = c->round;
+  int32_t nf = c->cnt[t & 1];
+  if ((int64_t)nf > a.n) nf = (int32_t)a.n;
+  if (st == ST_PUSH && nf > 0 && nf <= kScanBlock && t < c->max_rounds && c->beta >= 1.0) {
+    __shared__ int s_last;
+    if (last_block(&c->done[DONE_SELF], &s_last, false)) loop_rounds(a, slot, t, nf);
+    return;
+  }
+  self_body<kModePR>(a, slot);
+}
+__global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<kModeHK>(a, -1); }
+__global__ __launch_bounds__(kBlock) void k_nb_self(PlainArgs a) { self_body<kModeNB>(a, -1); }
 
 // edgeMap(G, Frontier, UpdateNgh) with the filter folded in.  Each
 // workgroup takes a contiguous range of edge tiles; every edge is one
@@ -347,13 +581,14 @@ __device__ __forceinline__ void decide(double old, double c, double thr, int32_t
 //     to list j+1; each entry's own rho / 2 is added by the workgroup whose
 //     tile holds the entry's first edge.
 template <int MODE>
-__device__ __forceinline__ void scatter_body(const PlainArgs& a) {
+__device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
   constexpr bool HK = MODE == kModeHK;
   constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
   if (HK ? t >= c->hk_N : t >= c->max_rounds) return;
+  if (c->selfed != t) return;  // no entries built for this round (a self loop stopped before it)
   __shared__ int32_t s_start[kEdgeTile + 1];
   __shared__ int64_t s_row[kEdgeTile + 1];
   __shared__ double s_coef[kEdgeTile + 1];
@@ -459,13 +694,16 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a) {
       c->edges += E;
       c->cnt[t & 1] = 0;
       c->round = t + 1;
+      if (slot >= 0) a.work_log[2 * slot + 1] = 1;
     }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a) { scatter_body<kModePR>(a); }
-__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<kModeHK>(a); }
-__global__ __launch_bounds__(kBlock) void k_nb_scatter(PlainArgs a) { scatter_body<kModeNB>(a); }
+__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a, int slot) {
+  scatter_body<kModePR>(a, slot);
+}
+__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<kModeHK>(a, -1); }
+__global__ __launch_bounds__(kBlock) void k_nb_scatter(PlainArgs a) { scatter_body<kModeNB>(a, -1); }
 
 // HK-PR initialisation (Fig. alg:hkpr: r = {(x, 1)}, Frontier = {x},
 // j = 0); level 0 touched only x.
@@ -500,6 +738,7 @@ __global__ void k_hk_init(PlainArgs a, int32_t x, int32_t N, double t, double A)
   c->best_den = 0;
   c->kstar = 0;
   c->phi = 0.0;
+  reset_round_book(c);
   c->hk_N = N;
   c->hk_t = t;
   c->hk_A = A;
@@ -545,6 +784,7 @@ __global__ void k_nb_init(PlainArgs a, int32_t x, double eps, int32_t T) {
   c->best_den = 0;
   c->kstar = 0;
   c->phi = 0.0;
+  reset_round_book(c);
   c->hk_N = 0;
   c->hk_tlc[0] = 1;
   c->hk_tlc[1] = 0;
@@ -1097,20 +1337,23 @@ hipError_t launch_hk_clear(hipStream_t s, const PlainArgs& a, int grid) {
   return hipGetLastError();
 }
 
-hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0, hipEvent_t t1) {
+hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0, hipEvent_t t1,
+                       int slot) {
+  if (slot >= kMaxChunk) return hipErrorInvalidValue;
   if (t0)
-    hipExtLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a);
+    hipExtLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a, slot);
   else
-    hipLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_self, dim3(grid), dim3(kBlock), 0, s, a, slot);
   return hipGetLastError();
 }
 
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0,
-                          hipEvent_t t1) {
+                          hipEvent_t t1, int slot) {
+  if (slot >= kMaxChunk) return hipErrorInvalidValue;
   if (t0)
-    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a);
+    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a, slot);
   else
-    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a, slot);
   return hipGetLastError();
 }
 

@@ -159,7 +159,8 @@ struct plc_ctx {
   std::set<plc_graph*> graphs;
   int num_cu = 256;
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
-  std::deque<int> round_hist;  // plain path: round counts of the last queries
+  std::deque<int> round_hist;  // plain path: working self launches of the last queries
+  std::vector<int32_t> work_log_h = std::vector<int32_t>(2 * plc::kMaxChunk);
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
   hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
   bool timing = false;
@@ -395,6 +396,7 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.hk_tl[1] = static_cast<int32_t*>(take(4 * N));
   a.hk_tl[2] = static_cast<int32_t*>(take(4 * N));
   a.hk_B = static_cast<double*>(take(8 * (size_t)(plc::kHkMaxLevels + 1)));
+  a.work_log = static_cast<int32_t*>(take(4 * 2 * (size_t)plc::kMaxChunk));
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -555,7 +557,8 @@ static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count
 
 // Queue `rounds` rounds as direct launches; with timing on, each kernel
 // carries start and stop events on its own dispatch timestamps
-// (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk).
+// (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk) and marks
+// a.work_log[2i] / [2i + 1] when it did work.
 
 static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, bool beta) {
   const PlainArgs& a = g->args;
@@ -572,9 +575,9 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, boo
       while (ctx->ev_scatter.size() <= k) ctx->ev_scatter.emplace_back();
       if ((r = ev_pair(ctx->ev_self[k])) != hipSuccess) return r;
       if ((r = ev_pair(ctx->ev_scatter[k])) != hipSuccess) return r;
-      if ((r = plc::launch_self(s, a, gs, ctx->ev_self[k].a, ctx->ev_self[k].b)) != hipSuccess)
+      if ((r = plc::launch_self(s, a, gs, ctx->ev_self[k].a, ctx->ev_self[k].b, i)) != hipSuccess)
         return r;
-      if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b)) !=
+      if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b, i)) !=
           hipSuccess)
         return r;
     } else {
@@ -605,10 +608,12 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
                                        ctx->opt.max_rounds, beta));
   }
   const bool use_beta = beta < 1.0;
-  // Push: chunks of rounds, each followed by a read-back of the control
-  // block.  Rounds queued past the end of the push exit at once but still
+  // Push: chunks of (self, scatter) launch pairs, each followed by a
+  // read-back of the control block.  A self launch may run several small
+  // rounds, and pairs queued past the end of the push exit at once but still
   // cost a dispatch each, so the first chunk is the lower quartile of the
-  // last queries' round counts and later chunks are short.
+  // last queries' counts of working self launches and later chunks are
+  // short.
   int queued = 0;
   int chunk = 16;
   if (!ctx->round_hist.empty()) {
@@ -616,7 +621,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     std::sort(hs.begin(), hs.end());
     chunk = hs[hs.size() / 4];
   }
-  chunk = std::max(2, std::min(256, chunk));
+  chunk = std::max(2, std::min(plc::kMaxChunk, chunk));
   Ctl& h = *ctx->ctl_host;
   for (;;) {
     const int R = chunk;
@@ -624,6 +629,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     // (the beta variant's rounds are launched directly too)
     Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta ? plain_chunk_graph(ctx, g, R)
                                                                 : nullptr;
+    if (ctx->timing) HIPCHK(ctx, hipMemsetAsync(a.work_log, 0, 4 * 2 * (size_t)R, s));
     if (cg)
       HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
     else
@@ -631,19 +637,26 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     const EventPair* ev_s = ctx->ev_self.data();
     const EventPair* ev_c = ctx->ev_scatter.data();
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (ctx->timing)
+      HIPCHK(ctx, hipMemcpyAsync(ctx->work_log_h.data(), a.work_log, 4 * 2 * (size_t)R,
+                                 hipMemcpyDeviceToHost, s));
     HIPCHK(ctx, hipStreamSynchronize(s));
     if (ctx->timing) {
-      // every round of an earlier chunk pushed (else the push would have
-      // ended there), so this chunk's pushing rounds are the first h.round - queued
-      const int ran = std::max(0, std::min(R, h.round - queued));
+      // only the launches that did work count (pairs past the end of the
+      // push, and scatters after a self launch that ran the rounds itself,
+      // exit at once)
       float ms = 0;
-      for (int i = 0; i < ran; i++) {
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ev_c[i].a, ev_c[i].b));
-        ctx->t_scatter.ms += ms;
-        ctx->t_scatter.launches++;
-        HIPCHK(ctx, hipEventElapsedTime(&ms, ev_s[i].a, ev_s[i].b));
-        ctx->t_self.ms += ms;
-        ctx->t_self.launches++;
+      for (int i = 0; i < R; i++) {
+        if (ctx->work_log_h[2 * i + 1]) {
+          HIPCHK(ctx, hipEventElapsedTime(&ms, ev_c[i].a, ev_c[i].b));
+          ctx->t_scatter.ms += ms;
+          ctx->t_scatter.launches++;
+        }
+        if (ctx->work_log_h[2 * i]) {
+          HIPCHK(ctx, hipEventElapsedTime(&ms, ev_s[i].a, ev_s[i].b));
+          ctx->t_self.ms += ms;
+          ctx->t_self.launches++;
+        }
       }
     }
     queued += R;
@@ -655,7 +668,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     if (h.cnt[h.round & 1] == 0) break;     // next frontier empty: the push is done
     chunk = std::max(2, std::min(64, queued / 3));
   }
-  ctx->round_hist.push_back(h.round);
+  ctx->round_hist.push_back(h.steps);
   if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
   return sweep_and_record(ctx, g, id_out, info_out);
 }
@@ -716,8 +729,9 @@ static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
   }
   if (ctx->timing) {
     float ms = 0;
-    ctx->t_scatter.units += h.edges;
-    ctx->t_scatter.entries += h.pushes;
+    // rounds run inside a self launch are not the scatter kernel's work
+    ctx->t_scatter.units += h.edges - h.loop_edges;
+    ctx->t_scatter.entries += h.pushes - h.loop_pushes;
     ctx->t_self.units += h.pushes;
     ctx->t_self.entries += h.pushes;
     HIPCHK(ctx, hipEventElapsedTime(&ms, sweep_ev->a, sweep_ev->b));
@@ -738,6 +752,9 @@ static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
   info.vol = h.best_vol;
   info.phi = h.phi;
   info.r_nnz = h.rnnz;
+  info.launches = h.steps;
+  info.loop_rounds = h.loop_rounds;
+  info.loop_edges = h.loop_edges;
   plc_status st = PLC_OK;
   if (!res.block) {
     info.status = PLC_E_NOMEM;

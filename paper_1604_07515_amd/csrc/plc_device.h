@@ -37,7 +37,9 @@ enum : int32_t { ST_IDLE = 0, ST_PUSH = 1, ST_SWEPT = 2, ST_LIMIT = 4, ST_SWEEPI
 enum : int32_t { SCAN_FRONTIER = 0, SCAN_VOL = 1, SCAN_CUT = 2, NUM_SCANS = 3 };
 
 // Last-workgroup counters.
-enum : int32_t { DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, NUM_DONE = 8 };
+enum : int32_t {
+  DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, DONE_SELF = 4, NUM_DONE = 8
+};
 
 // Where one query's sweep writes its results: the host's result block, or
 // the library's own buffers when none could be allocated.  The host fills a
@@ -92,6 +94,13 @@ struct __align__(64) Ctl {
   // set pushed per round, and this round's active count and pushed count
   double beta;
   int32_t beta_nf, beta_k;
+  // round bookkeeping: `selfed` is the round whose entries the last self
+  // step built (the scatter pushes only that round); `steps` counts self
+  // launches that did work; loop_rounds / loop_pushes / loop_edges count
+  // the small rounds a self launch ran on its own
+  int32_t selfed, steps;
+  int32_t loop_rounds, pad2;
+  long long loop_pushes, loop_edges;
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
@@ -132,6 +141,7 @@ struct PlainArgs {
   int32_t* hk_tl[3];
   double* hk_B;
   long long* bbest;    // per-block argmin candidates (cut, den, k)
+  int32_t* work_log;   // [2 kMaxChunk]: 1 where self (2i) / scatter (2i+1) launch i did work
   // hot destinations of the batched scatter (the highest-degree vertices,
   // combined in LDS there), kept with the graph
   const int32_t* hot_ids;  // [kHot] vertex of hot index j
@@ -147,6 +157,13 @@ constexpr int kEdgesPerThread = kEdgeTile / kBlock;
 constexpr int kHkMaxLevels = 1024;               // largest HK-PR Taylor degree N
 constexpr int kNbMaxSteps = 1024;                // largest Nibble step count T
 constexpr int kHot = 2048;                       // hot destinations (batched scatter)
+constexpr int kMaxChunk = 256;                   // rounds queued at once (work log size / 2)
+// Small rounds: while the frontier fits one scan block and a round has at
+// most kLoopEdges edges, workgroup 0 of the self launch runs whole rounds
+// back to back (kLoopPass edges per pass, at most kLoopMaxRounds per launch).
+constexpr int kLoopEdges = 4096;
+constexpr int kLoopPass = 2048;
+constexpr int kLoopMaxRounds = 256;
 static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 
 // Host-side launchers (return hipError_t of the launch).
@@ -176,10 +193,12 @@ hipError_t launch_nb_step(hipStream_t s, const PlainArgs& a, int grid_self, int 
 hipError_t launch_nb_finish(hipStream_t s, const PlainArgs& a, int32_t R, int32_t J, int grid);
 // With t0 set, the kernel is launched with start and stop events that take
 // its own dispatch timestamps (hipExtLaunchKernelGGL); not for graph capture.
+// With slot >= 0 (< kMaxChunk) a launch that does work sets
+// a.work_log[2 slot] (self) or a.work_log[2 slot + 1] (scatter).
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
-                       hipEvent_t t1 = nullptr);
+                       hipEvent_t t1 = nullptr, int slot = -1);
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
-                          hipEvent_t t1 = nullptr);
+                          hipEvent_t t1 = nullptr, int slot = -1);
 // max_count: bound on the support size, sets the number of merge passes.
 // The sweep writes its results to the destinations in *a.out_host and, in
 // its last kernel, resets the query's dense state (r over the touched list,
