@@ -930,17 +930,22 @@ __device__ __forceinline__ bool sweep_ready(const Ctl* c) {
 
 // Sort keys: non-increasing p/d is ascending order of the bit-inverted IEEE
 // pattern of the positive ratio; equal ratios order by ascending id.
-__global__ __launch_bounds__(kBlock) void k_sweep_keys(PlainArgs a) {
+// The sweep sequence is queued for supports of at most `bound` vertices (it
+// sets the number of merge passes); a larger support leaves the query
+// unswept, for a sweep queued with a larger bound.
+__global__ __launch_bounds__(kBlock) void k_sweep_keys(PlainArgs a, long long bound) {
   Ctl* c = a.ctl;
-  if (!sweep_ready(c)) return;
+  if (!sweep_ready(c) || (long long)c->support_cnt > bound) return;
   __shared__ int s_last;
-  if (blockIdx.x == 0 && threadIdx.x < sizeof(SweepOut) / 8) {
-    // this sweep's result destinations, from pinned host memory (system
-    // scope: the host wrote them just before the launch)
-    unsigned long long* src = reinterpret_cast<unsigned long long*>(
-        const_cast<SweepOut*>(a.out_host));
-    reinterpret_cast<unsigned long long*>(&c->out)[threadIdx.x] =
-        __hip_atomic_load(src + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SweepOut o;
+    o.ids = a.sid;
+    o.p = a.sp;
+    o.rid = a.rid;
+    o.rval = a.rval;
+    o.rcap = a.n;
+    o.pad = 0;
+    c->out = o;
   }
   const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
   for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
@@ -1357,8 +1362,31 @@ hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_
   return hipGetLastError();
 }
 
+// A finished query's results, from the sweep's buffers into its result
+// block: the support in sweep order with p, and the nonzeros of r.
+__global__ __launch_bounds__(kBlock) void k_copy_result(PlainArgs a, int32_t* ids, double* p,
+                                                        int32_t* rid, double* rval, int N, int R) {
+  const int stride = gridDim.x * kBlock;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += stride) {
+    ids[i] = a.sid[i];
+    p[i] = a.sp[i];
+  }
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < R; i += stride) {
+    rid[i] = a.rid[i];
+    rval[i] = a.rval[i];
+  }
+}
+
+hipError_t launch_copy_result(hipStream_t s, const PlainArgs& a, int32_t* ids, double* p,
+                              int32_t* rid, double* rval, int N, int R, int grid) {
+  if (N < 0 || R < 0 || N > a.n || R > a.n) return hipErrorInvalidValue;
+  if (N == 0 && R == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_result, dim3(grid), dim3(kBlock), 0, s, a, ids, p, rid, rval, N, R);
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count) {
-  hipLaunchKernelGGL(k_sweep_keys, dim3(grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sweep_keys, dim3(grid), dim3(kBlock), 0, s, a, (long long)max_count);
   SortArgs sa;
   sa.buf[0] = a.sbuf[0];
   sa.buf[1] = a.sbuf[1];

@@ -151,7 +151,6 @@ struct plc_ctx {
   Arena arena;
   plc_options opt{};
   Ctl* ctl_host = nullptr;  // pinned
-  plc::SweepOut* out_host = nullptr;  // pinned, coherent: the plain sweep's result destinations
   std::map<uint64_t, Result> results;
   std::map<uint64_t, plc_graph*> inflight;  // submitted to a batch engine, not finished
   uint64_t next_id = 1;
@@ -160,6 +159,7 @@ struct plc_ctx {
   int num_cu = 256;
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
+  std::deque<int> support_hist;  // plain path: support sizes of the last queries
   std::vector<int32_t> work_log_h = std::vector<int32_t>(2 * plc::kMaxChunk);
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
   hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
@@ -219,13 +219,6 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
     return PLC_E_HIP;
   }
   std::memset(c->ctl_host, 0, sizeof(Ctl));
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->out_host), sizeof(plc::SweepOut),
-                    hipHostMallocCoherent) != hipSuccess) {
-    (void)hipHostFree(c->ctl_host);
-    delete c;
-    return PLC_E_HIP;
-  }
-  std::memset(c->out_host, 0, sizeof(plc::SweepOut));
   // The caller's stream may be the null stream, which cannot be captured, so
   // graphs are recorded on a stream of our own and replayed on the caller's.
   if (c->opt.launch_mode == PLC_LAUNCH_GRAPH &&
@@ -265,7 +258,6 @@ extern "C" plc_status plc_destroy(plc_ctx* ctx) {
   free_events(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
-  if (ctx->out_host) (void)hipHostFree(ctx->out_host);
   delete ctx;
   return PLC_OK;
 }
@@ -390,7 +382,6 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   int32_t* hotcode = static_cast<int32_t*>(take(4 * N));
   a.hot_ids = hot_ids;
   a.hotcode = hotcode;
-  a.out_host = ctx->out_host;
   a.hk_r1 = static_cast<double*>(take(8 * N));
   a.hk_tl[0] = a.touched;
   a.hk_tl[1] = static_cast<int32_t*>(take(4 * N));
@@ -591,6 +582,9 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, boo
 
 static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
                                    plc_result_info* info_out);
+static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
+                                plc_result_info* info_out);
+static hipError_t queue_sweep(plc_ctx* ctx, plc_graph* g, int64_t bound);
 
 // One plain query: from q.seed, or, with set non-null, from the nset
 // distinct seeds in set (q.seed is then ignored).
@@ -619,9 +613,19 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   if (!ctx->round_hist.empty()) {
     std::vector<int> hs(ctx->round_hist.begin(), ctx->round_hist.end());
     std::sort(hs.begin(), hs.end());
-    chunk = hs[hs.size() / 4];
+    chunk = hs[(3 * hs.size()) / 4];
   }
   chunk = std::max(2, std::min(plc::kMaxChunk, chunk));
+  // Each chunk is followed by the sweep, queued for the largest recent
+  // support (its kernels exit at once unless the push has ended with a
+  // support within that bound), so a typical query needs one read-back.
+  int64_t spec_bound = 0;
+  if (!ctx->timing && !use_beta && !ctx->support_hist.empty()) {
+    spec_bound = 1024;
+    const int64_t mx = *std::max_element(ctx->support_hist.begin(), ctx->support_hist.end());
+    while (spec_bound < mx) spec_bound <<= 1;
+  }
+  bool swept = false;
   Ctl& h = *ctx->ctl_host;
   for (;;) {
     const int R = chunk;
@@ -634,6 +638,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
     else
       HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta));
+    if (spec_bound) HIPCHK(ctx, queue_sweep(ctx, g, spec_bound));
     const EventPair* ev_s = ctx->ev_self.data();
     const EventPair* ev_c = ctx->ev_scatter.data();
     HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -660,8 +665,9 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       }
     }
     queued += R;
+    if (h.status == plc::ST_SWEPT) { swept = true; break; }  // pushed and swept
     if (h.status == plc::ST_LIMIT) break;  // watchdog: sweep the partial p
-    if (h.status != plc::ST_PUSH) {         // unexpected state: device-side fault
+    if (h.status != plc::ST_PUSH || h.fault) {  // unexpected state: device-side fault
       ctx->broken = true;
       return PLC_E_HIP;
     }
@@ -670,62 +676,74 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   ctx->round_hist.push_back(h.steps);
   if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
+  ctx->support_hist.push_back(swept ? h.N : h.support_cnt);
+  if (ctx->support_hist.size() > 16) ctx->support_hist.pop_front();
+  if (swept) return record_result(ctx, g, id_out, info_out);
   return sweep_and_record(ctx, g, id_out, info_out);
 }
 
+// Queue the plain sweep for supports of at most `bound` vertices (a power
+// of 2: it sets the number of merge passes); with timing on, between the
+// context's sweep events.
+static hipError_t queue_sweep(plc_ctx* ctx, plc_graph* g, int64_t bound) {
+  hipStream_t s = ctx->stream;
+  Captured* sg = ctx->use_graphs && !ctx->timing ? plain_sweep_graph(ctx, g, bound) : nullptr;
+  if (sg) return hipGraphLaunch(sg->exec, s);
+  hipError_t r;
+  if (ctx->timing) {
+    if ((r = ev_pair(ctx->ev_sweep)) != hipSuccess) return r;
+    if ((r = hipEventRecord(ctx->ev_sweep.a, s)) != hipSuccess) return r;
+  }
+  r = plc::launch_sweep(s, g->args, shape(g->plain_sweep, ctx->grid_sweep), bound);
+  if (r != hipSuccess) return r;
+  if (ctx->timing) return hipEventRecord(ctx->ev_sweep.b, s);
+  return hipSuccess;
+}
+
 // After a plain push (the control block read back into ctx->ctl_host):
-// take the result block, run the sweep into it, record the result.
+// run the sweep, then record the result.
 static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
                                    plc_result_info* info_out) {
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   Ctl& h = *ctx->ctl_host;
-  // The result block, sized from the push's counters (support N; the
-  // nonzeros of r are among the T touched vertices), before the sweep: the
-  // sweep writes into it directly.  Without room, it writes into the
-  // library's own buffers and the query reports PLC_E_NOMEM.
-  const size_t N = (size_t)std::min<int64_t>(std::max(h.support_cnt, 0), g->n);
-  const size_t T = (size_t)std::min<int64_t>(std::max(h.touched_cnt, 0), g->n);
+  int64_t bound = 1024;
+  while (bound < h.support_cnt) bound <<= 1;
+  HIPCHK(ctx, queue_sweep(ctx, g, bound));
+  HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  return record_result(ctx, g, id_out, info_out);
+}
+
+// After a plain sweep (the control block read back into ctx->ctl_host):
+// take the result block, sized from the sweep's counts (support N, nonzeros
+// of r), queue the copy of the results into it and record the result.
+// Without room for the block the query reports PLC_E_NOMEM.
+static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
+                                plc_result_info* info_out) {
+  hipStream_t s = ctx->stream;
+  const PlainArgs& a = g->args;
+  Ctl& h = *ctx->ctl_host;
+  if (h.status != plc::ST_SWEPT || h.fault || h.N < 0 || h.N > g->n || h.rnnz < 0 ||
+      h.rnnz > g->n) {  // unexpected state: device-side fault
+    ctx->broken = true;
+    return PLC_E_HIP;
+  }
+  const size_t N = (size_t)h.N;
+  const size_t R = (size_t)h.rnnz;
   const size_t off_p = (4 * N + 255) & ~(size_t)255;
   const size_t off_rid = off_p + ((8 * N + 255) & ~(size_t)255);
-  const size_t off_rval = off_rid + ((4 * T + 255) & ~(size_t)255);
+  const size_t off_rval = off_rid + ((4 * R + 255) & ~(size_t)255);
   Result res;
-  res.block = ctx->arena.alloc(off_rval + 8 * T);
-  plc::SweepOut& o = *ctx->out_host;
+  res.block = ctx->arena.alloc(off_rval + 8 * R);
   if (res.block) {
     char* b = static_cast<char*>(res.block);
     res.ids = reinterpret_cast<int32_t*>(b);
     res.p = reinterpret_cast<double*>(b + off_p);
     res.rid = reinterpret_cast<int32_t*>(b + off_rid);
     res.rval = reinterpret_cast<double*>(b + off_rval);
-    o.ids = res.ids; o.p = res.p; o.rid = res.rid; o.rval = res.rval;
-    o.rcap = (long long)T;
-  } else {
-    o.ids = a.sid; o.p = a.sp; o.rid = a.rid; o.rval = a.rval;
-    o.rcap = (long long)g->n;
-  }
-  // Sweep, recorded for the smallest power-of-2 bound on the support size
-  // (it sets the number of merge passes).
-  int64_t bound = 1024;
-  while (bound < h.support_cnt) bound <<= 1;
-  const EventPair* sweep_ev = &ctx->ev_sweep;
-  Captured* sg = ctx->use_graphs && !ctx->timing ? plain_sweep_graph(ctx, g, bound) : nullptr;
-  if (sg) {
-    HIPCHK(ctx, hipGraphLaunch(sg->exec, s));
-  } else {
-    if (ctx->timing) {
-      HIPCHK(ctx, ev_pair(ctx->ev_sweep));
-      HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.a, s));
-    }
-    HIPCHK(ctx, plc::launch_sweep(s, a, shape(g->plain_sweep, ctx->grid_sweep), bound));
-    if (ctx->timing) HIPCHK(ctx, hipEventRecord(ctx->ev_sweep.b, s));
-  }
-  HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  HIPCHK(ctx, hipStreamSynchronize(s));
-  if (h.status != plc::ST_SWEPT || h.fault) {  // unexpected state: device-side fault
-    ctx->arena.release(res.block);
-    ctx->broken = true;
-    return PLC_E_HIP;
+    HIPCHK(ctx, plc::launch_copy_result(s, a, res.ids, res.p, res.rid, res.rval, (int)N, (int)R,
+                                        shape(g->plain_sweep, ctx->grid_sweep)));
   }
   if (ctx->timing) {
     float ms = 0;
@@ -734,7 +752,7 @@ static plc_status sweep_and_record(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
     ctx->t_scatter.entries += h.pushes - h.loop_pushes;
     ctx->t_self.units += h.pushes;
     ctx->t_self.entries += h.pushes;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, sweep_ev->a, sweep_ev->b));
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_sweep.a, ctx->ev_sweep.b));
     ctx->t_sweep.ms += ms;
     ctx->t_sweep.launches++;
     ctx->t_sweep.units += h.etotal;

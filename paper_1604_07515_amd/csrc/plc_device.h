@@ -41,10 +41,8 @@ enum : int32_t {
   DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, DONE_SELF = 4, NUM_DONE = 8
 };
 
-// Where one query's sweep writes its results: the host's result block, or
-// the library's own buffers when none could be allocated.  The host fills a
-// pinned, coherent copy before the sweep; k_sweep_keys moves it into the
-// control block, where the later sweep kernels read it.
+// Where the running sweep writes its results (the library's own buffers,
+// set by k_sweep_keys; the host copies them into the query's result block).
 struct SweepOut {
   int32_t* ids;     // [N] support in sweep order
   double* p;        // [N] p in sweep order
@@ -129,11 +127,10 @@ struct PlainArgs {
   int32_t* sdeg;       // degree in sweep order
   int64_t* svol;       // inclusive volume prefix in sweep order
   int32_t* scnt;       // # earlier-ranked neighbours per sweep position
-  double* sp;          // p in sweep order      } fallback result destinations
-  int32_t* sid;        // vertex ids in sweep order } when no result block
-  int32_t* rid;        // r nonzero ids           } could be allocated
-  double* rval;        // r nonzero values        }
-  const SweepOut* out_host;  // pinned host memory: this sweep's result destinations
+  double* sp;          // p in sweep order            } the sweep's results, copied
+  int32_t* sid;        // vertex ids in sweep order   } into the query's result
+  int32_t* rid;        // r nonzero ids               } block afterwards
+  double* rval;        // r nonzero values            }
   // HK-PR: level k's residuals live in vr[].r (k even) or hk_r1 (k odd);
   // the vertices level k touched are listed in hk_tl[k % 3] (hk_tl[0] is
   // the touched list); hk_B[k] = 2 N psi_k, the threshold denominator
@@ -199,10 +196,15 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
                        hipEvent_t t1 = nullptr, int slot = -1);
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr, int slot = -1);
-// max_count: bound on the support size, sets the number of merge passes.
-// The sweep writes its results to the destinations in *a.out_host and, in
-// its last kernel, resets the query's dense state (r over the touched list,
-// p and the rank over the support list).
+// max_count: bound on the support size, sets the number of merge passes; a
+// query with a larger support (or one still pushing) is left unswept, so the
+// sweep may be queued before the push is known to have ended.  The sweep
+// writes its results to a.sid, a.sp (support order, p) and a.rid, a.rval
+// (nonzeros of r) and, in its last kernel, resets the query's dense state
+// (r over the touched list, p and the rank over the support list).
+// launch_copy_result copies N and R of them into a result block.
 hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count);
+hipError_t launch_copy_result(hipStream_t s, const PlainArgs& a, int32_t* ids, double* p,
+                              int32_t* rid, double* rval, int N, int R, int grid);
 
 }  // namespace plc

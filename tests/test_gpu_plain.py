@@ -208,9 +208,35 @@ def test_int32_offsets_rmat16_seed0(plc):
     check_same(g, out[0], out[1])
 
 
+def test_sweep_queued_behind_push(plc):
+    """The sweep is queued after each push chunk for the largest recent
+    support and runs only if the push ended within that bound.  In a fresh
+    context: tiny queries (bound 1024), a query whose support exceeds it (the
+    queued sweep stands aside, an exact one follows), a tiny query under the
+    grown bound, and a 745-round push on a path (several chunks, the sweeps
+    queued behind the unfinished ones stand aside): all match the oracle."""
+    g = synth.rmat(13, 8, seed=4)
+    pg = synth.path(5000)
+    hub = int(np.argmax(g.deg))
+    with plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                     + plc.plain_arena_bytes(pg.n, pg.arcs) + (64 << 20)) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        hp = c.load_graph(pg.off, pg.nbr)
+        for eps in (1e-2, 1e-2, 1e-2, 1e-7, 1e-2):
+            say("case sweep behind push: rmat13 seed", hub, "eps", eps)
+            ids, infos = c.run(hg, [hub], 0.01, eps)
+            if eps == 1e-7:
+                assert infos[0]["support"] > 1024
+            check_query(g, c.result(ids[0], release=True), hub, 0.01, eps, OPT)
+        say("case sweep behind push: path5000 seed 0 eps 1e-8")
+        ids, infos = c.run(hp, [0], 0.01, 1e-8)
+        assert infos[0]["rounds"] == 745 and infos[0]["launches"] >= 3
+        check_query(pg, c.result(ids[0], release=True), 0, 0.01, 1e-8, OPT)
+
+
 def test_result_block_does_not_fit(plc):
-    """No room for a query's result block: the sweep writes into the
-    library's own buffers, the query reports PLC_E_NOMEM with its counters,
+    """No room for a query's result block: the query reports PLC_E_NOMEM
+    with its counters (the sweep itself writes into the library's buffers),
     and the dense state is still reset (a following query, whose neighbours
     the first one touched, matches the oracle)."""
     g = synth.rmat(14, 8, seed=2)
