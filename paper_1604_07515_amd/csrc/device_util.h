@@ -199,6 +199,21 @@ __device__ __forceinline__ bool last_block(unsigned* done, int* sh, bool with_ac
   return l != 0;
 }
 
+// Wavefront-ballot append into an LDS staging buffer: the lanes of the
+// calling wave with pred set store v at consecutive slots of buf, reserved
+// with one LDS atomic per wave (the popcount of the ballot); a lane's slot
+// is the number of set lanes below it.  Safe in divergent code: only the
+// active lanes take part.
+__device__ __forceinline__ void wave_append(bool pred, int32_t v, int32_t* buf, int* cnt) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if ((int)PLC_LANE == leader) base = atomicAdd(cnt, __popcll(m));
+  base = __shfl(base, leader);
+  if (pred) buf[base + __popcll(m & lanemask_lt())] = v;
+}
+
 // Workgroup-aggregated append of the values staged in an LDS buffer:
 // one global atomic per call.  Every thread must call it.  Writes
 // dst[base + j] = buf[j] for j < *count (slots >= cap raise *fault).

@@ -270,8 +270,10 @@ __device__ __forceinline__ void self_body(const PlainArgs& a, int slot) {
     for (int k = 0; k < kScanItems; k++) {
       const int i = i0 + k;
       int32_t d = 0;
+      int32_t v = 0;
+      bool stay = false, sup = false;
       if (i < nf) {
-        int32_t v = F[i];
+        v = F[i];
         double rho;
         if (LEVELS) {
           rho = *hk_res(a, t, v);
@@ -293,11 +295,13 @@ __device__ __forceinline__ void self_body(const PlainArgs& a, int slot) {
           double nr = opt ? -0.0 : keep * rho;
           a.vr[v].r = nr;
           a.coef[i] = (cn * rho) / (double)d;
-          if (!opt && nr >= eps * (double)d) s_stay[atomicAdd(&s_nstay, 1)] = v;
+          stay = !opt && nr >= eps * (double)d;
         }
         a.rowp[i] = a.off[v];
-        if (pold == 0.0) s_sup[atomicAdd(&s_nsup, 1)] = v;
+        sup = pold == 0.0;
       }
+      wave_append(stay, v, s_stay, &s_nstay);
+      wave_append(sup, v, s_sup, &s_nsup);
       dk[k] = d;
       dsum += d;
     }
@@ -334,12 +338,13 @@ __device__ __forceinline__ void self_body(const PlainArgs& a, int slot) {
   }
 }
 
-// Threshold decision for one addition of c to r[w] that returned `old`:
-// crossing appends w to the next frontier, first touch to the touched list.
-__device__ __forceinline__ void decide(double old, double c, double thr, int32_t w, int32_t* s_fn,
-                                       int* s_nfn, int32_t* s_tv, int* s_ntv) {
-  if (old < thr && old + c >= thr) s_fn[atomicAdd(s_nfn, 1)] = w;
-  if (__double_as_longlong(old) == 0) s_tv[atomicAdd(s_ntv, 1)] = w;
+// Threshold decision for one addition of c to r[w] that returned `old`
+// (lanes without an addition pass valid = false): crossing appends w to the
+// next frontier, first touch to the touched list (wave-ballot appends).
+__device__ __forceinline__ void decide(bool valid, double old, double c, double thr, int32_t w,
+                                       int32_t* s_fn, int* s_nfn, int32_t* s_tv, int* s_ntv) {
+  wave_append(valid && old < thr && old + c >= thr, w, s_fn, s_nfn);
+  wave_append(valid && __double_as_longlong(old) == 0, w, s_tv, s_ntv);
 }
 
 template <typename T>
@@ -414,10 +419,12 @@ __device__ void loop_rounds(const PlainArgs& a, int slot, int t, int nf) {
     for (int k = 0; k < kScanItems; k++) {
       const int i = i0 + k;
       int32_t d = 0;
+      int32_t v = 0;
+      bool stay = false, sup = false;
       ck[k] = 0.0;
       rk[k] = 0;
       if (i < nf) {
-        const int32_t v = F[i];
+        v = F[i];
         d = a.vr[v].deg;
         double* rp = &a.vr[v].r;
         const double rho = ld_agent(rp);
@@ -427,9 +434,11 @@ __device__ void loop_rounds(const PlainArgs& a, int slot, int t, int nf) {
         st_agent(rp, nr);
         ck[k] = (cn * rho) / (double)d;
         rk[k] = a.off[v];
-        if (!opt && nr >= eps * (double)d) s_stay[atomicAdd(&s_nstay, 1)] = v;
-        if (pold == 0.0) s_sup[atomicAdd(&s_nsup, 1)] = v;
+        stay = !opt && nr >= eps * (double)d;
+        sup = pold == 0.0;
       }
+      wave_append(stay, v, s_stay, &s_nstay);
+      wave_append(sup, v, s_sup, &s_nsup);
       dk[k] = d;
       dsum += d;
     }
@@ -501,7 +510,7 @@ __device__ void loop_rounds(const PlainArgs& a, int slot, int t, int nf) {
       for (int k = 0; k < kPer; k++) old[k] = w[k] >= 0 ? unsafeAtomicAdd(&a.vr[w[k]].r, cf[k]) : 0.0;
 #pragma unroll
       for (int k = 0; k < kPer; k++)
-        if (w[k] >= 0) decide(old[k], cf[k], eps * (double)dw[k], w[k], s_fn, &s_nfn, s_tv, &s_ntv);
+        decide(w[k] >= 0, old[k], cf[k], eps * (double)dw[k], w[k], s_fn, &s_nfn, s_tv, &s_ntv);
       __syncthreads();
       const int nfn = s_nfn, ntv = s_ntv;
       local_append(Fn, cap, s_F[cur ^ 1], s_fn, nfn, nnext, &c->fault);
@@ -664,12 +673,11 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
     }
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
-      if (w[k] < 0) continue;
-      if (hk_last) {
-        if (__double_as_longlong(old[k]) == 0) s_tv[atomicAdd(&s_ntv, 1)] = w[k];
-      } else {
-        decide(old[k], cf[k], (eps * (double)dw[k]) / den, w[k], s_fn, &s_nfn, s_tv, &s_ntv);
-      }
+      if (hk_last)
+        wave_append(w[k] >= 0 && __double_as_longlong(old[k]) == 0, w[k], s_tv, &s_ntv);
+      else
+        decide(w[k] >= 0, old[k], cf[k], (eps * (double)dw[k]) / den, w[k], s_fn, &s_nfn, s_tv,
+               &s_ntv);
     }
     if (!hk_last) block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
     block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
@@ -682,7 +690,7 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
         const int32_t v = Fc[i];
         const double h = a.sp[i];
         const double o = unsafeAtomicAdd(hk_res(a, t + 1, v), h);
-        decide(o, h, eps * (double)a.vr[v].deg, v, s_fn, &s_nfn, s_tv, &s_ntv);
+        decide(true, o, h, eps * (double)a.vr[v].deg, v, s_fn, &s_nfn, s_tv, &s_ntv);
       }
       block_flush(cntn, Fn, a.n, s_fn, &s_nfn, &s_base, &c->fault);
       block_flush(tv_cnt, tv_list, a.n, s_tv, &s_ntv, &s_base, &c->fault);
