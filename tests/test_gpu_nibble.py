@@ -65,6 +65,22 @@ def test_nibble_rmat16_paper_T(ctx):
             say("  steps", out["steps"], "support", out["support"])
 
 
+def test_nibble_rmat20_large_support(ctx):
+    """Nibble from the top hub of R-MAT 2^20 (ef 8) with the paper's T = 20
+    reaches ~5.5e5 vertices: the sweep's merge sort runs 134 block-sort tiles
+    and 8 merge passes with a ragged last tile, and the order, cluster and
+    conductance must still match the oracle's."""
+    g = synth.rmat(20, 8, seed=3)
+    hg = ctx.load_graph(g.off, g.nbr)
+    x = int(np.argmax(g.deg))
+    say("case nibble rmat20 hub", x, "eps 1e-10 T 20")
+    qid, info = ctx.run_nibble(hg, x, 1e-10, 20)
+    assert info["support"] > 500000
+    out = check_nibble(g, ctx.result(qid, release=True), oracle.nibble(g.off, g.nbr, x, 1e-10, 20))
+    say("  steps", out["steps"], "support", out["support"])
+    hg.free()
+
+
 def test_nibble_interleaved_with_prnibble_and_hkpr(ctx):
     g, hg = graph(ctx, "rmat13")
     for x in [int(v) for v in synth.uniform_seeds(g, 2, seed=9)]:
