@@ -1289,6 +1289,8 @@ static Captured* batch_round_graph(plc_ctx* ctx, plc_graph* g) {
   return ok ? &c : nullptr;
 }
 
+constexpr int kBatchChain = 4;  // rounds per read-back, dense throughput mode
+
 // One global step.  defer_sweep: while other queries are still pushing and
 // none waits for a slot, leave finished queries unswept so that they are
 // swept together later (fewer, larger sweeps: throughput mode).
@@ -1520,7 +1522,11 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     // events) and the scatter carries events on its own dispatch timestamps
     Captured* rg = ctx->use_graphs && !ctx->timing ? batch_round_graph(ctx, g) : nullptr;
     if (rg) {
-      HIPCHK(ctx, hipGraphLaunch(rg->exec, s));
+      // Dense slots with nothing waiting for admission (throughput mode) need
+      // no host action between rounds (k_b_plan retires a slot whose
+      // frontier emptied), so several rounds share one read-back.
+      const int chain = defer_sweep && E.queue.empty() && !E.compact ? kBatchChain : 1;
+      for (int i = 0; i < chain; i++) HIPCHK(ctx, hipGraphLaunch(rg->exec, s));
     } else {
       HIPCHK(ctx, plc::launch_batch_plan_self(s, a, shape(g->batch_self, ctx->grid_self),
                                               E.compact));
