@@ -130,6 +130,10 @@ typedef struct {
   int32_t launches;
   int32_t loop_rounds;
   int64_t loop_edges;
+  /* plain path only (0 elsewhere): wall time in the library from the
+   * query's start to its recorded result (push, sweep and read-backs; the
+   * copy into the result block is queued), in nanoseconds */
+  int64_t host_ns;
 } plc_result_info;
 
 /* Status code to a static string. */
@@ -366,7 +370,9 @@ plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);
 plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_ids, double* sweep_p,
                            int32_t* r_ids, double* r_vals);
 
-/* Return a finished query's arena memory. */
+/* Return a finished query's arena memory.  Does not wait for the GPU: any
+ * work that reuses the memory is queued behind the query's pending result
+ * copy on the context's stream.  PLC_E_NOTFOUND for an unknown id. */
 plc_status plc_release(plc_ctx* ctx, uint64_t id);
 
 /* Arena bytes currently free (largest free block in *largest, may be NULL). */

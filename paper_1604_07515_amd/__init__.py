@@ -71,7 +71,7 @@ class plc_result_info(C.Structure):
                 ("edges", C.c_int64), ("support", C.c_int64), ("kstar", C.c_int64),
                 ("cut", C.c_int64), ("vol", C.c_int64), ("phi", C.c_double),
                 ("r_nnz", C.c_int64), ("launches", C.c_int32), ("loop_rounds", C.c_int32),
-                ("loop_edges", C.c_int64)]
+                ("loop_edges", C.c_int64), ("host_ns", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

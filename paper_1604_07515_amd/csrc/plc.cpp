@@ -160,6 +160,7 @@ struct plc_ctx {
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
+  std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
   std::vector<int32_t> work_log_h = std::vector<int32_t>(2 * plc::kMaxChunk);
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
   hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
@@ -591,6 +592,7 @@ static hipError_t queue_sweep(plc_ctx* ctx, plc_graph* g, int64_t bound);
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
                           plc_result_info* info_out, const int32_t* set = nullptr,
                           int32_t nset = 0, double beta = 1.0) {
+  ctx->q_t0 = std::chrono::steady_clock::now();
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   if (set) {
@@ -773,6 +775,8 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
   info.launches = h.steps;
   info.loop_rounds = h.loop_rounds;
   info.loop_edges = h.loop_edges;
+  info.host_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                     std::chrono::steady_clock::now() - ctx->q_t0).count();
   plc_status st = PLC_OK;
   if (!res.block) {
     info.status = PLC_E_NOMEM;
@@ -859,6 +863,7 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
     return PLC_E_INVALID;
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
+  ctx->q_t0 = std::chrono::steady_clock::now();
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   // threshold of level k: ((e^-t eps) d(w)) / B_k with B_k = 2 N psi_k
@@ -910,6 +915,7 @@ extern "C" plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, d
   if (T < 0 || T > plc::kNbMaxSteps || !std::isfinite(eps) || !(eps > 0.0)) return PLC_E_INVALID;
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
+  ctx->q_t0 = std::chrono::steady_clock::now();
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   HIPCHK(ctx, plc::launch_nb_init(s, a, seed, eps, T));
@@ -970,15 +976,10 @@ extern "C" plc_status plc_release(plc_ctx* ctx, uint64_t id) {
   if (!ctx) return PLC_E_INVALID;
   auto it = ctx->results.find(id);
   if (it == ctx->results.end()) return PLC_E_NOTFOUND;
-  if (it->second.block) {
-    // the block may still be the target of queued copies
-    (void)hipSetDevice(ctx->device);
-    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
-      ctx->broken = true;
-      return PLC_E_HIP;
-    }
-    ctx->arena.release(it->second.block);
-  }
+  // The block may still be the target of the queued result copy, but every
+  // later user of arena memory is queued on the same stream, behind it, so
+  // it returns to the arena at once (no wait).
+  if (it->second.block) ctx->arena.release(it->second.block);
   ctx->results.erase(it);
   return PLC_OK;
 }

@@ -225,6 +225,7 @@ def test_sweep_queued_behind_push(plc):
         for eps in (1e-2, 1e-2, 1e-2, 1e-7, 1e-2):
             say("case sweep behind push: rmat13 seed", hub, "eps", eps)
             ids, infos = c.run(hg, [hub], 0.01, eps)
+            assert infos[0]["host_ns"] > 0
             if eps == 1e-7:
                 assert infos[0]["support"] > 1024
             check_query(g, c.result(ids[0], release=True), hub, 0.01, eps, OPT)
