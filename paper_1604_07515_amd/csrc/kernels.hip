@@ -14,9 +14,15 @@
 //             folded in: r only grows during a scatter, so w joins the next
 //             frontier exactly when one atomic's (old, old + c) pair straddles
 //             eps*d(w); that atomic appends w.
+// A frontier of at most one scan block is handled by k_self alone: its last
+// workgroup to arrive runs such rounds back to back (self step, scan, edge
+// scatter, round close) until the frontier grows, empties or a round has
+// too many edges for one workgroup; k_scatter then pushes only rounds whose
+// entries were built in memory.
 // Kernels read the round number and frontier size from the device control
-// block and return at once when the query has finished, so rounds can be
-// queued ahead of the host's termination check.
+// block and return at once when the query has finished, so rounds (and the
+// sweep, guarded the same way) can be queued ahead of the host's
+// termination check.
 //
 // Arithmetic matches the paper's updates evaluated in a fixed way: the
 // constants cs, cn, keep are rounded once, p[v] + cs*rho, keep*rho and

@@ -2,13 +2,14 @@
 //
 // A context owns a view of the caller's device arena, the caller's stream and
 // a pinned host mirror of the device control block.  plc_run drives the plain
-// path: per query it queues the seed initialisation and a chunk of rounds
-// (kernels of rounds past the end of the push exit at once), reads the
-// control block back, and queues short further chunks until the frontier is
-// empty; then the sweep sequence, recorded for the support size's number of
-// merge passes, and one more read-back.  Results are copied device-to-device
-// into an exact-size arena block, and the dense per-vertex state is reset
-// through the touched list.  The batch engine (plc_batch_reserve and after)
+// path: per query it queues the seed initialisation, a chunk of (self,
+// scatter) launch pairs (launches past the end of the push exit at once) and
+// the sweep sequence for the largest recent support (it runs only if the
+// push has ended within that bound), then reads the control block back; an
+// unfinished push gets short further chunks, and a larger support the sweep
+// for its own bound, each with a read-back.  Results are copied
+// device-to-device into an exact-size arena block, and the dense per-vertex
+// state is reset through the touched list.  The batch engine (plc_batch_reserve and after)
 // runs many queries per launch.
 #include <hip/hip_runtime.h>
 
