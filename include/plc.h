@@ -176,7 +176,8 @@ plc_status plc_graph_info_get(const plc_graph* g, plc_graph_info* out);
  * synchronous PR-Nibble (Sec. 3.3, Figs. alg:pr-nibble / alg:pr-nibble2)
  * followed by the sweep cut (Sec. 3.1, Theorem 1), blocking until all are
  * done.  ids[i] (may be NULL) receives a handle whose vectors stay in the
- * arena until plc_release; infos[i] (may be NULL) receives the summary.
+ * arena until plc_release (the block is sized for the support and the
+ * nonzeros of r); infos[i] (may be NULL) receives the summary.
  * A query rejected by parameter checks gets status PLC_E_INVALID in its info
  * and id 0, and the call still runs the others; the return value is the
  * first error met, or PLC_OK.
@@ -384,12 +385,15 @@ plc_status plc_arena_free_bytes(plc_ctx* ctx, size_t* total, size_t* largest);
  * recorded graphs, and the scatter and self kernels are launched with start
  * and stop events that take the kernel's own dispatch timestamps
  * (hipExtLaunchKernelGGL); the sweep is bracketed by an event pair.  Plain
- * path: only rounds that pushed something are counted for the scatter and
- * self kernels.  Batch engine: one scatter launch per step
+ * path: only launches that did work are counted.  A self launch may run
+ * whole small rounds itself (info->loop_rounds); their edges and pushes
+ * are not the scatter's.  Batch engine: one scatter launch per step
  * (all scheduled queries' edges) and one sweep sequence per step that swept;
  * self is not timed.
  *   scatter: the edgeMap kernel; units = pushed edges, entries = pushes
- *   self:    the vertexMap + frontier-scan kernel; units = pushes
+ *            (of the rounds it pushed)
+ *   self:    the vertexMap + frontier-scan kernel (and the small rounds it
+ *            runs); units = pushes
  *   sweep:   the whole sweep-cut sequence; units = support volume vol(S_N),
  *            entries = support size N
  */
