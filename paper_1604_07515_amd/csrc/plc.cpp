@@ -874,7 +874,9 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
                              s));
   HIPCHK(ctx, plc::launch_hk_init(s, a, seed, N, t, std::exp(-t) * eps));
   // at most N levels; levels past an empty frontier exit at once
-  const int gs = shape(g->plain_self, ctx->grid_self);
+  // (HK-PR levels and Nibble steps reach far larger frontiers than the
+  // PR-Nibble sample the shape was tuned on: at least CU/2 workgroups)
+  const int gs = std::max(shape(g->plain_self, ctx->grid_self), ctx->num_cu / 2);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   for (int32_t j = 0; j < N; j++) HIPCHK(ctx, plc::launch_hk_level(s, a, gs, gc));
   HIPCHK(ctx, plc::launch_hk_clear(s, a, shape(g->plain_sweep, ctx->grid_sweep)));
@@ -920,7 +922,9 @@ extern "C" plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, d
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   HIPCHK(ctx, plc::launch_nb_init(s, a, seed, eps, T));
-  const int gs = shape(g->plain_self, ctx->grid_self);
+  // (HK-PR levels and Nibble steps reach far larger frontiers than the
+  // PR-Nibble sample the shape was tuned on: at least CU/2 workgroups)
+  const int gs = std::max(shape(g->plain_self, ctx->grid_self), ctx->num_cu / 2);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   for (int32_t j = 0; j < T; j++) HIPCHK(ctx, plc::launch_nb_step(s, a, gs, gc));
   Ctl& h = *ctx->ctl_host;
@@ -1782,7 +1786,7 @@ extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* 
   int tried = 0;
   double best_plain = 0, best_batch = 0;
   if (which & PLC_TUNE_PLAIN) {
-    const int selfs[] = {cu / 2, cu, 2 * cu};
+    const int selfs[] = {cu / 8, cu / 4, cu / 2, cu, 2 * cu};
     const int scats[] = {cu / 2, cu, 2 * cu, 4 * cu};
     const int sweeps[] = {cu, 2 * cu};
     double ms = 0;
