@@ -608,7 +608,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   // Push: chunks of (self, scatter) launch pairs, each followed by a
   // read-back of the control block.  A self launch may run several small
   // rounds, and pairs queued past the end of the push exit at once but still
-  // cost a dispatch each, so the first chunk is the lower quartile of the
+  // cost a dispatch each, so the first chunk is the upper quartile of the
   // last queries' counts of working self launches and later chunks are
   // short.
   int queued = 0;
