@@ -539,7 +539,7 @@ def main():
                          "for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(seeds would shard across GPUs, one graph replica each); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
