@@ -55,6 +55,7 @@ __global__ void k_graph_init(PlainArgs a) {
 }
 
 __device__ __forceinline__ void reset_round_book(Ctl* c) {
+  c->init_held = 0;
   c->selfed = -1;
   c->steps = 0;
   c->loop_rounds = 0;
@@ -63,9 +64,8 @@ __device__ __forceinline__ void reset_round_book(Ctl* c) {
 }
 
 // Seed initialisation (Fig. alg:pr-nibble: r = {(x,1)}, Frontier = {x}).
-__global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alpha, double eps,
-                             int32_t max_rounds, double beta) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void query_init_body(const PlainArgs& a, int32_t seed, int32_t rule, double alpha,
+                                double eps, int32_t max_rounds, double beta) {
   Ctl* c = a.ctl;
   if (rule == 1) {  // original rule
     c->cs = alpha;
@@ -110,6 +110,25 @@ __global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alp
   a.touched[0] = seed;
   a.vr[seed].r = 1.0;
   c->status = ST_PUSH;
+}
+
+__global__ void k_query_init(PlainArgs a, int32_t seed, int32_t rule, double alpha, double eps,
+                             int32_t max_rounds, double beta) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  query_init_body(a, seed, rule, alpha, eps, max_rounds, beta);
+}
+
+// The same, only after a swept query (or none since the graph was loaded);
+// otherwise the previous query's state is left as it is.
+__global__ void k_query_init_guarded(PlainArgs a, int32_t seed, int32_t rule, double alpha,
+                                     double eps, int32_t max_rounds) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctl* c = a.ctl;
+  if (c->status != ST_SWEPT && c->status != ST_IDLE) {
+    c->init_held = 1;
+    return;
+  }
+  query_init_body(a, seed, rule, alpha, eps, max_rounds, 1.0);
 }
 
 // Seed-set initialisation (Sec. 3: a set S of seeds): the host has placed
@@ -1290,6 +1309,13 @@ hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, in
                              double alpha, double eps, int32_t max_rounds, double beta) {
   hipLaunchKernelGGL(k_query_init, dim3(1), dim3(64), 0, s, a, seed, rule, alpha, eps,
                      max_rounds, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_init_guarded(hipStream_t s, const PlainArgs& a, int32_t seed,
+                                     int32_t rule, double alpha, double eps, int32_t max_rounds) {
+  hipLaunchKernelGGL(k_query_init_guarded, dim3(1), dim3(64), 0, s, a, seed, rule, alpha, eps,
+                     max_rounds);
   return hipGetLastError();
 }
 

@@ -162,6 +162,8 @@ struct plc_ctx {
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
   std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
+  std::chrono::steady_clock::time_point next_t0;  // plain path: when the next query was queued
+  hipEvent_t rb_event = nullptr;  // plain path: recorded after the running query's read-back
   std::vector<int32_t> work_log_h = std::vector<int32_t>(2 * plc::kMaxChunk);
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
   hipStream_t cap_stream = nullptr;   // private stream that graphs are recorded on
@@ -246,6 +248,8 @@ static void free_events(plc_ctx* c) {
   c->ev_self.clear();
   if (c->ev_sweep.a) { (void)hipEventDestroy(c->ev_sweep.a); (void)hipEventDestroy(c->ev_sweep.b); }
   c->ev_sweep = EventPair{};
+  if (c->rb_event) (void)hipEventDestroy(c->rb_event);
+  c->rb_event = nullptr;
 }
 
 extern "C" plc_status plc_destroy(plc_ctx* ctx) {
@@ -590,13 +594,56 @@ static hipError_t queue_sweep(plc_ctx* ctx, plc_graph* g, int64_t bound);
 
 // One plain query: from q.seed, or, with set non-null, from the nset
 // distinct seeds in set (q.seed is then ignored).
+// Push: chunks of (self, scatter) launch pairs, each followed by a
+// read-back of the control block.  A self launch may run several small
+// rounds, and pairs queued past the end of the push exit at once but still
+// cost a dispatch each, so the first chunk is the upper quartile of the
+// last queries' counts of working self launches and later chunks are short.
+static int first_chunk(const plc_ctx* ctx) {
+  int chunk = 16;
+  if (!ctx->round_hist.empty()) {
+    std::vector<int> hs(ctx->round_hist.begin(), ctx->round_hist.end());
+    std::sort(hs.begin(), hs.end());
+    chunk = hs[(3 * hs.size()) / 4];
+  }
+  return std::max(2, std::min(plc::kMaxChunk, chunk));
+}
+
+// Queue query q's guarded initialisation and first chunk behind the running
+// query's read-back, so that the GPU works on it while the host takes that
+// read-back.  Returns the chunk's pair count (0: nothing queued, -1: error).
+static int prelaunch(plc_ctx* ctx, plc_graph* g, const plc_query& q) {
+  if (!ctx->use_graphs || ctx->timing) return 0;
+  const int R = first_chunk(ctx);
+  Captured* cg = plain_chunk_graph(ctx, g, R);
+  if (!cg) return 0;
+  hipStream_t s = ctx->stream;
+  if (plc::launch_query_init_guarded(s, g->args, q.seed, (int32_t)q.rule, q.alpha, q.eps,
+                                     ctx->opt.max_rounds) != hipSuccess ||
+      hipGraphLaunch(cg->exec, s) != hipSuccess) {
+    ctx->broken = true;
+    return -1;
+  }
+  ctx->next_t0 = std::chrono::steady_clock::now();
+  return R;
+}
+
+// One plain query: from q.seed, or, with set non-null, from the nset
+// distinct seeds in set (q.seed is then ignored).  pre > 0: its guarded
+// initialisation and first chunk of pre pairs are already queued.  next
+// (may be null): the following query, queued behind this one's first
+// read-back; *next_pre receives its chunk (0 when it must start afresh).
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
                           plc_result_info* info_out, const int32_t* set = nullptr,
-                          int32_t nset = 0, double beta = 1.0) {
-  ctx->q_t0 = std::chrono::steady_clock::now();
+                          int32_t nset = 0, double beta = 1.0, int pre = 0,
+                          const plc_query* next = nullptr, int* next_pre = nullptr) {
+  ctx->q_t0 = pre > 0 ? ctx->next_t0 : std::chrono::steady_clock::now();
+  if (next_pre) *next_pre = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
-  if (set) {
+  if (pre > 0) {
+    // (queued by the previous query's run)
+  } else if (set) {
     HIPCHK(ctx, hipMemcpyAsync(a.fbuf0, set, 4 * (size_t)nset, hipMemcpyHostToDevice, s));
     HIPCHK(ctx, plc::launch_query_init_set(s, a, nset, (int32_t)q.rule, q.alpha, q.eps,
                                            ctx->opt.max_rounds));
@@ -605,20 +652,8 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
                                        ctx->opt.max_rounds, beta));
   }
   const bool use_beta = beta < 1.0;
-  // Push: chunks of (self, scatter) launch pairs, each followed by a
-  // read-back of the control block.  A self launch may run several small
-  // rounds, and pairs queued past the end of the push exit at once but still
-  // cost a dispatch each, so the first chunk is the upper quartile of the
-  // last queries' counts of working self launches and later chunks are
-  // short.
   int queued = 0;
-  int chunk = 16;
-  if (!ctx->round_hist.empty()) {
-    std::vector<int> hs(ctx->round_hist.begin(), ctx->round_hist.end());
-    std::sort(hs.begin(), hs.end());
-    chunk = hs[(3 * hs.size()) / 4];
-  }
-  chunk = std::max(2, std::min(plc::kMaxChunk, chunk));
+  int chunk = pre > 0 ? pre : first_chunk(ctx);
   // Each chunk is followed by the sweep, queued for the largest recent
   // support (its kernels exit at once unless the push has ended with a
   // support within that bound), so a typical query needs one read-back.
@@ -630,17 +665,19 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   }
   bool swept = false;
   Ctl& h = *ctx->ctl_host;
-  for (;;) {
+  for (bool first = true;; first = false) {
     const int R = chunk;
-    // while timing is on, rounds are launched directly (graphs carry no events)
-    // (the beta variant's rounds are launched directly too)
-    Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta ? plain_chunk_graph(ctx, g, R)
-                                                                : nullptr;
-    if (ctx->timing) HIPCHK(ctx, hipMemsetAsync(a.work_log, 0, 4 * 2 * (size_t)R, s));
-    if (cg)
-      HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
-    else
-      HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta));
+    if (!(first && pre > 0)) {
+      // while timing is on, rounds are launched directly (graphs carry no
+      // events) (the beta variant's rounds are launched directly too)
+      Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta ? plain_chunk_graph(ctx, g, R)
+                                                                  : nullptr;
+      if (ctx->timing) HIPCHK(ctx, hipMemsetAsync(a.work_log, 0, 4 * 2 * (size_t)R, s));
+      if (cg)
+        HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
+      else
+        HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta));
+    }
     if (spec_bound) HIPCHK(ctx, queue_sweep(ctx, g, spec_bound));
     const EventPair* ev_s = ctx->ev_self.data();
     const EventPair* ev_c = ctx->ev_scatter.data();
@@ -648,7 +685,37 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     if (ctx->timing)
       HIPCHK(ctx, hipMemcpyAsync(ctx->work_log_h.data(), a.work_log, 4 * 2 * (size_t)R,
                                  hipMemcpyDeviceToHost, s));
-    HIPCHK(ctx, hipStreamSynchronize(s));
+    int held = 0;  // pairs of the next query's chunk queued behind this read-back
+    if (first && next && spec_bound && !set && !use_beta) {
+      if (!ctx->rb_event &&
+          hipEventCreateWithFlags(&ctx->rb_event, hipEventDisableTiming) != hipSuccess)
+        ctx->rb_event = nullptr;
+      if (ctx->rb_event) {
+        HIPCHK(ctx, hipEventRecord(ctx->rb_event, s));
+        held = prelaunch(ctx, g, *next);
+        if (held < 0) return PLC_E_HIP;
+      }
+    }
+    if (held > 0)
+      HIPCHK(ctx, hipEventSynchronize(ctx->rb_event));
+    else
+      HIPCHK(ctx, hipStreamSynchronize(s));
+    if (held > 0) {
+      if (h.status == plc::ST_SWEPT) {
+        if (next_pre) *next_pre = held;  // the next query started behind this one
+      } else {
+        // its initialisation stood aside and the chunk continued this query's
+        // push: wait for it and read the state again; the next query starts
+        // afresh later
+        HIPCHK(ctx, hipMemcpyAsync(&h, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(ctx, hipStreamSynchronize(s));
+        if (!h.init_held) {  // unexpected: the guard let a query start over this one
+          ctx->broken = true;
+          return PLC_E_HIP;
+        }
+        queued += held;
+      }
+    }
     if (ctx->timing) {
       // only the launches that did work count (pairs past the end of the
       // push, and scatters after a self launch that ran the rounds itself,
@@ -796,6 +863,7 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
   plc_status first = PLC_OK;
+  int pre = 0;  // the current query's queued first chunk (see run_one)
   for (int32_t i = 0; i < count; i++) {
     if (!query_ok(g, q[i])) {
       if (ids) ids[i] = 0;
@@ -806,7 +874,12 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
       if (first == PLC_OK) first = PLC_E_INVALID;
       continue;
     }
-    plc_status st = run_one(ctx, g, q[i], ids ? &ids[i] : nullptr, infos ? &infos[i] : nullptr);
+    // the next query (when valid) is queued behind this one's first read-back
+    const plc_query* nq = i + 1 < count && query_ok(g, q[i + 1]) ? &q[i + 1] : nullptr;
+    int next_pre = 0;
+    plc_status st = run_one(ctx, g, q[i], ids ? &ids[i] : nullptr, infos ? &infos[i] : nullptr,
+                            nullptr, 0, 1.0, pre, nq, &next_pre);
+    pre = next_pre;
     if (st == PLC_E_HIP) return st;
     if (st != PLC_OK && first == PLC_OK) first = st;
   }

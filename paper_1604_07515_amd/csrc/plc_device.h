@@ -97,7 +97,8 @@ struct __align__(64) Ctl {
   // launches that did work; loop_rounds / loop_pushes / loop_edges count
   // the small rounds a self launch ran on its own
   int32_t selfed, steps;
-  int32_t loop_rounds, pad2;
+  int32_t loop_rounds;
+  int32_t init_held;  // a queued guarded initialisation found the previous query unfinished
   long long loop_pushes, loop_edges;
 };
 
@@ -167,6 +168,12 @@ static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
 hipError_t launch_query_init(hipStream_t s, const PlainArgs& a, int32_t seed, int32_t rule,
                              double alpha, double eps, int32_t max_rounds, double beta = 1.0);
+// The same, queued before the previous query is known to have finished: it
+// initialises only if that query was swept (else it sets init_held and
+// leaves the state alone, so rounds queued behind it continue the previous
+// query's push).
+hipError_t launch_query_init_guarded(hipStream_t s, const PlainArgs& a, int32_t seed,
+                                     int32_t rule, double alpha, double eps, int32_t max_rounds);
 // beta variant: before a round, rank the active frontier by r/d and keep the
 // top ceil(beta |F|) in front as the round's frontier; after it, append the
 // rest to the next frontier (max_count bounds the frontier for the sort)

@@ -235,6 +235,41 @@ def test_sweep_queued_behind_push(plc):
         check_query(pg, c.result(ids[0], release=True), 0, 0.01, 1e-8, OPT)
 
 
+def test_queries_pipelined_in_one_call(plc):
+    """In one plc_run call the next query's initialisation and first chunk
+    are queued behind the running query's read-back.  When that query still
+    needs work (more rounds, or the sweep for a larger support), the queued
+    initialisation stands aside and its rounds continue the running query.
+    A fresh context and a mix of tiny and large queries (hub with eps 1e-2 /
+    1e-7, an invalid seed in between, both rules) cover both cases; every
+    result matches the oracle and equals the same query run alone."""
+    g = synth.rmat(13, 8, seed=4)
+    hub = int(np.argmax(g.deg))
+    xs = [int(v) for v in synth.uniform_seeds(g, 4, seed=31)]
+    seeds = [hub, xs[0], hub, xs[1], -1, hub, xs[2], hub, xs[3], xs[0]]
+    eps = [1e-2, 1e-6, 1e-7, 1e-2, 1e-5, 1e-2, 1e-7, 1e-6, 1e-2, 1e-8]
+    rules = [OPT, OPT, OPT, ORIG, OPT, OPT, OPT, ORIG, OPT, OPT]
+    with plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (64 << 20)) as c:
+        hg = c.load_graph(g.off, g.nbr)
+        say("case pipelined plc_run:", list(zip(seeds, eps, rules)))
+        ids, infos = c.run(hg, seeds, 0.01, eps, rules, check=False)
+        alone = []
+        for x, e, r in zip(seeds, eps, rules):
+            if x < 0:
+                alone.append(None)
+                continue
+            i1, _ = c.run(hg, [x], 0.01, e, r)
+            alone.append(c.result(i1[0], release=True))
+        for qid, info, x, e, r, ref in zip(ids, infos, seeds, eps, rules, alone):
+            if x < 0:
+                assert qid == 0 and info["status"] == plc.PLC_E_INVALID
+                continue
+            res = c.result(qid, release=True)
+            out = check_query(g, res, x, 0.01, e, r)
+            if not out["tie_push"]:
+                check_same(g, res, ref)
+
+
 def test_result_block_does_not_fit(plc):
     """No room for a query's result block: the query reports PLC_E_NOMEM
     with its counters (the sweep itself writes into the library's buffers),
