@@ -132,7 +132,9 @@ typedef struct {
   int64_t loop_edges;
   /* plain path only (0 elsewhere): wall time in the library from the
    * query's start to its recorded result (push, sweep and read-backs; the
-   * copy into the result block is queued), in nanoseconds */
+   * copy into the result block is queued), in nanoseconds.  A query queued
+   * behind the previous one of the same plc_run call starts when that one
+   * is known to be done. */
   int64_t host_ns;
 } plc_result_info;
 

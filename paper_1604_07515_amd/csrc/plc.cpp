@@ -162,7 +162,7 @@ struct plc_ctx {
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
   std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
-  std::chrono::steady_clock::time_point next_t0;  // plain path: when the next query was queued
+  std::chrono::steady_clock::time_point next_t0;  // plain path: start of the queued next query
   hipEvent_t rb_event = nullptr;  // plain path: recorded after the running query's read-back
   std::vector<int32_t> work_log_h = std::vector<int32_t>(2 * plc::kMaxChunk);
   bool use_graphs = false;            // replay captured graphs (PLC_LAUNCH_GRAPH)
@@ -624,7 +624,6 @@ static int prelaunch(plc_ctx* ctx, plc_graph* g, const plc_query& q) {
     ctx->broken = true;
     return -1;
   }
-  ctx->next_t0 = std::chrono::steady_clock::now();
   return R;
 }
 
@@ -702,7 +701,10 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       HIPCHK(ctx, hipStreamSynchronize(s));
     if (held > 0) {
       if (h.status == plc::ST_SWEPT) {
-        if (next_pre) *next_pre = held;  // the next query started behind this one
+        // the next query started behind this one: its time counts from here,
+        // when this one is known to be done
+        if (next_pre) *next_pre = held;
+        ctx->next_t0 = std::chrono::steady_clock::now();
       } else {
         // its initialisation stood aside and the chunk continued this query's
         // push: wait for it and read the state again; the next query starts
