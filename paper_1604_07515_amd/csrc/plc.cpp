@@ -7,7 +7,10 @@
 // the sweep sequence for the largest recent support (it runs only if the
 // push has ended within that bound), then reads the control block back; an
 // unfinished push gets short further chunks, and a larger support the sweep
-// for its own bound, each with a read-back.  Results are copied
+// for its own bound, each with a read-back.  Within one plc_run call the
+// next query's guarded initialisation and first chunk are queued behind the
+// running query's first read-back (they stand aside on the device while the
+// running query is unfinished), so the GPU works while the host reads back.  Results are copied
 // device-to-device into an exact-size arena block, and the dense per-vertex
 // state is reset through the touched list.  The batch engine (plc_batch_reserve and after)
 // runs many queries per launch.
