@@ -425,6 +425,37 @@ def bench_hkpr(plc, synth, g, seeds):
     return out, nb
 
 
+def one_at_a_time(plc, g, seeds, alpha=0.01, eps=1e-7):
+    """Plain PR-Nibble + sweep queries on g one at a time (each its own
+    plc_run call, timed from the host), after an autotune and two warm
+    queries.  Returns the open context, the graph handle and the figures."""
+    import torch
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (256 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+    ctx.autotune(hg, seeds[:2], alpha, eps, plc.PLC_TUNE_PLAIN)
+    for s in seeds[:2]:
+        ids, _ = ctx.run(hg, [s], alpha, eps)
+        ctx.release(ids[0])
+    lat, acc = [], {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in seeds:
+        q0 = time.perf_counter()
+        ids, infos = ctx.run(hg, [s], alpha, eps)
+        lat.append(time.perf_counter() - q0)
+        account(acc, infos, ids, ctx)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    nq = len(seeds)
+    per = el / nq
+    return ctx, hg, {"n": g.n, "arcs": g.arcs, "alpha": alpha, "eps": eps, "queries": nq,
+                     "seconds_per_query": per, "queries_per_s": nq / el,
+                     "edges_per_s": acc["edges"] / el,
+                     "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
+                     "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds",
+                                                            "support")}}
+
+
 def bench_grid3d(plc, synth, side=215, nq=8):
     """The paper's 3D-grid input (a side^3 torus, every vertex of degree 6;
     side 215 gives its n = 9,938,375 and 3n edges): one PR-Nibble + sweep at a
@@ -436,39 +467,38 @@ def bench_grid3d(plc, synth, side=215, nq=8):
     g = synth.torus3d(side)
     log("grid3d %d^3: n=%d arcs=%d (%.1fs)" % (side, g.n, g.arcs, time.time() - t0))
     seeds = [int(x) for x in np.random.default_rng(3).integers(0, g.n, nq)]
-    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (256 << 20))
-    hg = ctx.load_graph(g.off, g.nbr)
-    ctx.autotune(hg, seeds[:2], 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
-    for s in seeds[:2]:
-        ids, _ = ctx.run(hg, [s], 0.01, 1e-7)
-        ctx.release(ids[0])
-    lat, acc = [], {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
-    import torch
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s in seeds:
-        q0 = time.perf_counter()
-        ids, infos = ctx.run(hg, [s], 0.01, 1e-7)
-        lat.append(time.perf_counter() - q0)
-        account(acc, infos, ids, ctx)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
+    ctx, hg, out = one_at_a_time(plc, g, seeds)
     hk = hkpr_timed(ctx, hg, seeds)
     nb = nibble_timed(ctx, hg, seeds)
     ctx.close()
-    per = el / nq
     hk["paper_40core_seconds_per_query"] = 0.049
     hk["paper_1thread_seconds_per_query"] = 0.01
     nb["paper_40core_seconds_per_query"] = 0.040
     nb["paper_1thread_seconds_per_query"] = 0.01
-    return {"workload": "torus%d_3dgrid_plain" % side, "n": g.n, "arcs": g.arcs, "hkpr": hk,
-            "nibble": nb,
-            "alpha": 0.01, "eps": 1e-7, "queries": nq, "seconds_per_query": per,
-            "queries_per_s": nq / el, "edges_per_s": acc["edges"] / el,
-            "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
-            "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
-            "paper_40core_seconds_per_query": 0.502,
-            "speedup_vs_paper_40core": 0.502 / per}
+    out.update({"workload": "torus%d_3dgrid_plain" % side, "hkpr": hk, "nibble": nb,
+                "paper_40core_seconds_per_query": 0.502,
+                "speedup_vs_paper_40core": 0.502 / out["seconds_per_query"]})
+    return out
+
+
+def bench_randlocal(plc, synth, n=10_000_000, nq=8):
+    """The paper's randLocal input at its size (n = 10^7, five drawn
+    neighbours per vertex, offsets favouring near ids; 49.1 M distinct edges):
+    one PR-Nibble + sweep at a time, alpha 0.01, eps 1e-7, optimized rule,
+    seeds uniform over all vertices (every vertex has degree >= 2), against
+    the paper's PR-Nibble timing on it (40 cores: 1.250 s per query; one
+    thread 28.90 s)."""
+    t0 = time.time()
+    g = synth.rand_local(n)
+    log("randlocal n=%d: arcs=%d (%.1fs)" % (g.n, g.arcs, time.time() - t0))
+    seeds = [int(x) for x in synth.uniform_seeds(g, nq, seed=2)]
+    ctx, hg, out = one_at_a_time(plc, g, seeds)
+    ctx.close()
+    out.update({"workload": "randlocal%d_k5_plain" % n,
+                "paper_40core_seconds_per_query": 1.250,
+                "paper_1thread_seconds_per_query": 28.90,
+                "speedup_vs_paper_40core": 1.250 / out["seconds_per_query"]})
+    return out
 
 
 def cpu_baseline(oracle, g, work, budget):
@@ -520,7 +550,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["plain", "batched", "serving", "large", "grid3d"],
+    ap.add_argument("--only", choices=["plain", "batched", "serving", "large", "grid3d",
+                                       "randlocal"],
                     default=None,
                     help="run one workload only (the others are reported as skipped); "
                          "'large' (R-MAT 2^26, 1024 seeds) runs only when asked for")
@@ -591,6 +622,11 @@ def main():
             "Nibble %.2f ms" % (grid["seconds_per_query"] * 1e3, grid["speedup_vs_paper_40core"],
                                 grid["hkpr"]["seconds_per_query"] * 1e3,
                                 grid["nibble"]["seconds_per_query"] * 1e3))
+    rloc = bench_randlocal(plc, synth) if want("randlocal") else None
+    if rloc:
+        log("randlocal: %.2f ms per query (%.0fx the paper's 40-core time), %.3g edges/s" % (
+            rloc["seconds_per_query"] * 1e3, rloc["speedup_vs_paper_40core"],
+            rloc["edges_per_s"]))
     big = bench_large(plc, synth) if args.only == "large" else None
     if big:
         log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
@@ -613,7 +649,7 @@ def main():
                     "alpha": 0.01, "eps": 1e-7, "rule": "optimized", "queries_per_step": 16,
                     "path": "plain (one query at a time)"} if plain else
                    {"workload": bat["workload"], "n": g.n, "arcs": g.arcs} if bat else
-                   {"workload": (srv or big or grid or {}).get("workload")}),
+                   {"workload": (srv or big or grid or rloc or {}).get("workload")}),
     }
     if main_res:
         out["queries_per_s"] = main_res["queries_per_s"]
@@ -632,6 +668,8 @@ def main():
         out["large"] = big
     if grid:
         out["grid3d"] = grid
+    if rloc:
+        out["randlocal"] = rloc
     if rules:
         out["rules"] = rules
     if hkpr:

@@ -66,3 +66,27 @@ def test_query_generators():
     s = synth.uniform_seeds(g, 16, seed=2)
     assert np.array_equal(s, synth.uniform_seeds(g, 16, seed=2))
     assert synth.largest_component_min_vertex(g) == 0
+
+
+def test_rand_local_matches_paper_edge_count():
+    """The randLocal reading (offsets log-uniform on [1, 30000]) at the
+    paper's size: n = 10^7, five draws per vertex leave within 0.1 % of the
+    49,100,524 distinct edges its table of inputs lists (Sec. 5)."""
+    n = 10_000_000
+    e = synth.rand_local_edges(n)
+    a, b = np.minimum(e[:, 0], e[:, 1]), np.maximum(e[:, 0], e[:, 1])
+    keep = a != b
+    distinct = np.unique(a[keep] * n + b[keep]).size
+    assert abs(distinct / 49_100_524 - 1) < 1e-3, distinct
+
+
+def test_rand_local_small():
+    g = synth.rand_local(5000, seed=3)
+    synth.validate(g)
+    h = synth.rand_local(5000, seed=3)
+    assert np.array_equal(g.off, h.off) and np.array_equal(g.nbr, h.nbr)
+    # every arc joins ids at most the offset range apart (around the cycle)
+    src = np.repeat(np.arange(g.n), g.deg)
+    gap = np.abs(src - g.nbr.astype(np.int64))
+    assert np.all(np.minimum(gap, g.n - gap) <= synth.RANDLOCAL_RANGE)
+    assert g.deg.min() >= 1 and 9.0 < g.arcs / g.n < 10.0
