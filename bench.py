@@ -481,6 +481,34 @@ def bench_grid3d(plc, synth, side=215, nq=8):
     return out
 
 
+def randlocal_batched(plc, synth, g, nq=256, table_gib=64):
+    """nq queries at once (same setting as the plain leg, seeds uniform over
+    all vertices) through the compact-table engine, one slot per query; one
+    warm batch of 16, then the timed batch."""
+    import torch
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                      + plc.batch_arena_bytes(g.n, g.arcs, nq, compact=True,
+                                              table_bytes=table_gib << 30), compact=True)
+    hg = ctx.load_graph(g.off, g.nbr)
+    assert ctx.batch_reserve(hg, nq) == nq
+    ids, _ = ctx.run_batched(hg, [int(x) for x in synth.uniform_seeds(g, 16, seed=4)],
+                             0.01, 1e-7)
+    for q in ids:
+        ctx.release(q)
+    seeds = [int(x) for x in synth.uniform_seeds(g, nq, seed=2)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ids, infos = ctx.run_batched(hg, seeds, 0.01, 1e-7)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    edges = sum(int(i["edges"]) for i in infos)
+    for q in ids:
+        ctx.release(q)
+    ctx.close()
+    return {"queries": nq, "slots": nq, "seconds": el, "queries_per_s": nq / el,
+            "edges_per_s": edges / el, "per_query_edges": edges / nq}
+
+
 def bench_randlocal(plc, synth, n=10_000_000, nq=8):
     """The paper's randLocal input at its size (n = 10^7, five drawn
     neighbours per vertex, offsets favouring near ids; 49.1 M distinct edges):
@@ -494,6 +522,7 @@ def bench_randlocal(plc, synth, n=10_000_000, nq=8):
     seeds = [int(x) for x in synth.uniform_seeds(g, nq, seed=2)]
     ctx, hg, out = one_at_a_time(plc, g, seeds)
     ctx.close()
+    out["batched_compact"] = randlocal_batched(plc, synth, g)
     out.update({"workload": "randlocal%d_k5_plain" % n,
                 "paper_40core_seconds_per_query": 1.250,
                 "paper_1thread_seconds_per_query": 28.90,
@@ -624,9 +653,11 @@ def main():
                                 grid["nibble"]["seconds_per_query"] * 1e3))
     rloc = bench_randlocal(plc, synth) if want("randlocal") else None
     if rloc:
-        log("randlocal: %.2f ms per query (%.0fx the paper's 40-core time), %.3g edges/s" % (
-            rloc["seconds_per_query"] * 1e3, rloc["speedup_vs_paper_40core"],
-            rloc["edges_per_s"]))
+        log("randlocal: %.2f ms per query (%.0fx the paper's 40-core time), %.3g edges/s; "
+            "batched (compact): %.1f queries/s, %.3g edges/s" % (
+                rloc["seconds_per_query"] * 1e3, rloc["speedup_vs_paper_40core"],
+                rloc["edges_per_s"], rloc["batched_compact"]["queries_per_s"],
+                rloc["batched_compact"]["edges_per_s"]))
     big = bench_large(plc, synth) if args.only == "large" else None
     if big:
         log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
