@@ -13,3 +13,13 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_legs_listed_in_help():
+    """Every leg that --only selects is named in the help text, the
+    paper's two synthetic inputs included."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0
+    for leg in ("plain", "batched", "serving", "large", "grid3d", "randlocal"):
+        assert leg in r.stdout, leg
