@@ -116,3 +116,29 @@ def test_beta_rejects_bad_parameters(ctx):
         with pytest.raises(plc.PlcError) as e:
             ctx.run_beta(hg, 0, 0.01, 1e-6, beta)
         assert e.value.code == plc.PLC_E_INVALID
+
+
+@pytest.mark.parametrize("rounds,support", [(1, [0]), (2, [0, 1]), (3, [0, 1, 2, 3])])
+def test_beta_selection_rule_hand_derived(rounds, support):
+    """The hand-derived selection case of the oracle's pins (path 2-1-0-3 with
+    leaves 4, 5 on vertex 3; alpha 1/3, eps 1e-3, beta 1/2, seed 0), stopped
+    by the round watchdog after 1, 2 and 3 rounds: the GPU picks the
+    ceil(beta |S|) largest r/d each round, so p and r equal the derived
+    values (round 3 pushes 3 and 2: by r alone it would push 3 and 0, by the
+    smallest r/d 0 and 2, and floor would push 3 alone)."""
+    import paper_1604_07515_amd as plc
+    g = synth.from_edges(6, [(0, 1), (0, 3), (1, 2), (3, 4), (3, 5)])
+    want_p = {1: [1 / 2, 0, 0, 0, 0, 0], 2: [1 / 2, 1 / 8, 0, 0, 0, 0],
+              3: [1 / 2, 1 / 8, 1 / 32, 1 / 8, 0, 0]}[rounds]
+    want_r = {1: [0, 1 / 4, 0, 1 / 4, 0, 0], 2: [1 / 16, 0, 1 / 16, 1 / 4, 0, 0],
+              3: [1 / 16 + 1 / 24, 1 / 32, 0, 0, 1 / 24, 1 / 24]}[rounds]
+    with plc.Context(arena_bytes=64 << 20, max_rounds=rounds) as c:
+        hg = c.load_graph(g.off, g.nbr, validate=True)
+        qid, info = c.run_beta(hg, 0, 1.0 / 3.0, 1e-3, 0.5)
+        say("case beta hand-derived rounds", rounds, info)
+        assert info["status"] == plc.PLC_E_LIMIT and info["rounds"] == rounds
+        res = c.result(qid, release=True)
+        p, r = res.dense_p(6), res.dense_r(6)
+        assert np.flatnonzero(p > 0).tolist() == support
+        assert np.allclose(p, want_p, rtol=1e-14, atol=0)
+        assert np.allclose(r, want_r, rtol=1e-14, atol=0)
