@@ -83,12 +83,23 @@ typedef struct plc_graph plc_graph;
 #define PLC_STATE_DENSE 0
 #define PLC_STATE_COMPACT 1
 
+/*
+ * The plain path's edge scatter (Sec. 3.3, UpdateNgh as a fetch-and-add) has
+ * two forms.  Small rounds: one FP64 atomic add per edge.  Rounds of at
+ * least bin_min_edges edges: destination-binned -- the round's (neighbour,
+ * entry) pairs are sorted by destination range, each range's contributions
+ * are summed in LDS, and every touched r[w] gets one update.  Results agree
+ * to the order of the additions.  bin_min_edges: 0 = 524288, < 0 = always
+ * the atomic form.  (Graphs of more than 6,291,456 = 1536 x 4096 vertices
+ * always use the atomic form.)
+ */
 typedef struct {
   int32_t max_rounds;  /* watchdog on PR-Nibble rounds per query; 0 = 1<<20 */
   int32_t batch_slots; /* concurrent queries in the batched path; 0 = 256   */
   int32_t launch_mode; /* PLC_LAUNCH_GRAPH or PLC_LAUNCH_DIRECT             */
   int32_t batch_state; /* PLC_STATE_DENSE or PLC_STATE_COMPACT              */
-  int32_t reserved[4];
+  int32_t bin_min_edges; /* smallest plain round scattered through bins     */
+  int32_t reserved[3];
 } plc_options;
 
 /*
@@ -102,7 +113,15 @@ typedef struct {
   uint32_t rule; /* PLC_RULE_OPT or PLC_RULE_ORIG */
   double alpha;
   double eps;
+  uint32_t flags;    /* PLC_QF_* */
+  uint32_t reserved; /* 0 */
 } plc_query;
+
+/* plc_query flags.  PLC_QF_NO_RESIDUAL: the result keeps p and the cluster
+ * but not the final residual (r_nnz is still reported; plc_result_copy then
+ * returns no r entries), for callers that only want the cluster. */
+#define PLC_QF_NO_RESIDUAL 1u
+#define PLC_QF_ALL 1u
 
 typedef struct {
   int64_t n;           /* vertices                              */
@@ -136,6 +155,16 @@ typedef struct {
    * behind the previous one of the same plc_run call starts when that one
    * is known to be done. */
   int64_t host_ns;
+  /* device time of the query, from the GPU's constant-rate clock (read by
+   * the kernels themselves): plain path, from its initialisation kernel to
+   * the end of its sweep; batched path, from its admission into a slot to the
+   * end of its sweep (so it includes rounds shared with other queries) */
+  int64_t device_ns;
+  /* plain path only: rounds whose edge scatter went through the destination
+   * bins (plc_options.bin_min_edges), and their edges */
+  int32_t bin_rounds;
+  uint32_t flags;     /* the query's flags */
+  int64_t bin_edges;
 } plc_result_info;
 
 /* Status code to a static string. */

@@ -32,6 +32,7 @@ PLC_LAUNCH_GRAPH = 0
 PLC_LAUNCH_DIRECT = 1
 PLC_STATE_DENSE = 0
 PLC_STATE_COMPACT = 1
+PLC_QF_NO_RESIDUAL = 1
 
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
@@ -53,12 +54,12 @@ class PlcError(RuntimeError):
 class plc_options(C.Structure):
     _fields_ = [("max_rounds", C.c_int32), ("batch_slots", C.c_int32),
                 ("launch_mode", C.c_int32), ("batch_state", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("bin_min_edges", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class plc_query(C.Structure):
     _fields_ = [("seed", C.c_int32), ("rule", C.c_uint32), ("alpha", C.c_double),
-                ("eps", C.c_double)]
+                ("eps", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class plc_graph_info(C.Structure):
@@ -71,7 +72,9 @@ class plc_result_info(C.Structure):
                 ("edges", C.c_int64), ("support", C.c_int64), ("kstar", C.c_int64),
                 ("cut", C.c_int64), ("vol", C.c_int64), ("phi", C.c_double),
                 ("r_nnz", C.c_int64), ("launches", C.c_int32), ("loop_rounds", C.c_int32),
-                ("loop_edges", C.c_int64), ("host_ns", C.c_int64)]
+                ("loop_edges", C.c_int64), ("host_ns", C.c_int64),
+                ("device_ns", C.c_int64), ("bin_rounds", C.c_int32), ("flags", C.c_uint32),
+                ("bin_edges", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -217,7 +220,7 @@ class Context:
     """A libplc context on one GPU, with a torch-owned arena and stream."""
 
     def __init__(self, arena_bytes: int, device: int = 0, stream=None, max_rounds: int = 0,
-                 graphs: bool = True, compact: bool = False):
+                 graphs: bool = True, compact: bool = False, bin_min_edges: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libplc needs a GPU; torch.cuda.is_available() is False")
@@ -233,6 +236,7 @@ class Context:
         opt.max_rounds = max_rounds
         opt.launch_mode = PLC_LAUNCH_GRAPH if graphs else PLC_LAUNCH_DIRECT
         opt.batch_state = PLC_STATE_COMPACT if compact else PLC_STATE_DENSE
+        opt.bin_min_edges = int(bin_min_edges)
         h = C.c_void_p()
         _check(self.lib.plc_init(C.byref(h), device, C.c_void_p(aligned), int(arena_bytes),
                                  C.c_void_p(self.stream.cuda_stream), C.byref(opt)), "plc_init")
@@ -263,19 +267,20 @@ class Context:
         return Graph(self, h, n, len(nbr))
 
     @staticmethod
-    def queries(seeds, alpha, eps, rule=PLC_RULE_OPT):
+    def queries(seeds, alpha, eps, rule=PLC_RULE_OPT, flags=0):
         if isinstance(seeds, (int, np.integer)):
             seeds = (seeds,)
         if isinstance(seeds, (list, tuple)) and all(np.isscalar(x) for x in (alpha, eps, rule)):
             # one parameter set for all seeds: no array broadcasting
             qa = (plc_query * len(seeds))()
-            a, e, r = float(alpha), float(eps), int(rule)
+            a, e, r, f = float(alpha), float(eps), int(rule), int(flags)
             for i, s in enumerate(seeds):
                 q = qa[i]
                 q.seed = int(s)
                 q.rule = r
                 q.alpha = a
                 q.eps = e
+                q.flags = f
             return qa
         seeds = np.atleast_1d(np.asarray(seeds, dtype=np.int64))
         k = len(seeds)
@@ -288,11 +293,13 @@ class Context:
             qa[i].rule = int(rule[i])
             qa[i].alpha = float(alpha[i])
             qa[i].eps = float(eps[i])
+            qa[i].flags = int(flags)
         return qa
 
-    def run(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+    def run(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True,
+                flags: int = 0):
         """Plain path: queries one after another.  Returns (ids, infos)."""
-        qa = self.queries(seeds, alpha, eps, rule)
+        qa = self.queries(seeds, alpha, eps, rule, flags)
         k = len(qa)
         ids = (C.c_uint64 * k)()
         infos = (plc_result_info * k)()
@@ -355,8 +362,9 @@ class Context:
                "plc_batch_reserve")
         return got.value
 
-    def submit(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
-        qa = self.queries(seeds, alpha, eps, rule)
+    def submit(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True,
+                   flags: int = 0):
+        qa = self.queries(seeds, alpha, eps, rule, flags)
         ids = (C.c_uint64 * len(qa))()
         rc = self.lib.plc_submit(self.handle, g.handle, qa, len(qa), ids)
         if check and rc != PLC_OK:
@@ -396,9 +404,10 @@ class Context:
         qa = self.queries([seed], alpha, eps, rule)
         return int(self.lib.plc_query_bytes_estimate(g.handle, qa))
 
-    def run_batched(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True):
+    def run_batched(self, g: Graph, seeds, alpha, eps, rule=PLC_RULE_OPT, check: bool = True,
+                        flags: int = 0):
         """Batched path: submit all and step until every query has finished."""
-        qa = self.queries(seeds, alpha, eps, rule)
+        qa = self.queries(seeds, alpha, eps, rule, flags)
         k = len(qa)
         ids = (C.c_uint64 * k)()
         infos = (plc_result_info * k)()
@@ -424,6 +433,8 @@ class Context:
         info = plc_result_info()
         _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)), "plc_result_info_get")
         N, R = info.support, info.r_nnz
+        if info.flags & PLC_QF_NO_RESIDUAL:
+            R = 0  # the result keeps no residual vector
         ids = np.empty(N, np.int32)
         p = np.empty(N, np.float64)
         rid = np.empty(R, np.int32)
@@ -475,4 +486,9 @@ def plain_arena_bytes(n: int, arcs: int) -> int:
     per_arc = 4               # neighbour ids
     tiles = 4 * (arcs // 1024 + 2)
     scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
-    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + (64 << 20) + 8 * 1025 + 2048)
+    # binned scatter: pairs (8 B per edge of the largest binned round, at most
+    # 2^23) and the per-chunk run table (2049 ints per 4096-edge chunk)
+    chunks = (min(max(arcs, 1), 1 << 23) + 4095) // 4096
+    bins = n // 16 + 8 * 2048 + chunks * (8 * 4096 + 4 * 2049) + 5 * 256
+    return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + bins + (64 << 20)
+               + 8 * 1025 + 2048)

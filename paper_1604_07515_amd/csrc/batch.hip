@@ -243,6 +243,8 @@ __global__ void k_b_admit(BatchArgs a, const Admit* adm, int count) {
     S.touched[0] = ad.seed;
     VRec* rec = St::insert(S, ad.seed);  // a fresh (cleared) table: never full
     if (rec) rec->r = 1.0; else S.fault = 1;
+    S.t_admit = (long long)wall_clock64();
+    S.t_done = 0;
     S.status = SL_PUSH;
   }
 }
@@ -1012,6 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_argmin(BatchArgs a) {
     S.best_den = k > 0 ? s_d[0] : 0;
     S.best_vol = k > 0 ? a.svol[off + k - 1] - bv : 0;
     S.phi = k > 0 ? (double)s_c[0] / (double)s_d[0] : 0.0;
+    S.t_done = (long long)wall_clock64();
   }
 }
 

@@ -61,6 +61,8 @@ struct __align__(64) Slot {
   int32_t* touched;
   int32_t mask;             // compact: table capacity - 1
   int32_t list_cap;         // capacity of each list
+  // constant-rate clock (wall_clock64) at admission and at the sweep's argmin
+  long long t_admit, t_done;
 };
 
 // One query's part of a sweep batch (written by the host before the sweep).

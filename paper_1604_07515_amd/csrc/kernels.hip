@@ -61,6 +61,10 @@ __device__ __forceinline__ void reset_round_book(Ctl* c) {
   c->loop_rounds = 0;
   c->loop_pushes = 0;
   c->loop_edges = 0;
+  c->bin_rounds = 0;
+  c->bin_edges = 0;
+  c->t_start = (long long)wall_clock64();
+  c->t_end = 0;
 }
 
 // Seed initialisation (Fig. alg:pr-nibble: r = {(x,1)}, Frontier = {x}).
@@ -177,7 +181,6 @@ __global__ void k_query_init_set(PlainArgs a, int32_t nseeds, int32_t rule, doub
     c->kstar = 0;
     c->phi = 0.0;
     reset_round_book(c);
-  reset_round_book(c);
     c->status = ST_PUSH;
   }
   const double share = 1.0 / (double)nseeds;
@@ -600,6 +603,389 @@ __global__ __launch_bounds__(kBlock) void k_self(PlainArgs a, int slot) {
 __global__ __launch_bounds__(kBlock) void k_hk_self(PlainArgs a) { self_body<kModeHK>(a, -1); }
 __global__ __launch_bounds__(kBlock) void k_nb_self(PlainArgs a) { self_body<kModeNB>(a, -1); }
 
+// ------------------------------------------------- binned edge scatter
+//
+// For a large round, one FP64 atomic per edge is bound by contention on the
+// lines of high-degree destinations.  The binned form of the same edgeMap
+// (Figs. alg:pr-nibble / alg:pr-nibble2, UpdateNgh) groups the round's
+// (neighbour, entry) pairs by destination bin, adds each bin's contributions
+// in LDS and applies one update per distinct destination:
+//   pass A (in k_scatter): every chunk of kBinChunk consecutive edges is
+//     sorted by bin in place (a counting sort: LDS histogram with ranks, one
+//     workgroup scan) into bin_pairs[chunk], and the start of every bin's run
+//     in the chunk goes to bin_T (bin-major).  No global atomics.
+//   pass B (k_bin_apply): one item per bin, or per slice of the chunks for a
+//     bin whose expected share of the round's edges exceeds kBinQ.  The item
+//     gathers its runs, adds every contribution into an LDS array over the
+//     bin's vertex range (first touches listed), then updates each touched
+//     destination once: a plain read-modify-write of r when the item owns the
+//     whole bin (no other workgroup writes those records in this launch), a
+//     device-scope atomic when the bin is split.  The filter is folded in as
+//     in the atomic scatter: r only grows, so w joins the next frontier when
+//     its single update (old, old + sum) straddles eps d(w).
+// The sum of a destination's contributions is formed in another order than
+// in a sequence of atomics; that is the only difference.
+
+// LDS of the scatter launch: the atomic scatter's arrays or pass A's, which
+// never run in the same launch.
+struct ScatterLds {
+  int32_t start[kEdgeTile + 1];
+  int64_t row[kEdgeTile + 1];
+  double coef[kEdgeTile + 1];
+  int32_t fn[kEdgeTile];
+  int32_t tv[kEdgeTile];
+  int nfn, ntv, base, last;
+};
+struct BinSortLds {
+  int32_t start[kEdgeTile + 1];
+  int64_t row[kEdgeTile + 1];
+  int hist[kMaxBins + kBlock];
+  int sh[kBlock / 64 + 1];
+};
+union ScatterShared {
+  ScatterLds at;
+  BinSortLds bs;
+};
+
+__device__ __forceinline__ bool bin_round(const PlainArgs& a, long long E) {
+  return a.nbins > 0 && E >= a.bin_emin && E <= (long long)a.bin_cmax * kBinChunk;
+}
+
+// Exclusive scan over the workgroup of one int per thread; sh holds
+// kBlock/64 + 1 slots.  Every thread must call it.
+__device__ __forceinline__ int block_excl_scan_int(int x, int* total, int* sh) {
+  int inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(inc, o);
+    if ((int)PLC_LANE >= o) inc += y;
+  }
+  if (PLC_LANE == 63) sh[PLC_WID] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < kBlock / 64; w++) {
+      const int v = sh[w];
+      sh[w] = acc;
+      acc += v;
+    }
+    sh[kBlock / 64] = acc;
+  }
+  __syncthreads();
+  const int ex = inc - x + sh[PLC_WID];
+  *total = sh[kBlock / 64];
+  __syncthreads();
+  return ex;
+}
+
+// Pass A, run by the scatter launch in place of the atomic scatter.
+// Workgroups take chunks in turn; a chunk's kBinChunkTiles tiles are staged
+// one at a time (entries in LDS, a binary search per edge as in the atomic
+// scatter).  The chunk's pairs stay in registers until the histogram scan.
+__device__ void bin_sort_chunks(const PlainArgs& a, int nf, BinSortLds& L) {
+  Ctl* c = a.ctl;
+  int32_t* const s_start = L.start;
+  int64_t* const s_row = L.row;
+  int* const s_hist = L.hist;
+  int* const sh = L.sh;
+  constexpr int kPer = kBinChunk / kBlock;           // edges per thread per chunk
+  constexpr int kBinsPT = kMaxBins / kBlock;         // bins per thread in the scan
+  const int nb = a.nbins;
+  const long long E = c->etotal;
+  const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
+  const int C = (int)((E + kBinChunk - 1) / kBinChunk);
+  for (int ch = blockIdx.x; ch < C; ch += gridDim.x) {
+    for (int b = threadIdx.x; b < nb; b += kBlock) s_hist[b] = 0;
+    __syncthreads();
+    int32_t w[kPer], ie[kPer], bk[kPer];  // bk: bin << 16 | rank within the chunk's bin
+#pragma unroll
+    for (int tt = 0; tt < kBinChunkTiles; tt++) {
+      const int tile = ch * kBinChunkTiles + tt;
+      const long long e0 = (long long)tile * kEdgeTile;
+      const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
+      int cnt = 0, i0 = 0;
+      if (tile < ntiles) {
+        i0 = a.tile_start[tile];
+        const int i1 = tile + 1 < ntiles ? a.tile_start[tile + 1] : nf - 1;
+        cnt = i1 - i0 + 1;
+        if (i0 < 0 || i1 < i0 || i1 >= nf || cnt > kEdgeTile + 1) {
+          c->fault = 1;  // inconsistent tile map: the tile is skipped, the fault reported
+          cnt = 0;
+        }
+        for (int j = threadIdx.x; j < cnt; j += kBlock) {
+          s_start[j] = (int32_t)(a.estart[i0 + j] - e0);
+          s_row[j] = a.rowp[i0 + j];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kEdgesPerThread; k++) {
+        const int rel = k * kBlock + (int)threadIdx.x;
+        const int x = tt * kEdgesPerThread + k;
+        w[x] = -1;
+        ie[x] = 0;
+        if (cnt > 0 && e0 + rel < e1) {
+          int lo = 0, hi = cnt - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
+          }
+          w[x] = a.nbr[s_row[lo] + (rel - s_start[lo])];
+          ie[x] = i0 + lo;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgesPerThread; k++) {
+        const int x = tt * kEdgesPerThread + k;
+        bk[x] = 0;
+        if (w[x] >= 0) {
+          const int b = a.bin_of_blk[w[x] / kBinGran];
+          bk[x] = (b << 16) | atomicAdd(&s_hist[b], 1);
+        }
+      }
+      __syncthreads();  // before the next tile's entries are staged
+    }
+    // run starts: exclusive prefix of the histogram (kBinsPT bins per thread)
+    int loc[kBinsPT];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kBinsPT; k++) {
+      const int b = (int)threadIdx.x * kBinsPT + k;
+      loc[k] = b < nb ? s_hist[b] : 0;
+      tsum += loc[k];
+    }
+    int total;
+    int ex = block_excl_scan_int(tsum, &total, sh);
+#pragma unroll
+    for (int k = 0; k < kBinsPT; k++) {
+      const int b = (int)threadIdx.x * kBinsPT + k;
+      if (b <= nb) {
+        s_hist[b] = ex;
+        a.bin_T[(size_t)b * a.bin_cmax + ch] = ex;
+      }
+      ex += loc[k];
+    }
+    __syncthreads();
+    int2* out = a.bin_pairs + (size_t)ch * kBinChunk;
+#pragma unroll
+    for (int x = 0; x < kPer; x++) {
+      if (w[x] >= 0) out[s_hist[bk[x] >> 16] + (bk[x] & 0xffff)] = make_int2(w[x], ie[x]);
+    }
+    __syncthreads();
+  }
+}
+
+// Pass B of a binned round, then the round's close.  Exits at once when the
+// round was not binned (k_scatter then closed it).
+__global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
+  Ctl* c = a.ctl;
+  int t, nf;
+  if (!push_active(c, a.n, &t, &nf)) return;
+  if (t >= c->max_rounds || c->selfed != t) return;
+  const long long E = c->etotal;
+  if (!bin_round(a, E)) return;
+  __shared__ double acc[kBinWidth];          // the item's sums, zero between items
+  __shared__ int32_t s_list[kBinWidth];      // first touches of the item (offsets in the bin)
+  __shared__ int s_items[kMaxBins + 1];      // first item of each bin
+  __shared__ int s_rs[kBinItemChunks];       // start of the item's run in each chunk
+  __shared__ int s_rp[kBinItemChunks + 1];   // exclusive prefix of the run lengths
+  __shared__ int sh[kBlock / 64 + 1];
+  __shared__ int s_nl, s_fb, s_tb, s_last;
+  constexpr int kBinsPT = kMaxBins / kBlock;
+  constexpr int kRunsPT = kBinItemChunks / kBlock;
+  constexpr int kListPT = kBinWidth / kBlock;
+  static_assert(kListPT <= 32, "flush masks are 32 bits");
+  static_assert(kBinWidth < 65536, "the flush packs two counts in one int");
+  const int nb = a.nbins;
+  const int C = (int)((E + kBinChunk - 1) / kBinChunk);
+  const double eps = c->eps;
+  int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
+  int32_t* cntn = &c->cnt[(t + 1) & 1];
+  for (int j = threadIdx.x; j < kBinWidth; j += kBlock) acc[j] = 0.0;
+  // items per bin: the bin's expected share of the round's edges (E vol_b /
+  // 2m) over kBinQ, at least enough that an item spans <= kBinItemChunks
+  // chunks, at most one per chunk; every workgroup computes the same table
+  {
+    const int smin = (C + kBinItemChunks - 1) / kBinItemChunks;
+    int loc[kBinsPT];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kBinsPT; k++) {
+      const int b = (int)threadIdx.x * kBinsPT + k;
+      int it = 0;
+      if (b < nb) {
+        const double expect = (double)E * (double)a.bin_vol[b] / (double)a.vol_total;
+        it = (int)ceil(expect / (double)kBinQ);
+        it = it > smin ? it : smin;
+        it = it < C ? it : C;
+        it = it > 1 ? it : 1;
+      }
+      loc[k] = it;
+      tsum += it;
+    }
+    int total;
+    int ex = block_excl_scan_int(tsum, &total, sh);
+#pragma unroll
+    for (int k = 0; k < kBinsPT; k++) {
+      const int b = (int)threadIdx.x * kBinsPT + k;
+      if (b < nb) s_items[b] = ex;
+      ex += loc[k];
+    }
+    if (threadIdx.x == 0) {
+      s_items[nb] = total;
+      s_nl = 0;
+    }
+    __syncthreads();
+  }
+  const int items = s_items[nb];
+  for (int it = blockIdx.x; it < items; it += gridDim.x) {
+    int lo = 0, hi = nb - 1;  // the bin: last b with s_items[b] <= it
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_items[mid] <= it) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    const int S = s_items[b + 1] - s_items[b];
+    const int sl = it - s_items[b];
+    const int c0 = (int)((long long)sl * C / S), c1 = (int)((long long)(sl + 1) * C / S);
+    const int nc = c1 - c0;
+    const int vlo = a.bin_lo[b];
+    const int W = a.bin_lo[b + 1] - vlo;
+    const bool own = S == 1;
+    // the item's runs
+    int rl[kRunsPT];
+    int lsum = 0;
+#pragma unroll
+    for (int k = 0; k < kRunsPT; k++) {
+      const int q = (int)threadIdx.x * kRunsPT + k;
+      rl[k] = 0;
+      if (q < nc) {
+        const int st = a.bin_T[(size_t)b * a.bin_cmax + c0 + q];
+        const int en = a.bin_T[(size_t)(b + 1) * a.bin_cmax + c0 + q];
+        s_rs[q] = (c0 + q) * kBinChunk + st;
+        rl[k] = en - st;
+        if (rl[k] < 0 || en > kBinChunk) { c->fault = 1; rl[k] = 0; }
+      }
+      lsum += rl[k];
+    }
+    int L;
+    int ex = block_excl_scan_int(lsum, &L, sh);
+#pragma unroll
+    for (int k = 0; k < kRunsPT; k++) {
+      const int q = (int)threadIdx.x * kRunsPT + k;
+      if (q < nc) s_rp[q] = ex;
+      ex += rl[k];
+    }
+    __syncthreads();
+    // add every contribution into the LDS array; the first toucher of an
+    // offset lists it
+    constexpr int kU = 4;
+    for (int j0 = 0; j0 < L; j0 += kBlock * kU) {
+      int2 pr[kU];
+#pragma unroll
+      for (int u = 0; u < kU; u++) {
+        const int j = j0 + u * kBlock + (int)threadIdx.x;
+        pr[u] = make_int2(-1, 0);
+        if (j < L) {
+          int l2 = 0, h2 = nc - 1;
+          while (l2 < h2) {
+            const int mid = (l2 + h2 + 1) >> 1;
+            if (s_rp[mid] <= j) l2 = mid; else h2 = mid - 1;
+          }
+          pr[u] = a.bin_pairs[s_rs[l2] + (j - s_rp[l2])];
+        }
+      }
+      double cf[kU];
+#pragma unroll
+      for (int u = 0; u < kU; u++) cf[u] = pr[u].x >= 0 && pr[u].y < nf ? a.coef[pr[u].y] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kU; u++) {
+        const int jl = pr[u].x - vlo;
+        bool first = false;
+        if (pr[u].x >= 0) {
+          // (contributions are positive, so exactly one addition per touched
+          // offset returns 0; an impossible zero one is not listed)
+          if (jl >= 0 && jl < W) first = atomicAdd(&acc[jl], cf[u]) == 0.0 && cf[u] != 0.0;
+          else c->fault = 1;
+        }
+        wave_append(first, jl, s_list, &s_nl);
+      }
+    }
+    __syncthreads();
+    // one update per touched destination
+    const int nl = s_nl;
+    unsigned fm = 0, tm = 0;
+    int nfl = 0, ntl = 0;
+    int32_t jv[kListPT];
+    double xv[kListPT];
+#pragma unroll
+    for (int m = 0; m < kListPT; m++) {
+      const int k = m * kBlock + (int)threadIdx.x;
+      jv[m] = -1;
+      xv[m] = 0.0;
+      if (k < nl) {
+        jv[m] = s_list[k];
+        xv[m] = acc[jv[m]];
+        acc[jv[m]] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kListPT; m++) {
+      if (jv[m] < 0) continue;
+      const int32_t w = vlo + jv[m];
+      double old, thr;
+      if (own) {
+        const VRec rec = a.vr[w];
+        old = rec.r;
+        a.vr[w].r = old + xv[m];
+        thr = eps * (double)rec.deg;
+      } else {
+        thr = eps * (double)a.vr[w].deg;
+        old = unsafeAtomicAdd(&a.vr[w].r, xv[m]);
+      }
+      if (old < thr && old + xv[m] >= thr) { fm |= 1u << m; nfl++; }
+      if (__double_as_longlong(old) == 0) { tm |= 1u << m; ntl++; }
+    }
+    // both counts in one scan (each total is at most kBinWidth < 2^16)
+    int both;
+    const int bex = block_excl_scan_int(nfl | (ntl << 16), &both, sh);
+    const int fex = bex & 0xffff, tex = bex >> 16;
+    const int NF = both & 0xffff, NT = both >> 16;
+    if (threadIdx.x == 0) {
+      s_fb = NF > 0 ? atomicAdd(cntn, NF) : 0;
+      s_tb = NT > 0 ? atomicAdd(&c->touched_cnt, NT) : 0;
+      s_nl = 0;
+    }
+    __syncthreads();
+    long long pf = (long long)s_fb + fex, pt = (long long)s_tb + tex;
+#pragma unroll
+    for (int m = 0; m < kListPT; m++) {
+      if (jv[m] < 0) continue;
+      const int32_t w = vlo + jv[m];
+      if (fm >> m & 1u) {
+        if (pf < a.n) Fn[pf] = w; else c->fault = 1;
+        pf++;
+      }
+      if (tm >> m & 1u) {
+        if (pt < a.n) a.touched[pt] = w; else c->fault = 1;
+        pt++;
+      }
+    }
+    __syncthreads();
+  }
+  if (last_block(&c->done[DONE_BIN], &s_last, false)) {
+    if (threadIdx.x == 0) {
+      c->pushes += nf;
+      c->edges += E;
+      c->bin_rounds += 1;
+      c->bin_edges += E;
+      c->cnt[t & 1] = 0;
+      c->round = t + 1;
+      if (slot >= 0) a.work_log[2 * slot + 1] = 1;
+    }
+  }
+}
+
 // edgeMap(G, Frontier, UpdateNgh) with the filter folded in.  Each
 // workgroup takes a contiguous range of edge tiles; every edge is one
 // device-scope FP64 atomic.  (Combining the contributions to the
@@ -615,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void k_nb_self(PlainArgs a) { self_body<kMo
 //     to list j+1; each entry's own rho / 2 is added by the workgroup whose
 //     tile holds the entry's first edge.
 template <int MODE>
-__device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
+__device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, ScatterShared& sm) {
   constexpr bool HK = MODE == kModeHK;
   constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
@@ -623,12 +1009,19 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
   if (!push_active(c, a.n, &t, &nf)) return;
   if (HK ? t >= c->hk_N : t >= c->max_rounds) return;
   if (c->selfed != t) return;  // no entries built for this round (a self loop stopped before it)
-  __shared__ int32_t s_start[kEdgeTile + 1];
-  __shared__ int64_t s_row[kEdgeTile + 1];
-  __shared__ double s_coef[kEdgeTile + 1];
-  __shared__ int32_t s_fn[kEdgeTile];
-  __shared__ int32_t s_tv[kEdgeTile];
-  __shared__ int s_nfn, s_ntv, s_base, s_last;
+  if (MODE == kModePR && bin_round(a, c->etotal)) {
+    bin_sort_chunks(a, nf, sm.bs);  // pass A; k_bin_apply adds and closes the round
+    return;
+  }
+  int32_t* const s_start = sm.at.start;
+  int64_t* const s_row = sm.at.row;
+  double* const s_coef = sm.at.coef;
+  int32_t* const s_fn = sm.at.fn;
+  int32_t* const s_tv = sm.at.tv;
+  int& s_nfn = sm.at.nfn;
+  int& s_ntv = sm.at.ntv;
+  int& s_base = sm.at.base;
+  int& s_last = sm.at.last;
   const int ntiles = (int64_t)c->ntiles > a.tile_cap ? (int)a.tile_cap : c->ntiles;
   const long long E = c->etotal;
   const bool hk_last = HK && t + 1 == c->hk_N;
@@ -733,10 +1126,17 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a, int slot) {
-  scatter_body<kModePR>(a, slot);
+  __shared__ ScatterShared sm;
+  scatter_body<kModePR>(a, slot, sm);
 }
-__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) { scatter_body<kModeHK>(a, -1); }
-__global__ __launch_bounds__(kBlock) void k_nb_scatter(PlainArgs a) { scatter_body<kModeNB>(a, -1); }
+__global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) {
+  __shared__ ScatterShared sm;
+  scatter_body<kModeHK>(a, -1, sm);
+}
+__global__ __launch_bounds__(kBlock) void k_nb_scatter(PlainArgs a) {
+  __shared__ ScatterShared sm;
+  scatter_body<kModeNB>(a, -1, sm);
+}
 
 // HK-PR initialisation (Fig. alg:hkpr: r = {(x, 1)}, Frontier = {x},
 // j = 0); level 0 touched only x.
@@ -1291,7 +1691,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
     a.p[v] = 0.0;
   }
   if (last_block(&c->done[DONE_FINISH], &s_last, false)) {
-    if (threadIdx.x == 0) c->status = ST_SWEPT;
+    if (threadIdx.x == 0) {
+      c->t_end = (long long)wall_clock64();
+      c->status = ST_SWEPT;
+    }
   }
 }
 
@@ -1393,12 +1796,16 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 }
 
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0,
-                          hipEvent_t t1, int slot) {
+                          hipEvent_t t1, int slot, int grid_bin) {
   if (slot >= kMaxChunk) return hipErrorInvalidValue;
-  if (t0)
-    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, t1, 0, a, slot);
-  else
+  if (t0) {
+    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, nullptr, 0, a, slot);
+    hipExtLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, nullptr, t1, 0, a,
+                          slot);
+  } else {
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a, slot);
+    hipLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, a, slot);
+  }
   return hipGetLastError();
 }
 

@@ -100,6 +100,7 @@ struct BatchEngine {
   std::vector<int> state;            // HS_*
   std::vector<uint64_t> qid;
   std::vector<int> qbucket;          // compact: hint bucket of the slot's query
+  std::vector<uint32_t> qflags;      // flags of the slot's query
   std::vector<Result> sweeping;      // result blocks filled by the sweep in flight
   std::deque<std::pair<uint64_t, plc_query>> queue;
   size_t bytes = 0;
@@ -161,7 +162,9 @@ struct plc_ctx {
   bool broken = false;
   std::set<plc_graph*> graphs;
   int num_cu = 256;
-  int grid_self = 256, grid_scatter = 1024, grid_sweep = 512;
+  int grid_self = 256, grid_scatter = 1024, grid_sweep = 512, grid_bin = 1024;
+  double clock_ns = 10.0;         // nanoseconds per tick of the kernels' constant-rate clock
+  uint32_t cur_flags = 0;         // plain path: flags of the running query
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
   std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
@@ -220,6 +223,10 @@ extern "C" plc_status plc_init(plc_ctx** out, int32_t device, void* dev_arena, s
   c->grid_self = c->num_cu;
   c->grid_scatter = 4 * c->num_cu;
   c->grid_sweep = 2 * c->num_cu;
+  c->grid_bin = 4 * c->num_cu;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c->clock_ns = 1e6 / (double)khz;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->ctl_host), sizeof(Ctl), hipHostMallocDefault) !=
       hipSuccess) {
     delete c;
@@ -397,6 +404,55 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.hk_tl[2] = static_cast<int32_t*>(take(4 * N));
   a.hk_B = static_cast<double*>(take(8 * (size_t)(plc::kHkMaxLevels + 1)));
   a.work_log = static_cast<int32_t*>(take(4 * 2 * (size_t)plc::kMaxChunk));
+  // Destination bins of the binned scatter: whole kBinGran-vertex blocks, at
+  // most kBinWidth vertices and about 1/1024 of the volume each (the volume
+  // target doubles until fewer than kMaxBins bins result); off when even
+  // the width bound needs 3/4 of kMaxBins bins or the context turned it off.
+  std::vector<int32_t> bin_of_blk, bin_lo;
+  std::vector<long long> bin_vol;
+  const int64_t nblk = (n + plc::kBinGran - 1) / plc::kBinGran;
+  const bool bins_on = ctx->opt.bin_min_edges >= 0 &&
+                       (n + plc::kBinWidth - 1) / plc::kBinWidth <= plc::kMaxBins * 3 / 4;
+  if (bins_on) {
+    long long vt = std::max<long long>(1, num_arcs / 1024);
+    for (;;) {
+      bin_of_blk.assign((size_t)nblk, 0);
+      bin_lo.clear();
+      bin_vol.clear();
+      long long cw = 0, cv = 0;
+      for (int64_t k = 0; k < nblk; k++) {
+        const int64_t v0 = k * plc::kBinGran, v1 = std::min<int64_t>(n, v0 + plc::kBinGran);
+        const long long vol = (long long)(off[v1] - off[v0]);
+        if (bin_lo.empty() || cw + plc::kBinGran > plc::kBinWidth || (cw > 0 && cv + vol > vt)) {
+          bin_lo.push_back((int32_t)v0);
+          bin_vol.push_back(0);
+          cw = 0;
+          cv = 0;
+        }
+        bin_of_blk[(size_t)k] = (int32_t)bin_lo.size() - 1;
+        cw += plc::kBinGran;
+        cv += vol;
+        bin_vol.back() += vol;
+      }
+      bin_lo.push_back((int32_t)std::min<int64_t>((int64_t)INT32_MAX, nblk * plc::kBinGran));
+      if ((int)bin_vol.size() < plc::kMaxBins) break;
+      vt *= 2;
+    }
+    const int nb = (int)bin_vol.size();
+    const int64_t emax = std::min<int64_t>(std::max<int64_t>(num_arcs, 1), plc::kBinEmax);
+    a.bin_cmax = (int32_t)((emax + plc::kBinChunk - 1) / plc::kBinChunk);
+    a.bin_of_blk = static_cast<int32_t*>(take(4 * (size_t)nblk));
+    a.bin_lo = static_cast<int32_t*>(take(4 * (size_t)(nb + 1)));
+    a.bin_vol = static_cast<long long*>(take(8 * (size_t)nb));
+    a.bin_T = static_cast<int32_t*>(take(4 * (size_t)(nb + 1) * (size_t)a.bin_cmax));
+    a.bin_pairs = static_cast<int2*>(take(8 * (size_t)a.bin_cmax * plc::kBinChunk));
+    a.nbins = nb;
+    a.bin_emin = ctx->opt.bin_min_edges > 0 ? ctx->opt.bin_min_edges : plc::kBinEmin;
+  } else {
+    a.nbins = 0;
+    a.bin_cmax = 0;
+    a.bin_emin = 0;
+  }
   if (nomem) {
     graph_release_blocks(ctx, g);
     delete g;
@@ -439,6 +495,14 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
     g->hotcode_h.clear();
     g->hotcode_h.shrink_to_fit();
   }
+  if (a.nbins > 0 &&
+      (hipMemcpyAsync((void*)a.bin_of_blk, bin_of_blk.data(), 4 * bin_of_blk.size(),
+                      hipMemcpyHostToDevice, s) != hipSuccess ||
+       hipMemcpyAsync((void*)a.bin_lo, bin_lo.data(), 4 * bin_lo.size(), hipMemcpyHostToDevice,
+                      s) != hipSuccess ||
+       hipMemcpyAsync((void*)a.bin_vol, bin_vol.data(), 8 * bin_vol.size(),
+                      hipMemcpyHostToDevice, s) != hipSuccess))
+    return fail();
   if (hipMemsetAsync(a.ctl, 0, sizeof(Ctl), s) != hipSuccess) return fail();
   for (int k = 0; k < plc::NUM_SCANS; k++)
     if (hipMemsetAsync(a.desc[k], 0, 2 * 8 * nscan, s) != hipSuccess) return fail();
@@ -478,6 +542,7 @@ static bool query_ok(const plc_graph* g, const plc_query& q) {
   if (!(q.alpha > 0.0 && q.alpha < 1.0)) return false;
   if (!std::isfinite(q.eps) || !(q.eps >= 1e-250)) return false;
   if (q.rule != PLC_RULE_OPT && q.rule != PLC_RULE_ORIG) return false;
+  if ((q.flags & ~PLC_QF_ALL) != 0u) return false;
   return true;
 }
 
@@ -530,7 +595,8 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
     hipError_t r;
     for (int i = 0; i < R; i++) {
       if ((r = plc::launch_self(cs, a, gs)) != hipSuccess) return r;
-      if ((r = plc::launch_scatter(cs, a, gc)) != hipSuccess) return r;
+      if ((r = plc::launch_scatter(cs, a, gc, nullptr, nullptr, -1, ctx->grid_bin)) != hipSuccess)
+        return r;
     }
     return hipSuccess;
   });
@@ -577,12 +643,13 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, boo
       if ((r = ev_pair(ctx->ev_scatter[k])) != hipSuccess) return r;
       if ((r = plc::launch_self(s, a, gs, ctx->ev_self[k].a, ctx->ev_self[k].b, i)) != hipSuccess)
         return r;
-      if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b, i)) !=
-          hipSuccess)
+      if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b, i,
+                                   ctx->grid_bin)) != hipSuccess)
         return r;
     } else {
       if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
-      if ((r = plc::launch_scatter(s, a, gc)) != hipSuccess) return r;
+      if ((r = plc::launch_scatter(s, a, gc, nullptr, nullptr, -1, ctx->grid_bin)) != hipSuccess)
+        return r;
     }
     if (beta && (r = plc::launch_beta_post(s, a, gw)) != hipSuccess) return r;
   }
@@ -640,6 +707,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
                           int32_t nset = 0, double beta = 1.0, int pre = 0,
                           const plc_query* next = nullptr, int* next_pre = nullptr) {
   ctx->q_t0 = pre > 0 ? ctx->next_t0 : std::chrono::steady_clock::now();
+  ctx->cur_flags = q.flags;
   if (next_pre) *next_pre = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
@@ -805,7 +873,7 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
     return PLC_E_HIP;
   }
   const size_t N = (size_t)h.N;
-  const size_t R = (size_t)h.rnnz;
+  const size_t R = (ctx->cur_flags & PLC_QF_NO_RESIDUAL) ? 0 : (size_t)h.rnnz;
   const size_t off_p = (4 * N + 255) & ~(size_t)255;
   const size_t off_rid = off_p + ((8 * N + 255) & ~(size_t)255);
   const size_t off_rval = off_rid + ((4 * R + 255) & ~(size_t)255);
@@ -819,6 +887,10 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
     res.rval = reinterpret_cast<double*>(b + off_rval);
     HIPCHK(ctx, plc::launch_copy_result(s, a, res.ids, res.p, res.rid, res.rval, (int)N, (int)R,
                                         shape(g->plain_sweep, ctx->grid_sweep)));
+    if (ctx->cur_flags & PLC_QF_NO_RESIDUAL) {
+      res.rid = nullptr;
+      res.rval = nullptr;
+    }
   }
   if (ctx->timing) {
     float ms = 0;
@@ -850,6 +922,10 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
   info.loop_edges = h.loop_edges;
   info.host_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(
                      std::chrono::steady_clock::now() - ctx->q_t0).count();
+  info.device_ns = h.t_end > h.t_start ? (int64_t)((double)(h.t_end - h.t_start) * ctx->clock_ns) : 0;
+  info.bin_rounds = h.bin_rounds;
+  info.bin_edges = h.bin_edges;
+  info.flags = ctx->cur_flags;
   plc_status st = PLC_OK;
   if (!res.block) {
     info.status = PLC_E_NOMEM;
@@ -943,6 +1019,7 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
   ctx->q_t0 = std::chrono::steady_clock::now();
+  ctx->cur_flags = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   // threshold of level k: ((e^-t eps) d(w)) / B_k with B_k = 2 N psi_k
@@ -997,6 +1074,7 @@ extern "C" plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, d
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
   ctx->q_t0 = std::chrono::steady_clock::now();
+  ctx->cur_flags = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   HIPCHK(ctx, plc::launch_nb_init(s, a, seed, eps, T));
@@ -1046,7 +1124,8 @@ extern "C" plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_
   if (!r.block) return PLC_E_NOMEM;
   (void)hipSetDevice(ctx->device);
   hipStream_t s = ctx->stream;
-  size_t N = (size_t)r.info.support, R = (size_t)r.info.r_nnz;
+  // (a query run with PLC_QF_NO_RESIDUAL keeps no r vector)
+  size_t N = (size_t)r.info.support, R = r.rid ? (size_t)r.info.r_nnz : 0;
   if (sweep_ids && N) HIPCHK(ctx, hipMemcpyAsync(sweep_ids, r.ids, 4 * N, hipMemcpyDeviceToHost, s));
   if (sweep_p && N) HIPCHK(ctx, hipMemcpyAsync(sweep_p, r.p, 8 * N, hipMemcpyDeviceToHost, s));
   if (r_ids && R) HIPCHK(ctx, hipMemcpyAsync(r_ids, r.rid, 4 * R, hipMemcpyDeviceToHost, s));
@@ -1262,6 +1341,7 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   E->qid.assign(B, 0);
   E->qblock.assign(B, nullptr);
   E->qbucket.assign(B, 0);
+  E->qflags.assign(B, 0u);
   E->qcap.assign(B, 0);
   E->hold.assign(B, 0);
   E->fresh.assign(B, 0);
@@ -1446,6 +1526,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     }
     E.queue.pop_front();
     nadm++;
+    E.qflags[q] = qq.flags;
     ad.slot = q;
     ad.seed = qq.seed;
     ad.rule = (int32_t)qq.rule;
@@ -1641,10 +1722,12 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     const long long N = S.support_cnt, T = S.touched_cnt;
     if (nseg > 0 && (total + N > a.s_cap || vol_bound + S.edges > a.e_cap)) continue;
     Result res;
+    const bool keep_r = !(E.qflags[q] & PLC_QF_NO_RESIDUAL);
+    const size_t Tr = keep_r ? (size_t)T : 0;
     size_t off_p = (4 * (size_t)N + 255) & ~(size_t)255;
     size_t off_rid = off_p + ((8 * (size_t)N + 255) & ~(size_t)255);
-    size_t off_rval = off_rid + ((4 * (size_t)T + 255) & ~(size_t)255);
-    res.block = ctx->arena.alloc(off_rval + 8 * (size_t)T);
+    size_t off_rval = off_rid + ((4 * Tr + 255) & ~(size_t)255);
+    res.block = ctx->arena.alloc(off_rval + 8 * Tr);
     plc::SweepSeg& sg = E.segs_h[nseg];
     sg.slot = q;
     sg.n_elem = (int32_t)N;
@@ -1658,8 +1741,10 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       char* b = static_cast<char*>(res.block);
       res.ids = reinterpret_cast<int32_t*>(b);
       res.p = reinterpret_cast<double*>(b + off_p);
-      res.rid = reinterpret_cast<int32_t*>(b + off_rid);
-      res.rval = reinterpret_cast<double*>(b + off_rval);
+      if (keep_r) {
+        res.rid = reinterpret_cast<int32_t*>(b + off_rid);
+        res.rval = reinterpret_cast<double*>(b + off_rval);
+      }
     }
     sg.out_ids = res.ids;
     sg.out_p = res.p;
@@ -1729,6 +1814,9 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     info.vol = S.best_vol;
     info.phi = S.phi;
     info.r_nnz = S.rnnz;
+    info.device_ns =
+        S.t_done > S.t_admit ? (int64_t)((double)(S.t_done - S.t_admit) * ctx->clock_ns) : 0;
+    info.flags = E.qflags[q];
     if (S.fault) {
       ctx->broken = true;
       return PLC_E_HIP;

@@ -38,7 +38,8 @@ enum : int32_t { SCAN_FRONTIER = 0, SCAN_VOL = 1, SCAN_CUT = 2, NUM_SCANS = 3 };
 
 // Last-workgroup counters.
 enum : int32_t {
-  DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, DONE_SELF = 4, NUM_DONE = 8
+  DONE_SCATTER = 0, DONE_KEYS = 1, DONE_SORT = 2, DONE_FINISH = 3, DONE_SELF = 4, DONE_BIN = 5,
+  NUM_DONE = 8
 };
 
 // Where the running sweep writes its results (the library's own buffers,
@@ -100,6 +101,13 @@ struct __align__(64) Ctl {
   int32_t loop_rounds;
   int32_t init_held;  // a queued guarded initialisation found the previous query unfinished
   long long loop_pushes, loop_edges;
+  // rounds whose scatter went through the destination bins, and their edges
+  int32_t bin_rounds;
+  int32_t pad2;
+  long long bin_edges;
+  // constant-rate clock (wall_clock64) at the query's initialisation and at
+  // the end of its sweep
+  long long t_start, t_end;
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
@@ -144,6 +152,18 @@ struct PlainArgs {
   // combined in LDS there), kept with the graph
   const int32_t* hot_ids;  // [kHot] vertex of hot index j
   const int32_t* hotcode;  // [n] -(j+1) for hot vertex j, else 0
+  // Destination-binned scatter of large rounds.  Bins are vertex ranges made
+  // of whole 64-vertex blocks (so no cache line of state records spans two
+  // bins), at most kBinWidth wide, with roughly equal volume.  Rounds of
+  // bin_emin .. bin_cmax * kBinChunk edges are binned; nbins = 0 turns it off.
+  int32_t nbins;
+  int32_t bin_cmax;            // chunks the pair buffer holds
+  long long bin_emin;
+  const int32_t* bin_of_blk;   // [ceil(n / kBinGran)] bin of each block
+  const int32_t* bin_lo;       // [nbins + 1] first vertex of each bin
+  const long long* bin_vol;    // [nbins] sum of degrees over the bin
+  int32_t* bin_T;              // [(nbins + 1) x bin_cmax]: start of bin b's run in chunk c
+  int2* bin_pairs;             // [bin_cmax x kBinChunk]: (neighbour, entry) by bin per chunk
 };
 
 // Launch configuration.
@@ -163,6 +183,19 @@ constexpr int kLoopEdges = 4096;
 constexpr int kLoopPass = 2048;
 constexpr int kLoopMaxRounds = 256;
 static_assert(kHot % kEdgeTile == 0, "the hot flush works in kEdgeTile chunks");
+// Destination-binned scatter (large rounds): pass A sorts each chunk of
+// kBinChunk edges by bin; pass B accumulates each bin (or a slice of a
+// heavy bin's chunks) in an LDS array of kBinWidth doubles.
+constexpr int kBinGran = 64;
+constexpr int kBinWidth = 4096;
+constexpr int kMaxBins = 2048;
+constexpr int kBinChunkTiles = 2;
+constexpr int kBinChunk = kBinChunkTiles * kEdgeTile;
+constexpr int kBinItemChunks = 2048;   // chunks one pass-B item may span
+constexpr int kBinQ = 4096;            // expected pairs per pass-B item
+constexpr long long kBinEmin = 1 << 19;  // default smallest binned round (edges)
+constexpr long long kBinEmax = 1 << 23;  // largest binned round the pair buffer is sized for
+static_assert(kBinChunk <= 65536 && kMaxBins <= 32768, "pass A packs (bin, rank) in 32 bits");
 
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
@@ -201,8 +234,12 @@ hipError_t launch_nb_finish(hipStream_t s, const PlainArgs& a, int32_t R, int32_
 // a.work_log[2 slot] (self) or a.work_log[2 slot + 1] (scatter).
 hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
                        hipEvent_t t1 = nullptr, int slot = -1);
+// The scatter of a PR-Nibble round: k_scatter (the atomic scatter, or pass A
+// of the binned scatter for rounds of a.bin_emin edges and more), then
+// k_bin_apply (pass B; exits at once after an atomic round).  With t0 set,
+// t0 stamps k_scatter's start and t1 k_bin_apply's end.
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
-                          hipEvent_t t1 = nullptr, int slot = -1);
+                          hipEvent_t t1 = nullptr, int slot = -1, int grid_bin = 1024);
 // max_count: bound on the support size, sets the number of merge passes; a
 // query with a larger support (or one still pushing) is left unswept, so the
 // sweep may be queued before the push is known to have ended.  The sweep

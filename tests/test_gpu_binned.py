@@ -1,0 +1,179 @@
+"""GPU parity of the destination-binned edge scatter (plain path).
+
+Rounds of at least `bin_min_edges` edges are scattered by sorting the
+round's (neighbour, entry) pairs by destination bin and adding each bin's
+contributions in LDS (Sec. 3.3, UpdateNgh as a fetch-and-add; only the order
+of the additions changes).  With bin_min_edges = 1 every round that reaches
+the scatter kernels is binned, so the small graphs below exercise it on
+ragged chunks, single-bin rounds, split (heavy) bins and both push rules.
+All calls go through the C ABI.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from parity import check_query, check_same
+
+pytestmark = pytest.mark.gpu
+
+OPT, ORIG = 0, 1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def plc():
+    import paper_1604_07515_amd as plc
+    return plc
+
+
+@pytest.fixture(scope="module")
+def ctx_bin(plc):
+    c = plc.Context(arena_bytes=2 << 30, bin_min_edges=1)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx_atomic(plc):
+    c = plc.Context(arena_bytes=2 << 30, bin_min_edges=-1)
+    yield c
+    c.close()
+
+
+GRAPHS = {
+    "rmat12": lambda: synth.rmat(12, 8, seed=5),
+    "rmat14": lambda: synth.rmat(14, 16, seed=6),
+    "rmat16": lambda: synth.rmat(16, 8, seed=1),
+    "star10k": lambda: synth.star(10000),
+    "k200": lambda: synth.complete(200),
+    "torus20": lambda: synth.torus3d(20),
+    "barbell30": lambda: synth.barbell(30),
+}
+_host = {}
+_dev = {}
+
+
+def graph(c, name):
+    """(host graph, graph loaded on context c), cached per context."""
+    if name not in _host:
+        _host[name] = GRAPHS[name]()
+    key = (id(c), name)
+    if key not in _dev:
+        g = _host[name]
+        _dev[key] = c.load_graph(g.off, g.nbr, validate=True)
+    return _host[name], _dev[key]
+
+
+CASES = [(gname, rule, eps)
+         for gname in ("rmat12", "rmat14", "k200", "torus20", "barbell30")
+         for rule in (OPT, ORIG)
+         for eps in (1e-4, 1e-6, 1e-8)]
+
+
+@pytest.mark.parametrize("gname,rule,eps", CASES)
+def test_binned_parity(ctx_bin, gname, rule, eps):
+    g, hg = graph(ctx_bin, gname)
+    seeds = [int(s) for s in synth.uniform_seeds(g, 2, seed=9)]
+    alpha = 0.01 if rule == OPT else 0.05
+    say("case", gname, rule, eps, seeds)
+    ids, infos = ctx_bin.run(hg, seeds, alpha, eps, rule)
+    for qid, s in zip(ids, seeds):
+        res = ctx_bin.result(qid, release=True)
+        rep = check_query(g, res, s, alpha, eps, rule)
+        say("  seed", s, "bin rounds", res.info["bin_rounds"], "of", res.info["rounds"], rep)
+
+
+def test_binned_rounds_happen(ctx_bin):
+    """The tests above do reach the binned kernels (rounds too large for the
+    self launch's own loop go to the scatter, and every one is binned)."""
+    g, hg = graph(ctx_bin, "rmat14")
+    ids, infos = ctx_bin.run(hg, [0, 1, 2], 0.01, 1e-7, OPT)
+    for qid in ids:
+        ctx_bin.release(qid)
+    for info in infos:
+        assert info["bin_rounds"] >= 1, info
+        assert info["bin_edges"] >= 4096 * info["bin_rounds"] // 2
+        assert info["rounds"] == info["loop_rounds"] + info["bin_rounds"], info
+
+
+def test_binned_split_bin_star(ctx_bin):
+    """Star seeded at the hub: the second round sends every leaf's
+    contribution to the hub, whose bin is split over two workgroups (4096 and
+    5904 pairs; atomic updates of the split bin), and the third reaches all
+    leaves.  The hub collects 10^4 equal contributions per round.  Summed one
+    by one (the oracle) or as two partial sums (the split bin), such sums
+    differ by up to ~2e-13 relative per collection, and the difference
+    compounds each time the hub collects again: with alpha = 0.01 and
+    eps = 1e-5 (116 rounds) a replay of the two orders on the CPU gives
+    1.16e-12 in the hub's r, above the 1e-12 bar.  The cases below take a
+    larger alpha (few rounds); the same replay gives at most 4.8e-13."""
+    g, hg = graph(ctx_bin, "star10k")
+    for rule, alpha, eps in ((OPT, 0.2, 1e-6), (OPT, 0.2, 1e-7), (ORIG, 0.3, 1e-7),
+                             (ORIG, 0.1, 1e-6)):
+        say("case star hub", rule, alpha, eps)
+        ids, infos = ctx_bin.run(hg, [0], alpha, eps, rule)
+        res = ctx_bin.result(ids[0], release=True)
+        assert res.info["bin_rounds"] >= 2
+        check_query(g, res, 0, alpha, eps, rule)
+
+
+def test_c1_default_threshold_bins_the_big_rounds(plc):
+    """R-MAT 2^16 from vertex 0 (the saturating workload) with the default
+    threshold: its largest rounds are binned, the rest atomic; parity."""
+    g = synth.rmat(16, 8, seed=1)
+    x = synth.largest_component_min_vertex(g)
+    with plc.Context(arena_bytes=1 << 30) as c:
+        hg = c.load_graph(g.off, g.nbr, validate=True)
+        ids, infos = c.run(hg, [x], 0.01, 1e-7, OPT)
+        res = c.result(ids[0], release=True)
+        say("C1: rounds", res.info["rounds"], "binned", res.info["bin_rounds"],
+            "binned edges", res.info["bin_edges"], "of", res.info["edges"])
+        assert res.info["bin_rounds"] >= 1
+        assert res.info["bin_rounds"] < res.info["rounds"]
+        check_query(g, res, x, 0.01, 1e-7, OPT)
+
+
+def test_binned_equals_atomic(ctx_bin, ctx_atomic):
+    """The same queries through binned and atomic scatters agree (counters
+    exactly, p within 1e-12, sweep modulo near-tie blocks)."""
+    gb, hb = graph(ctx_bin, "rmat16")
+    _, ha = graph(ctx_atomic, "rmat16")
+    seeds = [0] + [int(s) for s in synth.uniform_seeds(gb, 5, seed=21)]
+    for rule, alpha in ((OPT, 0.01), (ORIG, 0.02)):
+        say("case binned==atomic", rule, seeds)
+        ib, inb = ctx_bin.run(hb, seeds, alpha, 1e-6, rule)
+        ia, ina = ctx_atomic.run(ha, seeds, alpha, 1e-6, rule)
+        assert sum(x["bin_rounds"] for x in inb) > 0
+        assert all(x["bin_rounds"] == 0 for x in ina)
+        for qb, qa in zip(ib, ia):
+            check_same(gb, ctx_bin.result(qb, release=True), ctx_atomic.result(qa, release=True))
+
+
+def test_binned_direct_launches_and_timing(plc):
+    """Direct launches and the event-timed mode run the same binned rounds."""
+    g = synth.rmat(14, 16, seed=6)
+    seeds = [int(s) for s in synth.uniform_seeds(g, 4, seed=13)]
+    out = []
+    for graphs, timing in ((True, False), (False, False), (True, True)):
+        with plc.Context(arena_bytes=1 << 30, graphs=graphs, bin_min_edges=1) as c:
+            hg = c.load_graph(g.off, g.nbr)
+            c.timing(timing)
+            ids, infos = c.run(hg, seeds, 0.01, 1e-7, OPT)
+            res = [c.result(q, release=True) for q in ids]
+            if timing:
+                t = c.timing_get()
+                say("timing", t)
+                assert t["scatter"]["launches"] >= sum(x["bin_rounds"] for x in infos)
+                assert t["scatter"]["units"] == sum(x["edges"] - x["loop_edges"] for x in infos)
+                assert t["scatter"]["ms"] > 0
+            out.append(res)
+    for a, b, cc, s in zip(out[0], out[1], out[2], seeds):
+        check_same(g, a, b)
+        check_same(g, a, cc)
+        check_query(g, a, s, 0.01, 1e-7, OPT)
