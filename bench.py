@@ -1,27 +1,36 @@
 #!/usr/bin/env python3
 """Benchmark of PR-Nibble + sweep cut on one MI355X.
 
-Default run (about two minutes): three workloads on synthetic undirected
-R-MAT graphs, (a,b,c,d) = (0.57,0.19,0.19,0.05), edge factor 16 (average
-degree ~31 after symmetrising and removing self-loops and duplicates),
-int32 ids, int64 offsets, FP64 p and r, optimized push rule:
+Default run (a few minutes): synthetic undirected R-MAT graphs,
+(a,b,c,d) = (0.57,0.19,0.19,0.05), int32 ids, int64 offsets, FP64 p and r,
+optimized push rule:
 
-* plain22 (the line's `value`): 2^22 vertices, 16 seeds drawn uniformly
-  from vertices of degree >= 1, run one after another, alpha = 0.01,
-  eps = 1e-7.  A step is those 16 queries, each a full PR-Nibble push
-  followed by the sweep cut, graph resident in HBM.
-* batched22: the same graph, 256 seeds in one batch (256 slots), eps
+* plain22 (the line's `value`): 2^22 vertices, edge factor 16, 16 seeds
+  drawn uniformly from vertices of degree >= 1, run one after another,
+  alpha = 0.01, eps = 1e-7.  A step is those 16 queries, each a full
+  PR-Nibble push followed by the sweep cut, graph resident in HBM, and the
+  copy of every query's p and cluster (support in sweep order with p on it)
+  to the host.  The same steps without the copies are reported beside it.
+* c1_rmat16: 2^16 vertices, edge factor 8, seed = the smallest vertex of the
+  largest component (vertex 0), alpha 0.01, eps 1e-7: the saturating query
+  (the diffusion covers the whole component over ~118 rounds).
+* batched22: the 2^22 graph, 256 seeds in one batch (256 slots), eps
   log-uniform in [1e-7, 1e-5], alpha in {0.01, 0.05}; a step is the batch.
   Run twice: with dense per-slot state and with compact per-query tables.
 * serve24: 2^24 vertices, seeds drawn proportionally to degree, eps
-  log-uniform in [1e-7, 1e-4], alpha = 0.01, continuous batching over 64
-  slots (compact tables by default: admission by memory): the saturation
-  rate (all queries queued at once) and Poisson arrivals at 50% and 90% of
-  it, with p50/p99 latency.
+  log-uniform in [1e-7, 1e-4], alpha = 0.01, continuous batching over 256
+  slots (compact tables: admission by memory): the saturation rate (all
+  queries queued at once), then Poisson arrivals at 0.25, 0.5, 0.75 and 0.9
+  of it, each with a 1 s warm-up and 10^4 measured queries, p50/p99 latency
+  including the copy of each result to the host.
+* large26: 2^26 vertices, 1024 seeds (32 of them the top-degree hubs), eps
+  log-uniform in [1e-8, 1e-6], compact tables; one warm-up pass, one timed
+  pass with no per-kernel events.
 
 Prints one JSON line.  The roofline object describes the edge-scatter
-kernel, timed with HIP events on the library's stream over the timed steps.
-The CPU baseline is the oracle timed on the host on a bounded sample.
+launches, timed with HIP events on the library's stream in an instrumented
+replay of the timed steps.  The CPU baseline is the oracle timed on the host
+on a bounded sample of the headline queries.
 """
 from __future__ import annotations
 
@@ -54,6 +63,10 @@ def pct(xs, q):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scatter_hbm_traffic_rmat22.md")
+# The plain path's edge scatter: the scatter launch (one FP64 atomic per edge,
+# or pass A of the binned scatter on large rounds) and k_bin_apply (pass B),
+# timed together per round.
+PLAIN_SCATTER = "k_scatter + k_bin_apply"
 
 
 def measured_traffic(kernel):
@@ -96,14 +109,14 @@ def roofline(tm, kernel, counted=True):
     }
 
 
-def timed_steps(ctx, step, steps, warmup):
+def timed_steps(ctx, step, steps, warmup, instrument=True):
     """Warm-up, then the timed steps with no per-kernel events (an event node
     between dependent kernels costs about as much as a short kernel), then
     the same steps again with HIP events around every kernel on the
     library's stream: the kernel durations of the roofline come from that
     instrumented replay."""
     import torch
-    acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0}
+    acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0, "bin_rounds": 0}
     for i in range(warmup):
         step([], dict(acc))
         log("  warmup step %d done" % i)
@@ -115,6 +128,8 @@ def timed_steps(ctx, step, steps, warmup):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     log("  timed steps done")
+    if not instrument:
+        return elapsed, lat, acc, None
     ctx.timing(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -130,45 +145,108 @@ def timed_steps(ctx, step, steps, warmup):
     return elapsed, lat, acc, tm
 
 
-def account(acc, infos, ids, ctx):
+def account(acc, infos, ids, ctx, fetch=False):
+    """Sum the query counters; fetch copies each result's p and cluster to
+    the host before the release."""
     for qid, info in zip(ids, infos):
         acc["edges"] += info["edges"]
         acc["pushes"] += info["pushes"]
         acc["rounds"] += info["rounds"]
         acc["support"] += info["support"]
         acc["queries"] += 1
-        ctx.release(qid)
+        acc["bin_rounds"] = acc.get("bin_rounds", 0) + info["bin_rounds"]
+        if fetch:
+            ctx.result(qid, release=True)
+        else:
+            ctx.release(qid)
 
 
 def bench_plain(plc, synth, g, steps, warmup):
-    import numpy as np
     seeds = synth.uniform_seeds(g, 16, seed=2)
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
     tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
     log("  plain launch shapes: self %d, scatter %d, sweep %d workgroups (%d tried)" % (
         tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"], tune["candidates"]))
+    sl = [int(s) for s in seeds]
 
     def step(lat, acc):
         # the 16 queries one after another in one call (each synchronous in
-        # the library); a query's latency is the library's own wall time from
-        # its start to its result
-        ids, infos = ctx.run(hg, [int(s) for s in seeds], 0.01, 1e-7)
+        # the library), then every query's p and cluster copied to the host;
+        # a query's latency is the library's own wall time from its start to
+        # its result on the device
+        ids, infos = ctx.run(hg, sl, 0.01, 1e-7, flags=plc.PLC_QF_NO_RESIDUAL)
+        lat.extend(i["host_ns"] * 1e-9 for i in infos)
+        account(acc, infos, ids, ctx, fetch=True)
+
+    def step_resident(lat, acc):
+        ids, infos = ctx.run(hg, sl, 0.01, 1e-7)
         lat.extend(i["host_ns"] * 1e-9 for i in infos)
         account(acc, infos, ids, ctx)
 
     elapsed, lat, acc, tm = timed_steps(ctx, step, steps, warmup)
+    el2, lat2, acc2, _ = timed_steps(ctx, step_resident, steps, 1, instrument=False)
+    dev = []
+    ids, infos = ctx.run(hg, sl, 0.01, 1e-7)
+    dev = [i["device_ns"] * 1e-6 for i in infos]
+    for q in ids:
+        ctx.release(q)
     ctx.close()
     nq = acc["queries"]
     return {
         "seeds": seeds, "elapsed": elapsed, "edges_per_s": acc["edges"] / elapsed,
         "queries_per_s": nq / elapsed, "ms_per_step": elapsed * 1e3 / steps,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
-                       "what": "per query: the library's wall time from its start to its result"},
-        "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
-        "kernels": tm, "roofline": roofline(tm, "k_scatter"),
+                       "what": "per query: the library's wall time from its start to its "
+                               "result on the device (a query queued behind the previous "
+                               "one of the same call starts when that one is known done)"},
+        "device_ms": {"p50": pct(dev, 50), "p99": pct(dev, 99),
+                      "what": "per query: device clock from its initialisation kernel to the "
+                              "end of its sweep"},
+        "result_copy": "p and the cluster of every query copied to the host inside the "
+                       "timed steps (PLC_QF_NO_RESIDUAL: r is not kept)",
+        "without_result_copy": {"edges_per_s": acc2["edges"] / el2,
+                                "queries_per_s": acc2["queries"] / el2,
+                                "ms_per_step": el2 * 1e3 / steps},
+        "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support",
+                                                 "bin_rounds")},
+        "kernels": tm, "roofline": roofline(tm, PLAIN_SCATTER),
         "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep")},
     }
+
+
+def bench_c1(plc, synth, reps=5):
+    """The saturating plain query: R-MAT 2^16 (edge factor 8) from the smallest
+    vertex of the largest component, alpha 0.01, eps 1e-7."""
+    import torch
+    g = synth.rmat(16, 8, seed=1)
+    x = synth.largest_component_min_vertex(g)
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (256 << 20))
+    hg = ctx.load_graph(g.off, g.nbr)
+    for _ in range(2):
+        ids, _ = ctx.run(hg, [x], 0.01, 1e-7)
+        ctx.release(ids[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc = {"edges": 0, "pushes": 0, "rounds": 0, "support": 0, "queries": 0, "bin_rounds": 0}
+    lat = []
+    for _ in range(reps):
+        ids, infos = ctx.run(hg, [x], 0.01, 1e-7, flags=plc.PLC_QF_NO_RESIDUAL)
+        lat.append(infos[0]["host_ns"] * 1e-9)
+        account(acc, infos, ids, ctx, fetch=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    last = infos[0]
+    ctx.close()
+    return {"workload": "rmat16_ef8_plain_seed%d" % x, "n": g.n, "arcs": g.arcs, "seed": x,
+            "alpha": 0.01, "eps": 1e-7, "queries": reps,
+            "seconds_per_query": el / reps, "queries_per_s": reps / el,
+            "edges_per_s": acc["edges"] / el,
+            "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
+            "per_query": {"edges": last["edges"], "pushes": last["pushes"],
+                          "rounds": last["rounds"], "support": last["support"],
+                          "bin_rounds": last["bin_rounds"], "bin_edges": last["bin_edges"],
+                          "kstar": last["kstar"], "phi": last["phi"]}}
 
 
 def bench_batched(plc, synth, g, steps, warmup, slots=256, compact=False):
@@ -207,15 +285,17 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256, compact=False):
     }
 
 
-def bench_serving(plc, synth, scale, nq, slots=64, compact=False):
+def bench_serving(plc, synth, scale, nq, slots=64, compact=False, measured=10000,
+                  warmup_s=1.0, fracs=(0.25, 0.5, 0.75, 0.9)):
     import numpy as np
     from paper_1604_07515_amd import serve
     t0 = time.time()
     g = synth.rmat(scale, 16, seed=1)
     log("serving graph 2^%d: n=%d arcs=%d (%.1fs)" % (scale, g.n, g.arcs, time.time() - t0))
     rng = np.random.default_rng(2)
-    seeds = synth.degree_weighted_seeds(g, nq, rng)
-    eps = 10.0 ** rng.uniform(-7, -4, nq)
+    pool = max(nq, 4 * measured)
+    seeds = synth.degree_weighted_seeds(g, pool, rng)
+    eps = 10.0 ** rng.uniform(-7, -4, pool)
     tables = (8 << 30) if compact else 0
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
                       + plc.batch_arena_bytes(g.n, g.arcs, slots, compact=compact,
@@ -224,24 +304,36 @@ def bench_serving(plc, synth, scale, nq, slots=64, compact=False):
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
     ctx.autotune(hg, seeds[:128], 0.01, eps[:128], plc.PLC_TUNE_BATCH)
-    serve.saturation(ctx, hg, seeds[:256], 0.01, eps[:256])  # warm-up
-    sat = serve.saturation(ctx, hg, seeds, 0.01, eps)
+    flags = plc.PLC_QF_NO_RESIDUAL
+    serve.serve(ctx, hg, seeds[:256], 0.01, eps[:256], np.zeros(256), fetch=True,
+                flags=flags)  # warm-up
+    sat = serve.serve(ctx, hg, seeds[:nq], 0.01, eps[:nq], np.zeros(nq), fetch=True, flags=flags)
     out = {"workload": "rmat%d_ef16_serving_poisson" % scale, "n": g.n, "arcs": g.arcs,
-           "state": "compact tables" if compact else "dense slots", "slots": got, "queries_per_run": nq, "alpha": 0.01, "eps": [1e-7, 1e-4],
-           "seeds": "proportional to degree",
-           "saturation": {"queries_per_s": sat.queries_per_s,
+           "state": "compact tables" if compact else "dense slots", "slots": got,
+           "alpha": 0.01, "eps": [1e-7, 1e-4], "seeds": "proportional to degree",
+           "result_copy": "each result's p and cluster copied to the host before it counts "
+                          "as done (PLC_QF_NO_RESIDUAL)",
+           "saturation": {"queries": nq, "queries_per_s": sat.queries_per_s,
                           "edges_per_s": sat.edges / sat.wall_s,
                           "p50_ms": sat.percentile_ms(50), "p99_ms": sat.percentile_ms(99)},
            "poisson": []}
-    for frac in (0.5, 0.9):
+    log("  saturation %.0f qps" % sat.queries_per_s)
+    off = nq
+    for frac in fracs:
         qps = frac * sat.queries_per_s
-        arr = serve.poisson_arrivals(nq, qps, np.random.default_rng(3))
-        rep = serve.serve(ctx, hg, seeds, 0.01, eps, arr)
-        out["poisson"].append({"offered_qps": qps, "served_qps": rep.queries_per_s,
+        k = int(qps * warmup_s) + measured
+        idx = np.arange(off, off + k) % pool
+        off += k
+        arr = serve.poisson_arrivals(k, qps, np.random.default_rng(3))
+        rep = serve.serve(ctx, hg, seeds[idx], 0.01, eps[idx], arr, warmup_s=warmup_s, fetch=True,
+                          flags=flags)
+        out["poisson"].append({"load": frac, "offered_qps": qps, "served_qps": rep.queries_per_s,
+                               "measured_queries": int(len(rep.latency_s)),
+                               "warmup_queries": rep.warmup_queries, "warmup_s": warmup_s,
                                "p50_ms": rep.percentile_ms(50), "p99_ms": rep.percentile_ms(99),
                                "max_in_flight": rep.max_in_flight})
-        log("  poisson %.0f qps: p50 %.2f ms p99 %.2f ms" % (qps, rep.percentile_ms(50),
-                                                            rep.percentile_ms(99)))
+        log("  poisson %.2f x saturation (%.0f qps): p50 %.2f ms p99 %.2f ms, %d measured" % (
+            frac, qps, rep.percentile_ms(50), rep.percentile_ms(99), len(rep.latency_s)))
     ctx.close()
     return out
 
@@ -265,31 +357,37 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
     hg = ctx.load_graph(g.off, g.nbr)
     got = ctx.batch_reserve(hg, slots)
     import torch
-    torch.cuda.synchronize()
+
+    def one_pass(tag):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ids = ctx.submit(hg, seeds, 0.01, eps)
+        done, acc, last_log = 0, {"edges": 0, "support": 0, "rounds": 0, "nomem": 0}, t1
+        left = len(ids)
+        while left > 0:
+            fin = []
+            left = ctx.progress(hg, fin)
+            for qid in fin:
+                info = ctx.result_info(qid)
+                if info["status"] == plc.PLC_E_NOMEM:
+                    acc["nomem"] += 1
+                acc["edges"] += info["edges"]
+                acc["support"] = max(acc["support"], info["support"])
+                acc["rounds"] = max(acc["rounds"], info["rounds"])
+                ctx.release(qid)
+                done += 1
+            if time.perf_counter() - last_log > 10:
+                last_log = time.perf_counter()
+                log("  large %s: %d of %d done (%.0fs)" % (tag, done, nq, last_log - t1))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        log("  large %s pass: %.2f s" % (tag, el))
+        return el, acc
+
+    one_pass("warm-up")
+    elapsed, acc = one_pass("timed")
     ctx.timing(True)
-    t1 = time.perf_counter()
-    ids = ctx.submit(hg, seeds, 0.01, eps)
-    done, acc, last_log, peak = [], {"edges": 0, "support": 0, "rounds": 0, "nomem": 0}, t1, 0
-    left = len(ids)
-    while left > 0:
-        fin = []
-        left = ctx.progress(hg, fin)
-        peak = max(peak, left)
-        for qid in fin:
-            info = ctx.result_info(qid)
-            if info["status"] == plc.PLC_E_NOMEM:
-                acc["nomem"] += 1
-            acc["edges"] += info["edges"]
-            acc["support"] = max(acc["support"], info["support"])
-            acc["rounds"] = max(acc["rounds"], info["rounds"])
-            ctx.release(qid)
-            done.append(qid)
-        if time.perf_counter() - last_log > 10:
-            last_log = time.perf_counter()
-            log("  large: %d of %d done, %.3g edges so far (%.0fs)" % (
-                len(done), nq, acc["edges"], last_log - t1))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t1
+    el_i, _ = one_pass("instrumented")
     tm = ctx.timing_get()
     ctx.timing(False)
     ctx.close()
@@ -299,6 +397,8 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
             "elapsed_s": elapsed, "edges_per_s": acc["edges"] / elapsed,
             "queries_per_s": nq / elapsed, "max_support": acc["support"],
             "max_rounds": acc["rounds"], "kernels": tm,
+            "what": "one warm-up pass, then the timed pass (no per-kernel events), then an "
+                    "instrumented pass for the kernel durations (%.2f s)" % el_i,
             "roofline": roofline(tm, "k_b_scatter<CompactState>", counted=False)}
 
 
@@ -530,9 +630,9 @@ def bench_randlocal(plc, synth, n=10_000_000, nq=8):
     return out
 
 
-def cpu_baseline(oracle, g, work, budget):
-    """The oracle, single-threaded, on the workload's queries in order (the
-    list repeated until `budget` seconds of work)."""
+def cpu_baseline(oracle, g, work, budget, what):
+    """The oracle, single-threaded, on the given queries in order (the list
+    repeated until `budget` seconds of work)."""
     c0 = time.perf_counter()
     done = e_sum = 0
     while work and time.perf_counter() - c0 <= budget:
@@ -546,9 +646,8 @@ def cpu_baseline(oracle, g, work, budget):
     ct = time.perf_counter() - c0
     return {"value": e_sum / ct, "unit": "pushed edges/s", "cores": 1, "kind": "oracle",
             "queries_per_s": done / ct,
-            "sample": "%d queries (the 16 plain seeds, then the 256 batched queries, in "
-                      "order, repeated), single-threaded oracle push + sweep on the same "
-                      "R-MAT 2^22 graph, %.1f s" % (done, ct)}
+            "sample": "%d queries: %s; single-threaded oracle push + sweep on the same "
+                      "R-MAT 2^22 graph, %.1f s" % (done, what, ct)}
 
 
 def cpu_multicore_baseline(g, work, budget):
@@ -570,8 +669,8 @@ def cpu_multicore_baseline(g, work, budget):
         s.close()
     return {"value": e_sum / ct, "unit": "pushed edges/s", "cores": cpu_multicore.threads(),
             "kind": "openmp", "queries_per_s": done / ct,
-            "sample": "%d queries (same list and order as cpu_baseline), OpenMP push with "
-                      "atomic adds + parallel sweep, %.1f s" % (done, ct)}
+            "sample": "%d queries (the headline's 16 plain queries in order, repeated), OpenMP "
+                      "push with atomic adds + parallel sweep, %.1f s" % (done, ct)}
 
 
 def main():
@@ -579,11 +678,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--only", choices=["plain", "batched", "serving", "large", "grid3d",
+    ap.add_argument("--only", choices=["plain", "c1", "batched", "serving", "large", "grid3d",
                                        "randlocal"],
                     default=None,
-                    help="run one workload only (the others are reported as skipped); "
-                         "'large' (R-MAT 2^26, 1024 seeds) runs only when asked for")
+                    help="run one workload only (the others are reported as skipped)")
+    ap.add_argument("--skip", action="append", default=[],
+                    choices=["c1", "batched", "serving", "large", "grid3d", "randlocal"],
+                    help="leave a workload out of the default run")
+    ap.add_argument("--serve-measured", type=int, default=10000,
+                    help="measured queries per Poisson load (after a 1 s warm-up)")
     ap.add_argument("--serve-scale", type=int, default=24)
     ap.add_argument("--serve-queries", type=int, default=2048)
     ap.add_argument("--serve-state", choices=["dense", "compact"], default="compact",
@@ -591,7 +694,11 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=256,
                     help="batch slots of the serving engine")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of oracle time for the CPU baseline (0 = skip)")
+                    help="seconds of oracle time for the CPU baseline on the headline "
+                         "queries (0 = skip)")
+    ap.add_argument("--cpu-mix-budget", type=float, default=5.0,
+                    help="seconds of oracle time on the plain and batched queries together "
+                         "(0 = skip)")
     ap.add_argument("--cpu-mc-budget", type=float, default=10.0,
                     help="seconds for the multicore (OpenMP) CPU baseline (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -621,10 +728,15 @@ def main():
     t0 = time.time()
     g = synth.rmat(22, 16, seed=1)
     log("graph 2^22: n=%d arcs=%d maxdeg=%d (%.1fs)" % (g.n, g.arcs, g.deg.max(), time.time() - t0))
-    want = lambda w: args.only is None or args.only == w
+    want = lambda w: (args.only is None and w not in args.skip) or args.only == w
     plain = bench_plain(plc, synth, g, args.steps, args.warmup) if want("plain") else None
     if plain:
         log("plain: %.3g edges/s, %.1f queries/s" % (plain["edges_per_s"], plain["queries_per_s"]))
+    c1 = bench_c1(plc, synth) if want("c1") else None
+    if c1:
+        log("c1 (R-MAT 2^16 from vertex %d): %.2f ms per query, %.3g edges/s, %d rounds, "
+            "%d binned" % (c1["seed"], c1["seconds_per_query"] * 1e3, c1["edges_per_s"],
+                           c1["per_query"]["rounds"], c1["per_query"]["bin_rounds"]))
     bat = bench_batched(plc, synth, g, max(2, args.steps // 2), 1) if want("batched") else None
     if bat:
         log("batched: %.3g edges/s, %.1f queries/s" % (bat["edges_per_s"], bat["queries_per_s"]))
@@ -634,7 +746,8 @@ def main():
         log("batched (compact tables): %.3g edges/s, %.1f queries/s" % (
             bat_c["edges_per_s"], bat_c["queries_per_s"]))
     srv = (bench_serving(plc, synth, args.serve_scale, args.serve_queries, args.serve_slots,
-                         compact=args.serve_state == "compact") if want("serving") else None)
+                         compact=args.serve_state == "compact", measured=args.serve_measured)
+           if want("serving") else None)
     rules = bench_rules(plc, synth, g, plain["seeds"]) if plain else None
     if rules:
         log("rules: optimized %.2f ms/query, original %.2f ms/query (%.2fx), pushes x%.2f" % (
@@ -658,7 +771,7 @@ def main():
                 rloc["seconds_per_query"] * 1e3, rloc["speedup_vs_paper_40core"],
                 rloc["edges_per_s"], rloc["batched_compact"]["queries_per_s"],
                 rloc["batched_compact"]["edges_per_s"]))
-    big = bench_large(plc, synth) if args.only == "large" else None
+    big = bench_large(plc, synth) if want("large") else None
     if big:
         log("large: %.3g edges/s, %.1f queries/s" % (big["edges_per_s"], big["queries_per_s"]))
 
@@ -688,6 +801,9 @@ def main():
         out["per_query"] = main_res["per_query"]
         out["roofline"] = main_res["roofline"]
         out["kernels"] = main_res["kernels"]
+        for k in ("device_ms", "result_copy", "without_result_copy"):
+            if k in main_res:
+                out[k] = main_res[k]
         out["launch_shapes"] = main_res["launch_shapes"]
     if bat:
         out["batched"] = {k: v for k, v in bat.items() if k != "queries"}
@@ -697,6 +813,8 @@ def main():
         out["batched_compact"] = {k: v for k, v in bat_c.items() if k != "queries"}
     if big:
         out["large"] = big
+    if c1:
+        out["c1"] = c1
     if grid:
         out["grid3d"] = grid
     if rloc:
@@ -708,17 +826,24 @@ def main():
         out["nibble"] = nibble
     if srv:
         out["serving"] = srv
-    work = []
-    if plain:
-        work += [(s, 0.01, 1e-7) for s in plain["seeds"]]
+    head = [(s, 0.01, 1e-7) for s in plain["seeds"]] if plain else []
+    mix = list(head)
     if bat:
         q = bat["queries"]
-        work += list(zip(q.seeds, q.alpha, q.eps))
-    if args.cpu_budget > 0 and work:
+        mix += list(zip(q.seeds, q.alpha, q.eps))
+    if args.cpu_budget > 0 and head:
         import oracle
-        out["cpu_baseline"] = cpu_baseline(oracle, g, work, args.cpu_budget)
-    if args.cpu_mc_budget > 0 and work:
-        out["cpu_multicore"] = cpu_multicore_baseline(g, work, args.cpu_mc_budget)
+        out["cpu_baseline"] = cpu_baseline(
+            oracle, g, head, args.cpu_budget,
+            "the headline workload: the 16 plain R-MAT 2^22 queries (alpha 0.01, eps 1e-7) in "
+            "order, repeated")
+    if args.cpu_mix_budget > 0 and mix:
+        import oracle
+        out["cpu_baseline_mix"] = cpu_baseline(
+            oracle, g, mix, args.cpu_mix_budget,
+            "the 16 plain queries, then the 256 batched queries, in order, repeated")
+    if args.cpu_mc_budget > 0 and head:
+        out["cpu_multicore"] = cpu_multicore_baseline(g, head, args.cpu_mc_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -22,13 +22,14 @@ import numpy as np
 
 @dataclass
 class ServeReport:
-    latency_s: np.ndarray          # per query, in arrival order
+    latency_s: np.ndarray          # per measured query, in arrival order
     ids: np.ndarray                # query handles (results kept until released)
-    wall_s: float                  # first arrival to last completion
+    wall_s: float                  # measured window: first measured arrival to last completion
     steps: int                     # plc_progress calls
     busy_steps: int = 0
     max_in_flight: int = 0
     edges: int = 0
+    warmup_queries: int = 0        # arrivals inside the warm-up window (not measured)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -47,11 +48,15 @@ def poisson_arrivals(count: int, qps: float, rng: np.random.Generator) -> np.nda
 
 
 def serve(ctx, g, seeds, alphas, epss, arrivals, release: bool = True,
-          clock=time.perf_counter) -> ServeReport:
+          clock=time.perf_counter, warmup_s: float = 0.0, fetch: bool = False,
+          flags: int = 0) -> ServeReport:
     """Run the request loop until every query has finished.
 
     seeds, alphas, epss: per-query parameters; arrivals: non-decreasing
-    arrival times in seconds from the start of the loop.
+    arrival times in seconds from the start of the loop.  Queries arriving
+    before warmup_s run but are left out of the latencies and the rate.
+    fetch: copy each finished query's result (support in sweep order and p
+    on it, so the cluster and p) to the host before it counts as done.
     """
     seeds = np.asarray(seeds)
     alphas = np.broadcast_to(np.asarray(alphas, np.float64), seeds.shape)
@@ -69,7 +74,7 @@ def serve(ctx, g, seeds, alphas, epss, arrivals, release: bool = True,
         now = clock() - t0
         j = int(np.searchsorted(arrivals, now, side="right"))
         if j > nxt:
-            new = ctx.submit(g, seeds[nxt:j], alphas[nxt:j], epss[nxt:j])
+            new = ctx.submit(g, seeds[nxt:j], alphas[nxt:j], epss[nxt:j], flags=flags)
             for k, qid in enumerate(new):
                 index[qid] = nxt + k
                 ids[nxt + k] = qid
@@ -80,20 +85,26 @@ def serve(ctx, g, seeds, alphas, epss, arrivals, release: bool = True,
             steps += 1
             busy += 1
             max_fl = max(max_fl, left + len(done))
-            t_done = clock() - t0
             for qid in done:
                 i = index.pop(qid)
-                lat[i] = t_done - arrivals[i]
-                if release:
+                if fetch:
+                    res = ctx.result(qid, release=release)
+                    edges += res.info["edges"]
+                elif release:
                     info = ctx.result_info(qid)
                     edges += info["edges"]
                     ctx.release(qid)
+                lat[i] = (clock() - t0) - arrivals[i]
         elif nxt < n:
             wait = arrivals[nxt] - (clock() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.001))
-    wall = (clock() - t0) - (arrivals[0] if n else 0.0)
-    return ServeReport(lat, ids, wall, steps, busy, max_fl, edges)
+    end = clock() - t0
+    meas = arrivals >= warmup_s if warmup_s > 0 else np.ones(n, bool)
+    first = arrivals[meas][0] if meas.any() else 0.0
+    wall = end - first
+    return ServeReport(lat[meas], ids, wall, steps, busy, max_fl, edges,
+                       warmup_queries=int(n - meas.sum()))
 
 
 def saturation(ctx, g, seeds, alphas, epss) -> ServeReport:

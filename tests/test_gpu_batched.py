@@ -185,3 +185,20 @@ def test_batched_launch_modes(plc, graphs):
         for i, qid in enumerate(ids):
             check_query(g, c.result(qid, release=True), int(seeds[i]), float(alpha[i]),
                         float(eps[i]), int(rules[i]))
+
+
+def test_batched_flags_and_device_time(setup, plc):
+    """The batched path honours PLC_QF_NO_RESIDUAL and reports each query's
+    device time from admission to its sweep's argmin."""
+    g, ctx, hg = setup
+    seeds, alpha, eps, rules = mixed_queries(g, 24, seed=41)
+    ids_a, infos_a = ctx.run_batched(hg, seeds, alpha, eps, rules)
+    ids_b, infos_b = ctx.run_batched(hg, seeds, alpha, eps, rules, flags=plc.PLC_QF_NO_RESIDUAL)
+    for i, (qa, qb) in enumerate(zip(ids_a, ids_b)):
+        ia, ib = infos_a[i], infos_b[i]
+        a = ctx.result(qa, release=True)
+        b = ctx.result(qb, release=True)
+        assert ib["flags"] == plc.PLC_QF_NO_RESIDUAL and ib["r_nnz"] == ia["r_nnz"]
+        assert len(b.r_ids) == 0
+        check_same(g, a, b)
+        assert 0 < ia["device_ns"] < 10 ** 10 and 0 < ib["device_ns"] < 10 ** 10

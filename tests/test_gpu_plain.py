@@ -337,3 +337,26 @@ def test_seed_set_rejects_bad_input(ctx, plc):
     if len(iso):
         with pytest.raises(plc.PlcError):
             ctx.run_set(hg, [int(iso[0])], 0.01, 1e-6)
+
+
+def test_query_flags_and_device_time(ctx, plc):
+    """PLC_QF_NO_RESIDUAL keeps the cluster and p but no residual vector
+    (its count is still reported); every result carries the query's device
+    time from the kernels' own clock; unknown flags are rejected."""
+    g, hg = graph(ctx, "rmat13")
+    seeds = [int(s) for s in synth.uniform_seeds(g, 3, seed=17)]
+    ids_a, infos_a = ctx.run(hg, seeds, 0.01, 1e-6, OPT)
+    ids_b, infos_b = ctx.run(hg, seeds, 0.01, 1e-6, OPT, flags=plc.PLC_QF_NO_RESIDUAL)
+    for qa, qb, ia, ib, s in zip(ids_a, ids_b, infos_a, infos_b, seeds):
+        a = ctx.result(qa, release=True)
+        b = ctx.result(qb, release=True)
+        say("flags", ib["flags"], "r_nnz", ib["r_nnz"], "device_ns", ia["device_ns"], ib["device_ns"],
+            "host_ns", ia["host_ns"])
+        assert ia["flags"] == 0 and ib["flags"] == plc.PLC_QF_NO_RESIDUAL
+        assert ib["r_nnz"] == ia["r_nnz"] > 0 and len(b.r_ids) == 0 and len(b.r_vals) == 0
+        check_same(g, a, b)
+        check_query(g, a, s, 0.01, 1e-6, OPT)
+        for info in (ia, ib):
+            assert 0 < info["device_ns"] < 10 ** 10
+    ids, infos = ctx.run(hg, [seeds[0]], 0.01, 1e-6, OPT, check=False, flags=2)
+    assert ids[0] == 0 and infos[0]["status"] == plc.PLC_E_INVALID
