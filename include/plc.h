@@ -217,6 +217,41 @@ plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, int32_t count
                    plc_result_info* infos);
 
 /*
+ * Allocation-free variant of plc_run for one query, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): no context, no arena, and no call to
+ * hipMalloc, hipFree, hipHostMalloc or any other allocating routine.  The
+ * query's working state (state records, frontiers, sort and sweep buffers,
+ * about 152 bytes per vertex plus 4 bytes per 1024 arcs) lives in one fixed
+ * device array of PLC_NOALLOC_SCRATCH_BYTES inside the library, which every
+ * GPU the library runs on holds until the process ends; graphs whose state
+ * does not fit (about 400,000 vertices) get PLC_E_NOMEM.  Every call
+ * re-initialises that array, so calls that overlap on one GPU (from several
+ * host threads, or on several streams) race and must not be made; calls on
+ * different GPUs are independent.
+ *   device:      HIP device to run on (made current).
+ *   hip_stream:  hipStream_t for all work, may be NULL; the call blocks until
+ *                its work on that stream is done.
+ *   d_off, d_nbr: the CSR graph in device memory (offsets n+1 int64, neighbour
+ *                ids num_arcs int32, as in plc_graph_load), read only; the
+ *                caller owns them.
+ *   q:           the query (seed, alpha, eps, rule, flags as in plc_query).
+ *   d_sweep_ids, d_sweep_p: caller-owned device buffers of n entries each;
+ *                on return their first info->support entries hold the
+ *                support in sweep order and p on it (the cluster is the
+ *                first info->kstar).  No residual vector is returned.
+ *   info:        host struct, filled as by plc_run (bin_rounds 0: this
+ *                variant always uses the atomic scatter).
+ * Errors: PLC_E_INVALID (null pointer, bad sizes, device or query
+ * parameters, a seed of degree 0), PLC_E_NOMEM (state larger than the array;
+ * nothing runs), PLC_E_HIP.  Same kernels and results as plc_run.
+ */
+#define PLC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+plc_status plc_run_noalloc(int32_t device, void* hip_stream, int64_t n, int64_t num_arcs,
+                           const int64_t* d_off, const int32_t* d_nbr, const plc_query* q,
+                           int32_t* d_sweep_ids, double* d_sweep_p, plc_result_info* info);
+
+/*
  * Plain path, one query from a seed set (Sec. 3: the local algorithms start
  * from a seed vertex or a set of seed vertices).  The paper leaves the
  * initial split of the unit mass open; it is split equally over the

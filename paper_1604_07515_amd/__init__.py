@@ -37,7 +37,7 @@ PLC_QF_NO_RESIDUAL = 1
 # Every symbol include/plc.h declares.
 SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_graph_free",
            "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_run_nibble",
-           "plc_run_beta",
+           "plc_run_beta", "plc_run_noalloc",
            "plc_result_info_get",
            "plc_result_copy",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
@@ -129,6 +129,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                      C.POINTER(plc_result_info)], I32),
         "plc_run_set": ([P, P, P, I32, C.c_double, C.c_double, I32, C.POINTER(U64),
                          C.POINTER(plc_result_info)], I32),
+        "plc_run_noalloc": ([I32, P, I64, I64, P, P, C.POINTER(plc_query), P, P,
+                             C.POINTER(plc_result_info)], I32),
         "plc_run_hkpr": ([P, P, I32, I32, C.c_double, C.c_double, C.POINTER(U64),
                           C.POINTER(plc_result_info)], I32),
         "plc_run_nibble": ([P, P, I32, C.c_double, I32, C.POINTER(U64),
@@ -478,6 +480,31 @@ def batch_arena_bytes(n: int, arcs: int, slots: int, compact: bool = False,
     fixed = (28 * nf_cap + 4 * (e_cap // 1024 + 2) + 96 * (max(nf_cap, s_cap) // 1024 + 2)
              + 56 * s_cap + 1024 * slots + 8 * n + (1 << 20))
     return int((per_slot * slots + fixed) * 17 // 16 + (192 << 20) + table_bytes)
+
+
+def run_noalloc(off, nbr, seed: int, alpha: float, eps: float, rule: int = PLC_RULE_OPT,
+                flags: int = 0, device: int = 0, stream=None, out=None, check: bool = True):
+    """plc_run_noalloc (one plain query, working state in the library's fixed
+    device array, nothing allocated by the library).  off, nbr: torch tensors
+    on the GPU (int64 n+1, int32 arcs).  out: optional (ids, p) torch tensors
+    of n entries on the same GPU, else allocated here.  Returns (status,
+    info, ids, p) with ids[:support], p[:support] the sweep order and p."""
+    import torch
+    lib = load_library()
+    n = int(off.numel()) - 1
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=off.device),
+               torch.empty(n, dtype=torch.float64, device=off.device))
+    ids, p = out
+    st = stream if stream is not None else torch.cuda.current_stream(off.device)
+    q = Context.queries([int(seed)], alpha, eps, rule, flags)
+    info = plc_result_info()
+    rc = lib.plc_run_noalloc(int(device), C.c_void_p(st.cuda_stream), n, int(nbr.numel()),
+                             C.c_void_p(off.data_ptr()), C.c_void_p(nbr.data_ptr()), q,
+                             C.c_void_p(ids.data_ptr()), C.c_void_p(p.data_ptr()), C.byref(info))
+    if check and rc != PLC_OK:
+        raise PlcError(rc, "plc_run_noalloc")
+    return rc, info.as_dict(), ids, p
 
 
 def plain_arena_bytes(n: int, arcs: int) -> int:

@@ -22,7 +22,7 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["kernels.hip", "sort.hip", "batch.hip", "plc.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "batch.hip", "plc.cpp", "noalloc.cpp"]
 
 
 def hipcc() -> str:
