@@ -1,23 +1,36 @@
 """Parity at the benchmark's full sizes, in the launch shapes it times.
 
 * plain: R-MAT 2^22 (ef 16), the benchmark's 16 uniform seeds, alpha 0.01,
-  eps 1e-7, after the same autotuning; every query against the oracle.
+  eps 1e-7, after the same autotuning, with the same query flags (no
+  residual kept; p and the cluster copied back); every query against the
+  oracle, and the same queries with the residual kept.
 * batched: the same graph, the benchmark's 256 queries (eps log-uniform in
-  [1e-7, 1e-5], alpha in {0.01, 0.05}) through 256 slots after autotuning;
-  a sample of 64 against the oracle, properties that hold at any size
-  (mass, termination, the reported cut and volume recounted from the
-  cluster) on all 256.
+  [1e-7, 1e-5], alpha in {0.01, 0.05}) through 256 slots after autotuning,
+  with dense slots and with compact tables (8 GiB of tables, as timed); a
+  sample of 64 against the oracle, properties that hold at any size (mass,
+  termination, the reported cut and volume recounted from the cluster) on
+  all 256.
 * serving: R-MAT 2^24, degree-weighted seeds, eps log-uniform in
-  [1e-7, 1e-4], 64 slots, Poisson arrivals; a sample against the oracle,
+  [1e-7, 1e-4], compact tables over 256 slots and no residual kept, as the
+  benchmark serves them, Poisson arrivals; a sample against the oracle,
   properties on all, and a few queries re-run alone.
+* Nibble from the top hub of R-MAT 2^22 with T = 2 and no truncation: a
+  support of 2,208,937 vertices (more than 2^21), so the sweep's deepest
+  merge passes and multi-million scans are checked against the oracle.
+
+Every oracle comparison is strict (p and r to 1e-12, counters, order,
+cluster) unless the oracle reports a threshold decision within 1e-10 of its
+threshold; for these inputs the oracle flags none, and the tests assert that
+every sampled query was checked strictly.
 """
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 import synth
-from parity import check_properties, check_query, check_same
+from parity import check_nibble, check_properties, check_query, check_same
 
 pytestmark = pytest.mark.gpu
 
@@ -38,6 +51,15 @@ def g22():
     return synth.rmat(22, 16, seed=1)
 
 
+def strict_report(name, reports):
+    """Print and return the number of strictly checked queries; the flagged
+    ones are listed with the oracle's gap."""
+    flagged = [(i, r["gap"]) for i, r in reports if r["tie_push"]]
+    say("%s: %d of %d checked strictly; flagged (index, gap): %s" % (
+        name, len(reports) - len(flagged), len(reports), flagged))
+    return len(reports) - len(flagged)
+
+
 def test_plain_rmat22_bench_shapes(plc, g22):
     g = g22
     seeds = synth.uniform_seeds(g, 16, seed=2)
@@ -46,34 +68,57 @@ def test_plain_rmat22_bench_shapes(plc, g22):
         hg = ctx.load_graph(g.off, g.nbr)
         tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
         say("plain 2^22 shapes", tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"])
-        ids, infos = ctx.run(hg, seeds, 0.01, 1e-7)
+        sl = [int(s) for s in seeds]
+        ids, infos = ctx.run(hg, sl, 0.01, 1e-7, flags=plc.PLC_QF_NO_RESIDUAL)
+        ids_r, _ = ctx.run(hg, sl, 0.01, 1e-7)
+        reps = []
+        for i, (qid, qr) in enumerate(zip(ids, ids_r)):
+            say("plain 2^22 seed", sl[i], "binned rounds", infos[i]["bin_rounds"])
+            orc = oracle.prnibble(g.off, g.nbr, sl[i], 0.01, 1e-7)
+            res = ctx.result(qid, release=True)
+            reps.append((i, check_query(g, res, sl[i], 0.01, 1e-7, 0, orc=orc, with_r=False)))
+            res_r = ctx.result(qr, release=True)
+            check_query(g, res_r, sl[i], 0.01, 1e-7, 0, orc=orc)
+            check_same(g, res_r, res)
+        assert strict_report("plain 2^22", reps) == 16
+        assert sum(x["bin_rounds"] for x in infos) >= 16
+    finally:
+        ctx.close()
+
+
+def _batched(plc, g, compact):
+    qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
+    tables = (8 << 30) if compact else 0
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
+                      + plc.batch_arena_bytes(g.n, g.arcs, 256, compact=compact,
+                                              table_bytes=tables) + (512 << 20),
+                      compact=compact)
+    name = "batched 2^22 %s" % ("compact" if compact else "dense")
+    try:
+        hg = ctx.load_graph(g.off, g.nbr)
+        assert ctx.batch_reserve(hg, 256) == 256
+        tune = ctx.autotune(hg, qs.seeds, qs.alpha, qs.eps, plc.PLC_TUNE_BATCH)
+        say(name, "shapes", tune["batch_self"], tune["batch_scatter"])
+        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps)
+        sample = set(np.argsort(qs.eps)[::4].tolist())  # every 4th eps, smallest to largest
+        reps = []
         for i, qid in enumerate(ids):
-            say("plain 2^22 seed", int(seeds[i]))
-            check_query(g, ctx.result(qid, release=True), int(seeds[i]), 0.01, 1e-7, 0)
+            res = ctx.result(qid, release=True)
+            check_properties(g, res, float(qs.eps[i]))
+            if i in sample:
+                reps.append((i, check_query(g, res, int(qs.seeds[i]), float(qs.alpha[i]),
+                                            float(qs.eps[i]), 0)))
+        assert strict_report(name, reps) == len(sample) == 64
     finally:
         ctx.close()
 
 
 def test_batched_rmat22_bench_shapes(plc, g22):
-    g = g22
-    qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
-    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
-                      + plc.batch_arena_bytes(g.n, g.arcs, 256) + (512 << 20))
-    try:
-        hg = ctx.load_graph(g.off, g.nbr)
-        assert ctx.batch_reserve(hg, 256) == 256
-        tune = ctx.autotune(hg, qs.seeds, qs.alpha, qs.eps, plc.PLC_TUNE_BATCH)
-        say("batched 2^22 shapes", tune["batch_self"], tune["batch_scatter"])
-        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps)
-        sample = set(np.argsort(qs.eps)[::4].tolist())  # every 4th eps, smallest to largest
-        for i, qid in enumerate(ids):
-            res = ctx.result(qid, release=True)
-            check_properties(g, res, float(qs.eps[i]))
-            if i in sample:
-                check_query(g, res, int(qs.seeds[i]), float(qs.alpha[i]), float(qs.eps[i]), 0)
-        say("batched 2^22: %d checked against the oracle" % len(sample))
-    finally:
-        ctx.close()
+    _batched(plc, g22, compact=False)
+
+
+def test_batched_compact_rmat22_bench_shapes(plc, g22):
+    _batched(plc, g22, compact=True)
 
 
 def test_serving_rmat24_bench_shapes(plc):
@@ -81,27 +126,51 @@ def test_serving_rmat24_bench_shapes(plc):
     g = synth.rmat(24, 16, seed=1)
     say("serving graph 2^24 arcs", g.arcs)
     rng = np.random.default_rng(2)
-    nq = 256
-    seeds = synth.degree_weighted_seeds(g, 2048, rng)[:nq]
-    eps = (10.0 ** rng.uniform(-7, -4, 2048))[:nq]
+    nq = 512
+    seeds = synth.degree_weighted_seeds(g, 40000, rng)[:nq]
+    eps = (10.0 ** rng.uniform(-7, -4, 40000))[:nq]
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs)
-                      + plc.batch_arena_bytes(g.n, g.arcs, 64) + (1 << 30))
+                      + plc.batch_arena_bytes(g.n, g.arcs, 256, compact=True,
+                                              table_bytes=8 << 30) + (1 << 30), compact=True)
     try:
         hg = ctx.load_graph(g.off, g.nbr)
-        assert ctx.batch_reserve(hg, 64) == 64
+        assert ctx.batch_reserve(hg, 256) == 256
         ctx.autotune(hg, seeds[:128], 0.01, eps[:128], plc.PLC_TUNE_BATCH)
-        arr = serve.poisson_arrivals(nq, 4000.0, np.random.default_rng(3))
-        rep = serve.serve(ctx, hg, seeds, 0.01, eps, arr, release=False)
+        arr = serve.poisson_arrivals(nq, 8000.0, np.random.default_rng(3))
+        rep = serve.serve(ctx, hg, seeds, 0.01, eps, arr, release=False,
+                          flags=plc.PLC_QF_NO_RESIDUAL)
         say("serving 2^24: %.0f q/s, max in flight %d" % (rep.queries_per_s, rep.max_in_flight))
         assert rep.max_in_flight > 1
         results = [ctx.result(int(qid), release=True) for qid in rep.ids]
         for i, res in enumerate(results):
-            check_properties(g, res, float(eps[i]))
-        for i in range(0, nq, 8):
+            check_properties(g, res, float(eps[i]), with_r=False)
+        reps = []
+        for i in range(0, nq, 16):
             say("serving 2^24 oracle query", i)
-            check_query(g, results[i], int(seeds[i]), 0.01, float(eps[i]), 0)
+            reps.append((i, check_query(g, results[i], int(seeds[i]), 0.01, float(eps[i]), 0,
+                                        with_r=False)))
+        assert strict_report("serving 2^24", reps) == len(reps)
         for i in (0, 101, 255):
-            ids1, _ = ctx.run_batched(hg, [int(seeds[i])], 0.01, float(eps[i]))
+            ids1, _ = ctx.run_batched(hg, [int(seeds[i])], 0.01, float(eps[i]),
+                                      flags=plc.PLC_QF_NO_RESIDUAL)
             check_same(g, ctx.result(ids1[0], release=True), results[i])
+    finally:
+        ctx.close()
+
+
+def test_nibble_support_above_2_21(plc, g22):
+    """Nibble (Sec. 3.2) from vertex 0 (the top hub) with T = 2 and eps
+    1e-300 (nothing truncated): p_2 covers every vertex within two hops,
+    2,208,937 of them, and the sweep over it is checked against the oracle."""
+    g = g22
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
+    try:
+        hg = ctx.load_graph(g.off, g.nbr)
+        qid, info = ctx.run_nibble(hg, 0, 1e-300, 2)
+        say("nibble 2^22 hub: support", info["support"], "kstar", info["kstar"])
+        assert info["support"] > (1 << 21)
+        orc = oracle.nibble(g.off, g.nbr, 0, 1e-300, 2)
+        rep = check_nibble(g, ctx.result(qid, release=True), orc)
+        say("nibble report", rep)
     finally:
         ctx.close()
