@@ -165,6 +165,12 @@ typedef struct {
   int32_t bin_rounds;
   uint32_t flags;     /* the query's flags */
   int64_t bin_edges;
+  /* plain path, plc_run only: 1 when this query's initialisation and first
+   * rounds were queued behind the previous query's read-back and started
+   * there; 2 when they were queued there but stood aside (the previous query
+   * still needed work) and the query started afresh; 0 otherwise */
+  int32_t pipelined;
+  int32_t reserved;
 } plc_result_info;
 
 /* Status code to a static string. */

@@ -74,10 +74,10 @@ class plc_result_info(C.Structure):
                 ("r_nnz", C.c_int64), ("launches", C.c_int32), ("loop_rounds", C.c_int32),
                 ("loop_edges", C.c_int64), ("host_ns", C.c_int64),
                 ("device_ns", C.c_int64), ("bin_rounds", C.c_int32), ("flags", C.c_uint32),
-                ("bin_edges", C.c_int64)]
+                ("bin_edges", C.c_int64), ("pipelined", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 PLC_TUNE_PLAIN = 1
@@ -513,9 +513,10 @@ def plain_arena_bytes(n: int, arcs: int) -> int:
     per_arc = 4               # neighbour ids
     tiles = 4 * (arcs // 1024 + 2)
     scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
-    # binned scatter: pairs (8 B per edge of the largest binned round, at most
-    # 2^23) and the per-chunk run table (2049 ints per 4096-edge chunk)
-    chunks = (min(max(arcs, 1), 1 << 23) + 4095) // 4096
-    bins = n // 16 + 8 * 2048 + chunks * (8 * 4096 + 4 * 2049) + 5 * 256
+    # binned scatter (graphs up to 6,291,456 vertices): pairs (8 B per edge of the
+    # largest binned round, at most 2^23) and the per-chunk run table (2049
+    # ints per 2048-edge chunk)
+    chunks = (min(max(arcs, 1), 1 << 23) + 2047) // 2048 if n <= 1536 * 4096 else 0
+    bins = n // 16 + 12 * 2048 + chunks * (8 * 2048 + 4 * 2049) + 5 * 256
     return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + bins + (64 << 20)
                + 8 * 1025 + 2048)

@@ -165,6 +165,7 @@ struct plc_ctx {
   int grid_self = 256, grid_scatter = 1024, grid_sweep = 512, grid_bin = 1024;
   double clock_ns = 10.0;         // nanoseconds per tick of the kernels' constant-rate clock
   uint32_t cur_flags = 0;         // plain path: flags of the running query
+  int32_t cur_pipe = 0;           // plain path: plc_result_info.pipelined of the running query
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
   std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
@@ -406,13 +407,15 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
   a.work_log = static_cast<int32_t*>(take(4 * 2 * (size_t)plc::kMaxChunk));
   // Destination bins of the binned scatter: whole kBinGran-vertex blocks, at
   // most kBinWidth vertices and about 1/1024 of the volume each (the volume
-  // target doubles until fewer than kMaxBins bins result); off when even
-  // the width bound needs 3/4 of kMaxBins bins or the context turned it off.
+  // target doubles until fewer than kMaxBins bins result); off for graphs of
+  // more than kBinMaxVertices vertices or when the context turned it off.
   std::vector<int32_t> bin_of_blk, bin_lo;
   std::vector<long long> bin_vol;
   const int64_t nblk = (n + plc::kBinGran - 1) / plc::kBinGran;
   const bool bins_on = ctx->opt.bin_min_edges >= 0 &&
-                       (n + plc::kBinWidth - 1) / plc::kBinWidth <= plc::kMaxBins * 3 / 4;
+                       n <= plc::kBinMaxVertices;
+  static_assert(plc::kBinMaxVertices / plc::kBinWidth <= plc::kMaxBins * 3 / 4,
+                "the width bound alone leaves room for the volume bins");
   if (bins_on) {
     long long vt = std::max<long long>(1, num_arcs / 1024);
     for (;;) {
@@ -705,10 +708,13 @@ static int prelaunch(plc_ctx* ctx, plc_graph* g, const plc_query& q) {
 static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64_t* id_out,
                           plc_result_info* info_out, const int32_t* set = nullptr,
                           int32_t nset = 0, double beta = 1.0, int pre = 0,
-                          const plc_query* next = nullptr, int* next_pre = nullptr) {
+                          const plc_query* next = nullptr, int* next_pre = nullptr,
+                          int pipe_in = 0, int* next_pipe = nullptr) {
   ctx->q_t0 = pre > 0 ? ctx->next_t0 : std::chrono::steady_clock::now();
   ctx->cur_flags = q.flags;
+  ctx->cur_pipe = pipe_in;
   if (next_pre) *next_pre = 0;
+  if (next_pipe) *next_pipe = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   if (pre > 0) {
@@ -775,6 +781,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
         // the next query started behind this one: its time counts from here,
         // when this one is known to be done
         if (next_pre) *next_pre = held;
+        if (next_pipe) *next_pipe = 1;
         ctx->next_t0 = std::chrono::steady_clock::now();
       } else {
         // its initialisation stood aside and the chunk continued this query's
@@ -786,6 +793,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
           ctx->broken = true;
           return PLC_E_HIP;
         }
+        if (next_pipe) *next_pipe = 2;
         queued += held;
       }
     }
@@ -926,6 +934,7 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
   info.bin_rounds = h.bin_rounds;
   info.bin_edges = h.bin_edges;
   info.flags = ctx->cur_flags;
+  info.pipelined = ctx->cur_pipe;
   plc_status st = PLC_OK;
   if (!res.block) {
     info.status = PLC_E_NOMEM;
@@ -944,7 +953,8 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
   if (ctx->broken) return PLC_E_HIP;
   (void)hipSetDevice(ctx->device);
   plc_status first = PLC_OK;
-  int pre = 0;  // the current query's queued first chunk (see run_one)
+  int pre = 0;   // the current query's queued first chunk (see run_one)
+  int pipe = 0;  // the current query's plc_result_info.pipelined
   for (int32_t i = 0; i < count; i++) {
     if (!query_ok(g, q[i])) {
       if (ids) ids[i] = 0;
@@ -957,10 +967,11 @@ extern "C" plc_status plc_run(plc_ctx* ctx, plc_graph* g, const plc_query* q, in
     }
     // the next query (when valid) is queued behind this one's first read-back
     const plc_query* nq = i + 1 < count && query_ok(g, q[i + 1]) ? &q[i + 1] : nullptr;
-    int next_pre = 0;
+    int next_pre = 0, next_pipe = 0;
     plc_status st = run_one(ctx, g, q[i], ids ? &ids[i] : nullptr, infos ? &infos[i] : nullptr,
-                            nullptr, 0, 1.0, pre, nq, &next_pre);
+                            nullptr, 0, 1.0, pre, nq, &next_pre, pipe, &next_pipe);
     pre = next_pre;
+    pipe = next_pipe;
     if (st == PLC_E_HIP) return st;
     if (st != PLC_OK && first == PLC_OK) first = st;
   }
@@ -1020,6 +1031,7 @@ extern "C" plc_status plc_run_hkpr(plc_ctx* ctx, plc_graph* g, int32_t seed, int
   (void)hipSetDevice(ctx->device);
   ctx->q_t0 = std::chrono::steady_clock::now();
   ctx->cur_flags = 0;
+  ctx->cur_pipe = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   // threshold of level k: ((e^-t eps) d(w)) / B_k with B_k = 2 N psi_k
@@ -1075,6 +1087,7 @@ extern "C" plc_status plc_run_nibble(plc_ctx* ctx, plc_graph* g, int32_t seed, d
   (void)hipSetDevice(ctx->device);
   ctx->q_t0 = std::chrono::steady_clock::now();
   ctx->cur_flags = 0;
+  ctx->cur_pipe = 0;
   hipStream_t s = ctx->stream;
   const PlainArgs& a = g->args;
   HIPCHK(ctx, plc::launch_nb_init(s, a, seed, eps, T));

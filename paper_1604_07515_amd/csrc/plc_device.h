@@ -195,6 +195,9 @@ constexpr int kBinItemChunks = 2048;   // chunks one pass-B item may span
 constexpr int kBinQ = 4096;            // expected pairs per pass-B item
 constexpr long long kBinEmin = 1 << 19;  // default smallest binned round (edges)
 constexpr long long kBinEmax = 1 << 23;  // largest binned round the pair buffer is sized for
+// larger graphs use the atomic scatter only (their width-bound bins alone
+// would crowd out the volume-balanced ones)
+constexpr long long kBinMaxVertices = (long long)kMaxBins * 3 / 4 * kBinWidth;
 static_assert(kBinChunk <= 65536 && kMaxBins <= 32768, "pass A packs (bin, rank) in 32 bits");
 
 // Host-side launchers (return hipError_t of the launch).

@@ -208,13 +208,13 @@ def torus3d(side: int) -> Graph:
 # Offset range of rand_local: with offsets d drawn with probability
 # proportional to 1/d on [1, RANDLOCAL_RANGE], five draws per vertex at
 # n = 10^7 leave 49.12 M distinct edges, within 0.05 % of the 49,100,524 the
-# paper lists for its randLocal input (Sec. 5, table of inputs).
+# paper lists for its randLocal input (Sec. 4, table of inputs).
 RANDLOCAL_RANGE = 30_000
 
 
 def rand_local_edges(n: int, k: int = 5, seed: int = 1,
                      span: int = RANDLOCAL_RANGE) -> np.ndarray:
-    """The paper's randLocal input (Sec. 5): every vertex v draws k neighbours
+    """The paper's randLocal input (Sec. 4): every vertex v draws k neighbours
     v + d (mod n), the offset d log-uniform on [1, span] (probability about
     proportional to 1/d, so near ids are favoured).  Returns the drawn (v, w)
     pairs; self pairs and duplicates are dropped when the CSR is built."""

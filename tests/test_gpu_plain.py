@@ -268,6 +268,10 @@ def test_queries_pipelined_in_one_call(plc):
             out = check_query(g, res, x, 0.01, e, r)
             if not out["tie_push"]:
                 check_same(g, res, ref)
+        # both branches of the queued start were taken
+        pipes = [info["pipelined"] for info, x in zip(infos, seeds) if x >= 0]
+        say("pipelined per query:", pipes)
+        assert pipes.count(1) >= 1 and pipes.count(2) >= 1
 
 
 def test_result_block_does_not_fit(plc):

@@ -71,13 +71,31 @@ def test_query_generators():
 def test_rand_local_matches_paper_edge_count():
     """The randLocal reading (offsets log-uniform on [1, 30000]) at the
     paper's size: n = 10^7, five draws per vertex leave within 0.1 % of the
-    49,100,524 distinct edges its table of inputs lists (Sec. 5)."""
+    49,100,524 distinct edges its table of inputs lists (Sec. 4)."""
     n = 10_000_000
     e = synth.rand_local_edges(n)
     a, b = np.minimum(e[:, 0], e[:, 1]), np.maximum(e[:, 0], e[:, 1])
     keep = a != b
     distinct = np.unique(a[keep] * n + b[keep]).size
     assert abs(distinct / 49_100_524 - 1) < 1e-3, distinct
+
+
+def test_rand_local_literal_reading_misses_paper_edge_count():
+    """The literal reading of Sec. 4 (a neighbour at id offset d with
+    probability proportional to d) almost never draws the same pair twice:
+    five draws per vertex at n = 10^7 leave ~50.0 M distinct edges, 1.8 %
+    above the table's 49,100,524.  The table's count needs the collisions
+    that draws favouring near ids produce, which is why rand_local favours
+    them (probability about proportional to 1/d)."""
+    n, k = 10_000_000, 5
+    rng = np.random.default_rng(1)
+    u = np.repeat(np.arange(n, dtype=np.int64), k)
+    d = np.ceil(np.sqrt(rng.random(n * k)) * (n - 1)).astype(np.int64)  # P(d) ~ d on [1, n-1]
+    w = (u + d) % n
+    a, b = np.minimum(u, w), np.maximum(u, w)
+    keep = a != b
+    distinct = np.unique(a[keep] * n + b[keep]).size
+    assert distinct / 49_100_524 - 1 > 0.015, distinct
 
 
 def test_rand_local_small():
