@@ -170,7 +170,11 @@ typedef struct {
    * there; 2 when they were queued there but stood aside (the previous query
    * still needed work) and the query started afresh; 0 otherwise */
   int32_t pipelined;
-  int32_t reserved;
+  /* batched path with compact tables only (0 elsewhere): times the query's
+   * table moved to a larger block, and its capacity in records when the
+   * query finished pushing */
+  int32_t table_grows;
+  int64_t table_cap;
 } plc_result_info;
 
 /* Status code to a static string. */
@@ -388,7 +392,8 @@ plc_status plc_wait(plc_ctx* ctx, uint64_t id, int64_t timeout_us);
  * Dense: the state of one slot (residual record, p, two frontier buffers,
  * support and touched lists over all n vertices; plc_batch_reserve takes it
  * for every slot).  Compact: the largest table block the query can reach
- * (36 B per record, capacity the power of two >= 2 x its touched bound).
+ * (36 B per record, capacity twice its touched bound rounded up to a
+ * multiple of 1024 records).
  * The bounds come from the push's work bound (Sec. 3.3): every push except
  * the seed's moves at least alpha' eps d(v) of the unit mass into p, with
  * alpha' = 2 alpha/(1+alpha) for the optimized rule and alpha for the

@@ -74,7 +74,8 @@ class plc_result_info(C.Structure):
                 ("r_nnz", C.c_int64), ("launches", C.c_int32), ("loop_rounds", C.c_int32),
                 ("loop_edges", C.c_int64), ("host_ns", C.c_int64),
                 ("device_ns", C.c_int64), ("bin_rounds", C.c_int32), ("flags", C.c_uint32),
-                ("bin_edges", C.c_int64), ("pipelined", C.c_int32), ("reserved", C.c_int32)]
+                ("bin_edges", C.c_int64), ("pipelined", C.c_int32), ("table_grows", C.c_int32),
+                ("table_cap", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -470,7 +471,7 @@ def batch_arena_bytes(n: int, arcs: int, slots: int, compact: bool = False,
     """Arena bytes for a batch engine with `slots` slots (on top of the plain path).
 
     Dense layout: the slots' per-vertex state (40 B per vertex per slot).
-    Compact layout: `table_bytes` for the running queries' tables (32 B per
+    Compact layout: `table_bytes` for the running queries' tables (36 B per
     table record; plc_query_bytes_estimate bounds one query's need)."""
     per_slot = 0 if compact else 40 * n
     nf_cap = min(max(2 * n, 1 << 22), slots * n)

@@ -32,7 +32,12 @@
 namespace plc {
 
 constexpr int kMaxSlots = 1024;
-constexpr int kSlotRange = 256;  // per-tile slot range aggregated in LDS
+// Per-tile slot range aggregated in LDS, and the hot destinations whose
+// contributions the scatter sums in LDS (the first kHotB of the graph's kHot
+// hot vertices): sized so that four scatter workgroups fit in a CU's LDS.
+constexpr int kSlotRange = 128;
+constexpr int kHotB = 1024;
+static_assert(kHotB <= kHot, "the batched hot set is a prefix of the graph's");
 
 __device__ __forceinline__ int slot_of(const int32_t* pref, int B, long long g) {
   // largest q in [0, B) with pref[q] <= g (pref[B] = total > g)
@@ -66,97 +71,152 @@ __device__ __forceinline__ uint32_t vhash(uint32_t x) {
   return x;
 }
 
+// Home position of v in a table of `cap` records (any capacity: the hash is
+// mapped onto [0, cap) by a multiply-high), and the next position of a probe.
+__device__ __forceinline__ uint32_t home_of(int32_t v, uint32_t cap) {
+  return (uint32_t)(((unsigned long long)vhash((uint32_t)v) * cap) >> 32);
+}
+__device__ __forceinline__ uint32_t probe_next(uint32_t h, uint32_t cap) {
+  return h + 1 == cap ? 0u : h + 1;
+}
+
 // The part of a slot's state the edge scatter needs (staged in LDS per tile).
 struct TabView {
   VRec* tab;
-  double* tp;
-  int32_t mask;
+  int32_t tcap;
 };
 
-// Dense: record v of the slot's n records; always present.
+// Dense: record v of the slot's n records; always present.  The scatter's
+// first load is the record's {d(v), hot code} word, which needs no probing.
 struct DenseState {
   static constexpr bool kCompact = false;
-  __device__ static VRec* insert_v(const TabView& t, int32_t v) { return t.tab + v; }
-  __device__ static int32_t probe_start(const TabView&, int32_t, uint32_t*) { return 0; }
-  __device__ static VRec* probe_finish(const TabView& t, int32_t v, uint32_t, int32_t) {
+  __device__ static unsigned long long probe_start(const BatchArgs&, const TabView& t, int32_t v,
+                                                   uint32_t*) {
+    return *reinterpret_cast<const unsigned long long*>(&t.tab[v].deg);
+  }
+  // record of v, its degree and hot index (-1 when not hot)
+  __device__ static VRec* probe_finish(const BatchArgs&, const TabView& t, int32_t v, uint32_t,
+                                       unsigned long long w, int32_t* d, int32_t* hj) {
+    *d = (int32_t)(uint32_t)w;
+    *hj = -(int32_t)(uint32_t)(w >> 32) - 1;
     return t.tab + v;
   }
-  __device__ static int2 deg_hot_v(const BatchArgs&, const TabView& t, int32_t v) {
-    return *reinterpret_cast<const int2*>(&t.tab[v].deg);
-  }
+  __device__ static int32_t hot_deg(const BatchArgs&, int32_t, int32_t d) { return d; }
   __device__ static VRec* find(const Slot& S, int32_t v) { return S.tab + v; }
-  __device__ static VRec* insert(const Slot& S, int32_t v) { return S.tab + v; }
+  __device__ static VRec* insert(const BatchArgs&, const Slot& S, int32_t v) { return S.tab + v; }
   __device__ static int32_t rank_of(const Slot& S, int32_t v) { return S.tab[v].rank; }
   __device__ static int32_t rank_at(const VRec* tab, int32_t, int32_t v) { return tab[v].rank; }
   __device__ static double* pp(const Slot& S, int32_t v, const VRec*) { return S.tp + v; }
   __device__ static int2 deg_hot(const BatchArgs&, const Slot& S, int32_t v) {
     return *reinterpret_cast<const int2*>(&S.tab[v].deg);
   }
+  __device__ static int32_t deg_rec(const BatchArgs&, int32_t, const VRec* rec) { return rec->deg; }
 };
 
-// Compact: linear probing from vhash(v); the record's deg field holds the key
-// (kEmptyKey when free), rank is 0 outside a sweep.
+// Compact: linear probing from home_of(v).  A record's deg field holds the key
+// (kEmptyKey when free) and its rank field, while the query pushes, a tag
+// written together with the key: -(j+1) for hot vertex j, else
+// -(1 + kHot + d(v)), so the scatter learns d(v) and hotness from the probe
+// itself; the sweep overwrites the tags of the support with ranks >= 1 (its
+// rank lookups treat any value < 1 as "not in the support").
 struct CompactState {
   static constexpr bool kCompact = true;
+  __device__ static int32_t tag_of(int2 dh) { return dh.y < 0 ? dh.y : -1 - kHot - dh.x; }
+  __device__ static unsigned long long word(int32_t key, int32_t tag) {
+    return (unsigned long long)(uint32_t)key | ((unsigned long long)(uint32_t)tag << 32);
+  }
+  __device__ static unsigned long long* kw(const TabView& t, uint32_t h) {
+    return reinterpret_cast<unsigned long long*>(&t.tab[h].deg);
+  }
+  __device__ static unsigned long long probe_load(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   // record holding v, or nullptr when v is not in the table (valid after the
   // kernel that inserted v has finished)
   __device__ static VRec* find(const Slot& S, int32_t v) {
-    const uint32_t m = (uint32_t)S.mask;
-    uint32_t h = vhash((uint32_t)v) & m;
-    for (uint32_t i = 0; i <= m; i++) {
+    const uint32_t cap = (uint32_t)S.tcap;
+    uint32_t h = home_of(v, cap);
+    for (uint32_t i = 0; i < cap; i++) {
       const int32_t k = S.tab[h].deg;
       if (k == v) return S.tab + h;
       if (k == kEmptyKey) return nullptr;
-      h = (h + 1) & m;
+      h = probe_next(h, cap);
     }
     return nullptr;
   }
-  // record of v, claimed with a compare-and-swap when v is new; concurrent
-  // inserts of v agree on one record.  nullptr only if the table is full.
-  __device__ static VRec* insert_v(const TabView& t, int32_t v) {
-    const uint32_t m = (uint32_t)t.mask;
-    uint32_t h = vhash((uint32_t)v) & m;
-    for (uint32_t i = 0; i <= m; i++) {
-      int32_t* kp = &t.tab[h].deg;
-      const int32_t k = __hip_atomic_load(kp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (k == v) return t.tab + h;
+  // Resolve a probe of v that saw `w` at position h: the record holding v,
+  // claimed together with its tag by a 64-bit compare-and-swap when v is new
+  // (tag: the tag to write, or 0 to take it from gdh when needed); concurrent
+  // inserts of v agree on one record.  *tag_out: the record's tag.  nullptr
+  // only if the table is full.
+  __device__ static VRec* claim(const BatchArgs& a, const TabView& t, int32_t v, uint32_t h,
+                                unsigned long long w, int32_t tag, int32_t* tag_out) {
+    const uint32_t cap = (uint32_t)t.tcap;
+    for (uint32_t i = 0; i < cap; i++) {
+      int32_t k = (int32_t)(uint32_t)w;
       if (k == kEmptyKey) {
-        const int32_t old = atomicCAS(kp, kEmptyKey, v);
-        if (old == kEmptyKey || old == v) return t.tab + h;
+        if (tag >= 0) tag = tag_of(a.gdh[v]);
+        const unsigned long long old = atomicCAS(kw(t, h), w, word(v, tag));
+        if (old == w) {
+          *tag_out = tag;
+          return t.tab + h;
+        }
+        w = old;  // taken meanwhile: by v, or by another key
+        k = (int32_t)(uint32_t)w;
       }
-      h = (h + 1) & m;
+      if (k == v) {
+        *tag_out = (int32_t)(uint32_t)(w >> 32);
+        return t.tab + h;
+      }
+      h = probe_next(h, cap);
+      w = probe_load(kw(t, h));
     }
     return nullptr;
   }
-  __device__ static VRec* insert(const Slot& S, int32_t v) {
-    return insert_v(TabView{S.tab, S.tp, S.mask}, v);
+  __device__ static VRec* insert_tag(const BatchArgs& a, const TabView& t, int32_t v, int32_t tag) {
+    uint32_t h;
+    const unsigned long long w = probe_start(a, t, v, &h);
+    int32_t got;
+    return claim(a, t, v, h, w, tag, &got);
   }
-  // insert_v split in two so that a thread's first key loads overlap:
-  // probe_start loads the key at v's home position, probe_finish resolves it.
-  __device__ static int32_t probe_start(const TabView& t, int32_t v, uint32_t* h) {
-    *h = vhash((uint32_t)v) & (uint32_t)t.mask;
-    return __hip_atomic_load(&t.tab[*h].deg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __device__ static VRec* insert(const BatchArgs& a, const Slot& S, int32_t v) {
+    return insert_tag(a, TabView{S.tab, S.tcap}, v, 0);
   }
-  __device__ static VRec* probe_finish(const TabView& t, int32_t v, uint32_t h, int32_t k) {
-    if (k == v) return t.tab + h;
-    if (k == kEmptyKey) {
-      const int32_t old = atomicCAS(&t.tab[h].deg, kEmptyKey, v);
-      if (old == kEmptyKey || old == v) return t.tab + h;
-    }
-    return insert_v(t, v);  // collision: probe on from the home position
+  // The scatter's probe in two steps so that a thread's first loads overlap:
+  // probe_start loads the {key, tag} word at v's home position, probe_finish
+  // resolves it (probing on, or claiming a free record).
+  __device__ static unsigned long long probe_start(const BatchArgs&, const TabView& t, int32_t v,
+                                                   uint32_t* h) {
+    *h = home_of(v, (uint32_t)t.tcap);
+    return probe_load(kw(t, *h));
   }
-  __device__ static int2 deg_hot_v(const BatchArgs& a, const TabView&, int32_t v) {
-    return a.gdh[v];
+  // record of v, its degree (-1 for a hot vertex: see hot_deg) and hot index
+  // (-1 when not hot)
+  __device__ static VRec* probe_finish(const BatchArgs& a, const TabView& t, int32_t v, uint32_t h,
+                                       unsigned long long w, int32_t* d, int32_t* hj) {
+    int32_t tag = 0;
+    VRec* rec = (int32_t)(uint32_t)w == v ? t.tab + h : claim(a, t, v, h, w, 0, &tag);
+    if ((int32_t)(uint32_t)w == v) tag = (int32_t)(uint32_t)(w >> 32);
+    *hj = tag >= -kHot ? -tag - 1 : -1;
+    *d = tag >= -kHot ? -1 : -1 - kHot - tag;
+    return rec;
   }
-  __device__ static int32_t rank_of(const Slot& S, int32_t v) { return rank_at(S.tab, S.mask, v); }
-  __device__ static int32_t rank_at(const VRec* tab, int32_t mask, int32_t v) {
-    const uint32_t m = (uint32_t)mask;
-    uint32_t h = vhash((uint32_t)v) & m;
-    for (uint32_t i = 0; i <= m; i++) {
-      const int2 kr = *reinterpret_cast<const int2*>(&tab[h].deg);  // {key, rank}
+  __device__ static int32_t hot_deg(const BatchArgs& a, int32_t v, int32_t d) {
+    return d >= 0 ? d : a.gdh[v].x;
+  }
+  __device__ static int32_t deg_rec(const BatchArgs& a, int32_t v, const VRec* rec) {
+    const int32_t tag = rec->rank;
+    return tag < -kHot ? -1 - kHot - tag : a.gdh[v].x;
+  }
+  __device__ static int32_t rank_of(const Slot& S, int32_t v) { return rank_at(S.tab, S.tcap, v); }
+  __device__ static int32_t rank_at(const VRec* tab, int32_t tcap, int32_t v) {
+    const uint32_t cap = (uint32_t)tcap;
+    uint32_t h = home_of(v, cap);
+    for (uint32_t i = 0; i < cap; i++) {
+      const int2 kr = *reinterpret_cast<const int2*>(&tab[h].deg);  // {key, rank or tag}
       if (kr.x == v) return kr.y;
       if (kr.x == kEmptyKey) return 0;
-      h = (h + 1) & m;
+      h = probe_next(h, cap);
     }
     return 0;
   }
@@ -237,11 +297,11 @@ __global__ void k_b_admit(BatchArgs a, const Admit* adm, int count) {
     S.fb[1] = ad.fb1;
     S.support = ad.support;
     S.touched = ad.touched;
-    S.mask = ad.mask;
+    S.tcap = ad.tcap;
     S.list_cap = ad.list_cap;
     S.fb[0][0] = ad.seed;
     S.touched[0] = ad.seed;
-    VRec* rec = St::insert(S, ad.seed);  // a fresh (cleared) table: never full
+    VRec* rec = St::insert(a, S, ad.seed);  // a fresh (cleared) table: never full
     if (rec) rec->r = 1.0; else S.fault = 1;
     S.t_admit = (long long)wall_clock64();
     S.t_done = 0;
@@ -360,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void k_b_self(BatchArgs a) {
         int32_t d = 0;
         if (rp) {
           rho = rp->r;
-          d = St::deg_hot(a, S, v).x;
+          d = St::deg_rec(a, v, rp);
           double* pv = St::pp(S, v, rp);
           const double pold = *pv;
           *pv = pold + S.cs * rho;
@@ -461,12 +521,12 @@ __device__ void b_flush_hot(const BatchArgs& a, int hs, double* s_hacc, int* fau
   __syncthreads();
   if (hs >= 0) {
     const Slot& S = a.slots[hs];
-    for (int j = threadIdx.x; j < kHot; j += kBlock) {
+    for (int j = threadIdx.x; j < kHotB; j += kBlock) {
       const double sum = s_hacc[j];
       if (sum != 0.0) {
         s_hacc[j] = 0.0;
         const int32_t w = a.hot_ids[j];
-        VRec* rec = St::insert(S, w);
+        VRec* rec = St::insert(a, S, w);
         if (!rec) {
           *fault = 1;
           continue;
@@ -500,13 +560,13 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
   __shared__ unsigned long long s_efn[kSlotRange];
   __shared__ TabView s_view[kSlotRange];
   __shared__ double s_eps[kSlotRange];
-  __shared__ double s_hacc[kHot];
+  __shared__ double s_hacc[kHotB];
   int hs = -1;  // slot whose hot sums s_hacc holds
   const int per = (ntiles + gridDim.x - 1) / gridDim.x;
   const int tb = xcd_block(blockIdx.x, gridDim.x) * per;
   const int te = tb + per < ntiles ? tb + per : ntiles;
   if (tb >= te) return;  // no tiles for this workgroup
-  for (int j = threadIdx.x; j < kHot; j += kBlock) s_hacc[j] = 0.0;
+  for (int j = threadIdx.x; j < kHotB; j += kBlock) s_hacc[j] = 0.0;
   __syncthreads();
 
   for (int tile = tb; tile < te; tile++) {
@@ -530,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
     const int rr = range < kSlotRange ? range : kSlotRange;
     for (int j = threadIdx.x; j < rr; j += kBlock) {
       const Slot& S = a.slots[qlo + j];
-      s_view[j] = TabView{S.tab, S.tp, S.mask};
+      s_view[j] = TabView{S.tab, S.tcap};
       s_eps[j] = S.eps;
     }
     for (int j = threadIdx.x; j < cnt; j += kBlock) {
@@ -564,53 +624,79 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
         q[k] = s_slot[lo];
       }
     }
-    int2 dr[kEdgesPerThread];
-#pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) {
-      dr[k] = make_int2(0, 0);
-      if (w[k] >= 0) {
-        const int j = q[k] - qlo;
-        const Slot& S = a.slots[q[k]];
-        const TabView v = j < kSlotRange ? s_view[j] : TabView{S.tab, S.tp, S.mask};
-        dr[k] = St::deg_hot_v(a, v, w[k]);
-      }
-    }
-    // hot destinations of the current slot: combined in LDS; the others:
-    // first probe of every edge, then resolution, then the atomics
+    // first load of every edge (dense: the record's {d, hot code} word;
+    // compact: the {key, tag} word at the home position), then resolution
+    // (compact: probing on or claiming a record); hot destinations of the
+    // current slot are then combined in LDS, the others take the atomics
     TabView tv[kEdgesPerThread];
     uint32_t hp[kEdgesPerThread];
-    int32_t k0[kEdgesPerThread];
+    unsigned long long k0[kEdgesPerThread];
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       if (w[k] < 0) continue;
-      const int hj = -dr[k].y - 1;
-      if (q[k] == hs && hj >= 0 && hj < kHot) {
-        atomicAdd(&s_hacc[hj], cf[k]);
-        w[k] = -1;
-        continue;
-      }
       const int j = q[k] - qlo;
       const Slot& S = a.slots[q[k]];
-      tv[k] = j < kSlotRange ? s_view[j] : TabView{S.tab, S.tp, S.mask};
-      k0[k] = St::probe_start(tv[k], w[k], &hp[k]);
+      tv[k] = j < kSlotRange ? s_view[j] : TabView{S.tab, S.tcap};
+      k0[k] = St::probe_start(a, tv[k], w[k], &hp[k]);
     }
     VRec* rec[kEdgesPerThread];
+    int32_t dw[kEdgesPerThread];
+    double old[kEdgesPerThread];
+    bool pend[kEdgesPerThread];
 #pragma unroll
     for (int k = 0; k < kEdgesPerThread; k++) {
       rec[k] = nullptr;
-      if (w[k] < 0) continue;
-      rec[k] = St::probe_finish(tv[k], w[k], hp[k], k0[k]);
+      dw[k] = 0;
+      old[k] = 0.0;
+      pend[k] = w[k] >= 0;
+    }
+    // resolve edge k's first word into its record, then the LDS sum (hot
+    // destination of the current slot) or the atomic on r
+    auto settle = [&](int k) {
+      pend[k] = false;
+      int32_t hj;
+      rec[k] = St::probe_finish(a, tv[k], w[k], hp[k], k0[k], &dw[k], &hj);
       if (!rec[k]) {
         c->fault = 1;  // full table: the host sizes tables so that this cannot happen
         w[k] = -1;
+        return;
+      }
+      if (hj >= 0) {
+        if (q[k] == hs && hj < kHotB) {
+          atomicAdd(&s_hacc[hj], cf[k]);
+          w[k] = -1;
+          return;
+        }
+        dw[k] = St::hot_deg(a, w[k], dw[k]);
+      }
+      old[k] = unsafeAtomicAdd(&rec[k]->r, cf[k]);
+    };
+    if constexpr (St::kCompact) {
+      // destinations found at home: their atomics go out at once; then those
+      // whose home record was free: their tags and every claim of the thread
+      // in flight together (a lost claim leaves the record's current word for
+      // the resolution below to probe on from)
+#pragma unroll
+      for (int k = 0; k < kEdgesPerThread; k++)
+        if (pend[k] && (int32_t)(uint32_t)k0[k] == w[k]) settle(k);
+      int32_t tg[kEdgesPerThread];
+#pragma unroll
+      for (int k = 0; k < kEdgesPerThread; k++) {
+        tg[k] = 0;
+        if (pend[k] && (int32_t)(uint32_t)k0[k] == kEmptyKey)
+          tg[k] = CompactState::tag_of(a.gdh[w[k]]);
+      }
+#pragma unroll
+      for (int k = 0; k < kEdgesPerThread; k++) {
+        if (tg[k] >= 0) continue;
+        const unsigned long long want = CompactState::word(w[k], tg[k]);
+        const unsigned long long got = atomicCAS(CompactState::kw(tv[k], hp[k]), k0[k], want);
+        k0[k] = got == k0[k] ? want : got;
       }
     }
-    double old[kEdgesPerThread];
 #pragma unroll
-    for (int k = 0; k < kEdgesPerThread; k++) {
-      old[k] = 0.0;
-      if (w[k] >= 0) old[k] = unsafeAtomicAdd(&rec[k]->r, cf[k]);
-    }
+    for (int k = 0; k < kEdgesPerThread; k++)
+      if (pend[k]) settle(k);
     // decisions: rank within (slot, list) from LDS counters, or a direct
     // global reservation when the tile spans more slots than the LDS range
     int rfn[kEdgesPerThread], rtv[kEdgesPerThread];
@@ -621,14 +707,14 @@ __global__ __launch_bounds__(kBlock) void k_b_scatter(BatchArgs a) {
       if (w[k] < 0) continue;
       const int j = q[k] - qlo;
       if (j < kSlotRange) {
-        const double thr = s_eps[j] * (double)dr[k].x;
+        const double thr = s_eps[j] * (double)dw[k];
         if (old[k] < thr && old[k] + cf[k] >= thr) {
           rfn[k] = atomicAdd(&s_cfn[j], 1);
-          atomicAdd(&s_efn[j], (unsigned long long)dr[k].x);
+          atomicAdd(&s_efn[j], (unsigned long long)dw[k]);
         }
         if (__double_as_longlong(old[k]) == 0) rtv[k] = atomicAdd(&s_ctv[j], 1);
       } else {
-        b_decide_direct(a, q[k], w[k], dr[k].x, old[k], cf[k], &c->fault);
+        b_decide_direct(a, q[k], w[k], dw[k], old[k], cf[k], &c->fault);
       }
     }
     __syncthreads();
@@ -682,52 +768,69 @@ __global__ __launch_bounds__(kMaxSlots) void k_b_round_end(BatchArgs a) {
 
 constexpr int kMaxClearJobs = 2 * kMaxSlots;  // admissions + growths of one step
 
+// Tables are processed in runs of 256 records (4 per lane of a wave):
+// capacities are multiples of kScanBlock records, so a run of the
+// concatenated tables lies in one table and one search finds it.
+constexpr int kTabRun = 4 * 64;
+static_assert(kScanBlock % kTabRun == 0, "table runs lie in one table");
+
 // Clear every record (key kEmptyKey, r 0, rank 0) and p of each job's
-// block; x runs over the records of all jobs end to end.
+// block; the runs cover the records of all jobs end to end.
 __global__ __launch_bounds__(kBlock) void k_c_clear(const ClearJob* jobs, int count,
                                                     long long total) {
   __shared__ long long s_off[kMaxClearJobs];
   for (int j = threadIdx.x; j < count; j += kBlock) s_off[j] = jobs[j].off;
   __syncthreads();
-  for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < total;
-       x += (long long)gridDim.x * kBlock) {
-    const int j = seg_of(s_off, count, x);
+  const long long nrun = total / kTabRun;
+  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  VRec r;
+  r.r = 0.0;
+  r.deg = kEmptyKey;
+  r.rank = 0;
+  for (long long wr = (long long)blockIdx.x * (kBlock / 64) + PLC_WID; wr < nrun; wr += nw) {
+    const long long x0 = wr * kTabRun;
+    const int j = seg_of(s_off, count, x0);
     const ClearJob& J = jobs[j];
-    const long long i = x - s_off[j];
-    if (i >= J.cap) continue;
-    VRec r;
-    r.r = 0.0;
-    r.deg = kEmptyKey;
-    r.rank = 0;
-    J.tab[i] = r;
-    J.tp[i] = 0.0;
+    const long long i0 = x0 - s_off[j];
+    if (i0 + kTabRun > J.cap) continue;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      J.tab[i0 + k * 64 + PLC_LANE] = r;
+      J.tp[i0 + k * 64 + PLC_LANE] = 0.0;
+    }
   }
 }
 
 // Re-insert every record of the growing tables into their new (cleared)
-// tables.  x runs over the old records of all growing tables end to end.
+// tables; the runs cover the old records of all growing tables end to end.
 __global__ __launch_bounds__(kBlock) void k_c_rehash(BatchArgs a, const Grow* gr, int count,
                                                      long long total) {
   __shared__ long long s_off[kMaxSlots];
   for (int j = threadIdx.x; j < count; j += kBlock) s_off[j] = gr[j].rec_off;
   __syncthreads();
-  for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < total;
-       x += (long long)gridDim.x * kBlock) {
-    const int j = seg_of(s_off, count, x);
+  const long long nrun = total / kTabRun;
+  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  for (long long wr = (long long)blockIdx.x * (kBlock / 64) + PLC_WID; wr < nrun; wr += nw) {
+    const long long x0 = wr * kTabRun;
+    const int j = seg_of(s_off, count, x0);
     const Grow& G = gr[j];
     const Slot& S = a.slots[G.slot];  // still the old table
-    const long long i = x - s_off[j];
-    if (i > G.old_mask) continue;
-    const VRec rec = S.tab[i];
-    if (rec.deg == kEmptyKey) continue;
-    VRec* dst = CompactState::insert_v(TabView{G.tab, G.tp, G.new_mask}, rec.deg);
-    if (!dst) {
-      a.ctl->fault = 1;
-      continue;
+    const long long i0 = x0 - s_off[j];
+    if (i0 + kTabRun > G.old_cap) continue;
+    VRec rec[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) rec[k] = S.tab[i0 + k * 64 + PLC_LANE];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      if (rec[k].deg == kEmptyKey) continue;
+      VRec* dst = CompactState::insert_tag(a, TabView{G.tab, G.new_cap}, rec[k].deg, rec[k].rank);
+      if (!dst) {
+        a.ctl->fault = 1;
+        continue;
+      }
+      dst->r = rec[k].r;  // (the key and its tag went in with the claim)
+      G.tp[dst - G.tab] = S.tp[i0 + k * 64 + PLC_LANE];
     }
-    dst->r = rec.r;
-    dst->rank = rec.rank;
-    G.tp[dst - G.tab] = S.tp[i];
   }
 }
 
@@ -772,7 +875,7 @@ __global__ void k_c_commit(BatchArgs a, const Grow* gr, int count) {
     S.fb[1] = G.fb1;
     S.support = G.support;
     S.touched = G.touched;
-    S.mask = G.new_mask;
+    S.tcap = G.new_cap;
     S.list_cap = G.list_cap;
     S.hold = 0;
   }
@@ -914,7 +1017,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
   __shared__ int32_t s_cnt[kEdgeTile + 1];
   __shared__ int32_t s_own[kEdgeTile + 1];
   __shared__ const VRec* s_tab[kEdgeTile + 1];
-  __shared__ int32_t s_mask[kEdgeTile + 1];
+  __shared__ int32_t s_tcap[kEdgeTile + 1];
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long long e0 = (long long)tile * kEdgeTile;
     const long long e1 = e0 + kEdgeTile < E ? e0 + kEdgeTile : E;
@@ -934,7 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
       s_own[j] = (int32_t)(k - sg.elem_off + 1);
       const Slot& S = a.slots[sg.slot];
       s_tab[j] = S.tab;
-      s_mask[j] = S.mask;
+      s_tcap[j] = S.tcap;
       s_cnt[j] = 0;
     }
     __syncthreads();
@@ -952,7 +1055,7 @@ __global__ __launch_bounds__(kBlock) void k_sw_count(BatchArgs a) {
           if (s_start[mid] <= rel) lo = mid; else hi = mid - 1;
         }
         const int32_t w = a.nbr[s_row[lo] + (rel - s_start[lo])];
-        rw[kk] = St::rank_at(s_tab[lo], s_mask[lo], w);
+        rw[kk] = St::rank_at(s_tab[lo], s_tcap[lo], w);
         own[kk] = lo;
       }
     }
@@ -1093,48 +1196,52 @@ __global__ __launch_bounds__(kBlock) void k_sw_finish(BatchArgs a) {
 
 // Compact layout: gather the nonzeros of r of every swept query by scanning
 // its table (the block returns to the arena afterwards, so nothing is
-// reset).  Tables are powers of two of at least kScanBlock records, so every
+// reset).  Table capacities are multiples of kScanBlock records, so every
 // kScanBlock-record chunk of the concatenated tables lies in one table.
+// Each wave takes such a chunk (16 records per lane, in four rounds of
+// coalesced loads), counts its nonzeros with ballots and reserves their
+// output positions with one atomic on the slot's count; without an r output
+// (PLC_QF_NO_RESIDUAL) it only counts.
 __global__ __launch_bounds__(kBlock) void k_sw_gather(BatchArgs a) {
   BatchCtl* c = a.ctl;
   const int nseg = c->sw_nseg;
+  constexpr int kPer = kScanBlock / 64;  // records per lane
   const long long nchunk = c->sw_touch_total / kScanBlock;
   __shared__ long long s_toff[kMaxSlots];
-  __shared__ long long sh[kBlock / 64 + 1];
-  __shared__ long long s_base;
-  __shared__ int s_seg;
   for (int j = threadIdx.x; j < nseg; j += kBlock) s_toff[j] = a.segs[j].touch_off;
   __syncthreads();
-  for (long long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+  const long long nw = (long long)gridDim.x * (kBlock / 64);
+  for (long long ch = (long long)blockIdx.x * (kBlock / 64) + PLC_WID; ch < nchunk; ch += nw) {
     const long long x0 = ch * kScanBlock;
-    if (threadIdx.x == 0) s_seg = seg_of(s_toff, nseg, x0);
-    __syncthreads();
-    const SweepSeg& sg = a.segs[s_seg];
+    const int sgi = seg_of(s_toff, nseg, x0);
+    const SweepSeg& sg = a.segs[sgi];
     Slot& S = a.slots[sg.slot];
-    const long long i0 = x0 - s_toff[s_seg];
-    int32_t vk[kScanItems];
-    double rk[kScanItems];
-    long long cnt = 0;
+    const VRec* tab = S.tab + (x0 - s_toff[sgi]);
+    int32_t vk[kPer];
+    double rk[kPer];
+    int tot = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-      const VRec rec = S.tab[i0 + k * kBlock + threadIdx.x];
+    for (int k = 0; k < kPer; k++) {
+      const VRec rec = tab[k * 64 + PLC_LANE];
       vk[k] = rec.deg;
       rk[k] = rec.deg != kEmptyKey ? rec.r : 0.0;
-      cnt += rk[k] != 0.0;
+      tot += __popcll(__ballot(rk[k] != 0.0));
     }
-    long long tot;
-    long long pos = block_excl_scan<kBlock>(cnt, &tot, sh);
-    if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&S.rnnz, (int)tot) : 0;
-    __syncthreads();
-    pos += s_base;
+    if (tot == 0) continue;
+    int base = 0;
+    if (PLC_LANE == 0) base = atomicAdd(&S.rnnz, tot);
+    if (!sg.out_rid) continue;
+    base = __shfl(base, 0);
 #pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-      if (rk[k] == 0.0) continue;
-      if (pos >= S.touched_cnt) c->fault = 1;
-      else if (sg.out_rid) { sg.out_rid[pos] = vk[k]; sg.out_rval[pos] = rk[k]; }
-      pos++;
+    for (int k = 0; k < kPer; k++) {
+      const unsigned long long m = __ballot(rk[k] != 0.0);
+      if (rk[k] != 0.0) {
+        const long long pos = (long long)base + __popcll(m & lanemask_lt());
+        if (pos >= S.touched_cnt) c->fault = 1;
+        else { sg.out_rid[pos] = vk[k]; sg.out_rval[pos] = rk[k]; }
+      }
+      base += __popcll(m);
     }
-    __syncthreads();
   }
 }
 

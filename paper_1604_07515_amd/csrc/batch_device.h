@@ -16,8 +16,10 @@
 //           capacity mask+1 (a power of 2, linear probing, at most half
 //           full), allocated from the arena at admission and grown between
 //           rounds, so a query holds memory in proportion to the vertices it
-//           touched rather than to n.  d(v) and the hot code come from a
-//           graph-wide array.
+//           touched rather than to n.  d(v) and the hot code sit in the
+//           record beside the key (claimed with it in one 64-bit
+//           compare-and-swap, from a graph-wide array), so the scatter's
+//           probe returns them.
 // Round buffers (per-entry coefficient, row, edge start, slot) are shared by
 // all slots: a round's entries are the concatenation of the scheduled slots'
 // frontiers, in slot order.
@@ -59,7 +61,7 @@ struct __align__(64) Slot {
   int32_t* fb[2];
   int32_t* support;
   int32_t* touched;
-  int32_t mask;             // compact: table capacity - 1
+  int32_t tcap;             // compact: table capacity (records)
   int32_t list_cap;         // capacity of each list
   // constant-rate clock (wall_clock64) at admission and at the sweep's argmin
   long long t_admit, t_done;
@@ -137,7 +139,7 @@ struct BatchArgs {
 struct __align__(16) Admit {
   int32_t slot, seed, rule, max_rounds;
   double alpha, eps;
-  int32_t seed_deg, mask, list_cap, pad;
+  int32_t seed_deg, tcap, list_cap, pad;
   VRec* tab;
   double* tp;
   int32_t* fb0;
@@ -149,7 +151,7 @@ struct __align__(16) Admit {
 // Compact layout: a table that moves to a larger block (host-written).
 struct __align__(16) Grow {
   int32_t slot;
-  int32_t old_mask, new_mask, list_cap;
+  int32_t old_cap, new_cap, list_cap;
   long long rec_off;        // first record of this table in the flattened rehash index
   long long list_off;       // first list entry of this slot in the flattened copy index
   int32_t par;              // current frontier buffer

@@ -113,6 +113,8 @@ struct BatchEngine {
   // compact layout: per slot, the running query's block and table capacity
   std::vector<void*> qblock;
   std::vector<int64_t> qcap;
+  std::vector<int32_t> qgrows;       // growths of the slot's table
+  std::vector<int64_t> qbound;       // touched bound of the slot's query
   std::vector<int> hold;             // hold flag last sent to the device
   std::vector<char> fresh;           // admitted this step: slots_h not read back yet
   plc::Grow* grow_h = nullptr;       // pinned grow records
@@ -1251,25 +1253,40 @@ static size_t batch_fixed_bytes(const plc_graph* g, int B) {
   return b;
 }
 
-// Compact layout.  A table of capacity cap (a power of 2, at least 1024) is
-// sized so that before a round at most half of it is occupied and the
-// round's worst case (occupancy + one new key per edge of the frontier)
-// stays within 3/4 of it: linear probing then stays short even in the rare
-// round that adds as many new keys as it has edges, and a table never fills.
-// A query block holds the records (16 B), p (8 B) and four lists of
-// 3/4 cap vertex ids (12 B): 36 B per record.
+// Compact layout.  A table's capacity is a multiple of kScanBlock records
+// (the r gather scans tables in kScanBlock chunks) sized so that before a
+// round at most half of it is occupied and the round's worst case
+// (occupancy + one new key per edge of the frontier, "worst") stays within
+// 3/4 of it: linear probing then stays short even in the rounds that add
+// nearly as many new keys as they have edges (the first rounds of a query),
+// and a table never fills.  A query block holds the records (16 B), p (8 B)
+// and four lists of 3/4 cap vertex ids (12 B): 36 B per record.
 static int64_t table_cap_for(const plc_graph* g, int64_t occupied, int64_t worst) {
   occupied = std::min<int64_t>(std::max<int64_t>(occupied, 1), g->n);
   worst = std::min<int64_t>(std::max<int64_t>(worst, occupied), g->n);
-  int64_t cap = plc::kScanBlock;  // the r gather scans tables in kScanBlock chunks
-  while (cap < 2 * occupied || 4 * worst > 3 * cap) cap <<= 1;
-  return cap;
+  const int64_t need = std::max<int64_t>(2 * occupied, (4 * worst + 2) / 3);
+  return (need + plc::kScanBlock - 1) / plc::kScanBlock * plc::kScanBlock;
 }
 static bool table_needs_growth(int64_t cap, int64_t occupied, int64_t worst) {
   return 2 * occupied > cap || 4 * worst > 3 * cap;
 }
 static size_t table_block_bytes(int64_t cap) { return 36 * (size_t)cap; }
 static int64_t table_list_cap(int64_t cap) { return cap / 4 * 3; }
+// growth: at least twice the current capacity (few rehashes), but never
+// beyond the table that the query's touched bound needs
+static int64_t table_grown_cap(const plc_graph* g, int64_t cap, int64_t occupied, int64_t worst,
+                               int64_t bound) {
+  return std::max<int64_t>(table_cap_for(g, occupied, worst),
+                           std::min<int64_t>(2 * cap, table_cap_for(g, bound, bound)));
+}
+// Touched bound of a query (the push's work bound, Sec. 3.3): every push but
+// the seed's moves at least alpha' eps d(v) of the unit mass into p, so at
+// most 1 + d(seed) + 1/(alpha' eps) vertices are touched (and at most n).
+static int64_t touched_bound(const plc_graph* g, const plc_query& q) {
+  const double ap = q.rule == PLC_RULE_OPT ? 2.0 * q.alpha / (1.0 + q.alpha) : q.alpha;
+  const double b = 1.0 + (double)g->deg[q.seed] + std::floor(1.0 / (ap * q.eps));
+  return (int64_t)std::min(b, (double)g->n);
+}
 
 // Arena kept free for result blocks when tables are taken (admission) or
 // grown (half of it).
@@ -1356,6 +1373,8 @@ static plc_status batch_create(plc_ctx* ctx, plc_graph* g, int B) {
   E->qbucket.assign(B, 0);
   E->qflags.assign(B, 0u);
   E->qcap.assign(B, 0);
+  E->qgrows.assign(B, 0);
+  E->qbound.assign(B, 0);
   E->hold.assign(B, 0);
   E->fresh.assign(B, 0);
   if (hipHostMalloc(reinterpret_cast<void**>(&E->slots_h), sizeof(plc::Slot) * B,
@@ -1488,13 +1507,12 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     plc::Admit& ad = E.adm_h[nadm];
     if (E.compact) {
       int64_t expect = 1;
+      const int64_t bound = touched_bound(g, qq);
       auto hint = E.touched_hint.find(hint_bucket(qq));
-      if (hint != E.touched_hint.end()) {
-        // never above this query's own touched bound (plc_query_bytes_estimate)
-        const double ap = qq.rule == PLC_RULE_OPT ? 2.0 * qq.alpha / (1.0 + qq.alpha) : qq.alpha;
-        const double bound = 1.0 + g->deg[qq.seed] + std::floor(1.0 / (ap * qq.eps));
-        expect = (int64_t)std::min(hint->second, std::min(bound, (double)n));
-      }
+      // never above this query's own touched bound (plc_query_bytes_estimate)
+      if (hint != E.touched_hint.end())
+        expect = (int64_t)std::min(hint->second, (double)bound);
+      E.qbound[q] = bound;
       // the hinted size if the arena has room for it, else the seed's first
       // round only (the table then grows like any other)
       const int64_t first = table_cap_for(g, 1, 1 + (int64_t)g->deg[qq.seed]);
@@ -1516,7 +1534,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       ad.fb1 = lists + L;
       ad.support = lists + 2 * L;
       ad.touched = lists + 3 * L;
-      ad.mask = (int32_t)(cap - 1);
+      ad.tcap = (int32_t)cap;
       ad.list_cap = (int32_t)L;
       plc::ClearJob& J = E.clear_h[njobs++];
       J.tab = ad.tab;
@@ -1526,6 +1544,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       clear_total += cap;
       E.qblock[q] = blk;
       E.qcap[q] = cap;
+      E.qgrows[q] = 0;
       E.qbucket[q] = hint_bucket(qq);
     } else {
       ad.tab = a.vr + (int64_t)q * n;
@@ -1534,7 +1553,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       ad.fb1 = E.d_fbuf + (2 * (int64_t)q + 1) * n;
       ad.support = E.d_support + (int64_t)q * n;
       ad.touched = E.d_touched + (int64_t)q * n;
-      ad.mask = 0;
+      ad.tcap = 0;
       ad.list_cap = (int32_t)n;
     }
     E.queue.pop_front();
@@ -1566,7 +1585,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       const plc::Slot& S = E.slots_h[q];
       if (S.status != plc::SL_PUSH) continue;
       const int64_t occ = S.touched_cnt;
-      const int64_t worst = std::min<int64_t>(n, occ + S.edge_next[S.par]);
+      const int64_t worst = std::min<int64_t>(E.qbound[q], occ + S.edge_next[S.par]);
       if (!table_needs_growth(E.qcap[q], occ, worst)) {
         if (E.hold[q]) {
           E.holds_h[nhold++] = q;
@@ -1574,7 +1593,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
         }
         continue;
       }
-      const int64_t cap = std::max<int64_t>(table_cap_for(g, occ, worst), 2 * E.qcap[q]);
+      const int64_t cap = table_grown_cap(g, E.qcap[q], occ, worst, E.qbound[q]);
       const size_t bytes = table_block_bytes(cap);
       void* blk = ctx->arena.free_bytes() >= bytes + result_headroom(ctx) / 2
                       ? ctx->arena.alloc(bytes) : nullptr;
@@ -1589,8 +1608,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       const int64_t L = table_list_cap(cap);
       plc::Grow& G = E.grow_h[ngrow++];
       G.slot = q;
-      G.old_mask = (int32_t)(E.qcap[q] - 1);
-      G.new_mask = (int32_t)(cap - 1);
+      G.old_cap = (int32_t)E.qcap[q];
+      G.new_cap = (int32_t)cap;
       G.list_cap = (int32_t)L;
       G.rec_off = total_old;
       G.list_off = total_list;
@@ -1616,6 +1635,7 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
       old_blocks.push_back(E.qblock[q]);
       E.qblock[q] = blk;
       E.qcap[q] = cap;
+      E.qgrows[q]++;
       E.hold[q] = 0;  // k_c_move_lists clears the device flag
     }
     if (nhold > 0) {
@@ -1830,6 +1850,8 @@ static plc_status batch_step(plc_ctx* ctx, plc_graph* g, int32_t* in_flight, uin
     info.device_ns =
         S.t_done > S.t_admit ? (int64_t)((double)(S.t_done - S.t_admit) * ctx->clock_ns) : 0;
     info.flags = E.qflags[q];
+    info.table_grows = E.compact ? E.qgrows[q] : 0;
+    info.table_cap = E.compact ? E.qcap[q] : 0;
     if (S.fault) {
       ctx->broken = true;
       return PLC_E_HIP;
@@ -1899,7 +1921,7 @@ extern "C" size_t plc_query_bytes_estimate(const plc_graph* g, const plc_query* 
   const double w = 1.0 / (ap * q->eps);  // bound on the pushed volume outside the seed
   const double nn = (double)g->n;
   const double sup = std::min(nn, 1.0 + std::floor(w));
-  const double tch = std::min(nn, 1.0 + (double)g->deg[q->seed] + std::floor(w));
+  const double tch = (double)touched_bound(g, *q);
   // result block: support ids + p, nonzero ids + values of r, each part 256-B aligned
   const double res = 12.0 * sup + 12.0 * tch + 4 * 256.0;
   const size_t state = g->ctx && g->ctx->opt.batch_state == PLC_STATE_COMPACT

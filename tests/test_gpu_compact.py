@@ -158,7 +158,9 @@ def test_compact_first_table_does_not_fit(plc):
     cannot be admitted and, with nothing else running, fails at once with
     PLC_E_NOMEM."""
     g = synth.rmat(20, 8, seed=5)
-    c, hg = tight_context(plc, g, 4, 2)  # the hub's first table needs 2.25 MiB
+    # the hub's first table: 4/3 (d + 1) = 52948 records rounded up to 53248,
+    # 36 B each (1.83 MiB)
+    c, hg = tight_context(plc, g, 4, 1)
     with c:
         seed = int(np.argmax(g.deg))
         ids, infos = c.run_batched(hg, [seed], 0.01, 1e-4, check=False)
