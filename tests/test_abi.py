@@ -53,3 +53,41 @@ def test_product_package_does_not_touch_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle.c" not in text and "liboracle" not in text, f
+
+
+STRUCTS = ("plc_options", "plc_query", "plc_graph_info", "plc_result_info", "plc_tune",
+           "plc_kernel_time")
+
+
+def _c_layout(tmp_path):
+    """Size and field offsets of every plc.h struct, as a C compiler lays them out."""
+    import shutil
+    import subprocess
+    import paper_1604_07515_amd as plc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "plc.h"', "int main(void) {"]
+    for s in STRUCTS:
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (s, s))
+        for f, _ in getattr(plc, s)._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (s, f, s, f))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of the C structs have the header's size and field offsets."""
+    import paper_1604_07515_amd as plc
+    c = _c_layout(tmp_path)
+    for s in STRUCTS:
+        cls = getattr(plc, s)
+        assert c[(s, "size")] == ctypes.sizeof(cls), s
+        for f, _ in cls._fields_:
+            assert c[(s, f)] == getattr(cls, f).offset, (s, f)
