@@ -221,11 +221,12 @@ def check_properties(g, res, eps, with_r=True):
     assert info["phi"] == info["cut"] / min(info["vol"], g.arcs - info["vol"])
 
 
-def check_nibble(g, res, orc) -> dict:
+def check_nibble(g, res, orc, rtol=RTOL) -> dict:
     """GPU Nibble result against the oracle's (oracle.nibble): the returned
-    vector within RTOL with the same support, steps, pushes and edges
-    exactly, no residual reported, and the sweep as for PR-Nibble; near
-    threshold decisions (oracle gap < TIE) relax the first part."""
+    vector within rtol (RTOL, or a per-vertex array) with the same support,
+    steps, pushes and edges exactly, no residual reported, and the sweep as
+    for PR-Nibble; near threshold decisions (oracle gap < TIE) relax the
+    first part."""
     info = res.info
     p = res.dense_p(g.n)
     assert info["status"] == 0 and info["r_nnz"] == 0
@@ -236,7 +237,8 @@ def check_nibble(g, res, orc) -> dict:
         sup = orc.p > 0
         assert np.array_equal(sup, p > 0), "support"
         err = np.abs(p[sup] - orc.p[sup]) / orc.p[sup]
-        assert err.max(initial=0) <= RTOL, ("p", err.max())
+        tol = rtol[sup] if np.ndim(rtol) else rtol
+        assert np.all(err <= tol), ("p", err.max(), float(np.max(err / tol)))
     tie_sweep = check_sweep(g, res, orc.p, p, tie_push)
     return {"tie_push": tie_push, "tie_sweep": tie_sweep, "steps": info["rounds"],
             "support": info["support"]}

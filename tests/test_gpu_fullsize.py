@@ -30,7 +30,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_nibble, check_properties, check_query, check_same
+from parity import RTOL, check_nibble, check_properties, check_query, check_same
 
 pytestmark = pytest.mark.gpu
 
@@ -161,7 +161,14 @@ def test_serving_rmat24_bench_shapes(plc):
 def test_nibble_support_above_2_21(plc, g22):
     """Nibble (Sec. 3.2) from vertex 0 (the top hub) with T = 2 and eps
     1e-300 (nothing truncated): p_2 covers every vertex within two hops,
-    2,208,937 of them, and the sweep over it is checked against the oracle."""
+    2,208,937 of them, and the sweep over it is checked against the oracle.
+
+    Tolerance: p_1 has one addend per vertex, so both sides form the
+    addends of step 2 bit for bit and differ only in the order of the sums:
+    p_2[w] adds at most d(w) + 1 positive terms, and two orders of k positive
+    terms differ by at most 2 (k - 1) u relative (u = 2^-53), which passes
+    1e-12 once k exceeds about 4500.  Each vertex is held to the larger of
+    1e-12 and 2 d(w) u; the test reports how many needed more than 1e-12."""
     g = g22
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
     try:
@@ -170,7 +177,15 @@ def test_nibble_support_above_2_21(plc, g22):
         say("nibble 2^22 hub: support", info["support"], "kstar", info["kstar"])
         assert info["support"] > (1 << 21)
         orc = oracle.nibble(g.off, g.nbr, 0, 1e-300, 2)
-        rep = check_nibble(g, ctx.result(qid, release=True), orc)
+        res = ctx.result(qid, release=True)
+        tol = np.maximum(RTOL, 2.0 * g.deg.astype(np.float64) * 2.0 ** -53)
+        p = res.dense_p(g.n)
+        sup = orc.p > 0
+        err = np.abs(p[sup] - orc.p[sup]) / orc.p[sup]
+        say("nibble p: max rel err %.3g, %d of %d vertices above 1e-12 (max degree there %d)" % (
+            err.max(), int((err > RTOL).sum()), int(sup.sum()),
+            int(g.deg[np.flatnonzero(sup)[err > RTOL]].max(initial=0))))
+        rep = check_nibble(g, res, orc, rtol=tol)
         say("nibble report", rep)
     finally:
         ctx.close()
