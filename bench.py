@@ -166,8 +166,9 @@ def bench_plain(plc, synth, g, steps, warmup):
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
     tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
-    log("  plain launch shapes: self %d, scatter %d, sweep %d workgroups (%d tried)" % (
-        tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"], tune["candidates"]))
+    log("  plain launch shapes: self %d, scatter %d, sweep %d workgroups, binned rounds from %d "
+        "edges (%d tried)" % (tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"],
+                              tune["plain_bin_min_edges"], tune["candidates"]))
     sl = [int(s) for s in seeds]
 
     def step(lat, acc):
@@ -211,7 +212,8 @@ def bench_plain(plc, synth, g, steps, warmup):
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support",
                                                  "bin_rounds")},
         "kernels": tm, "roofline": roofline(tm, PLAIN_SCATTER),
-        "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep")},
+        "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep",
+                                               "plain_bin_min_edges")},
     }
 
 
@@ -532,7 +534,7 @@ def one_at_a_time(plc, g, seeds, alpha=0.01, eps=1e-7):
     import torch
     ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (256 << 20))
     hg = ctx.load_graph(g.off, g.nbr)
-    ctx.autotune(hg, seeds[:2], alpha, eps, plc.PLC_TUNE_PLAIN)
+    tune = ctx.autotune(hg, seeds[:2], alpha, eps, plc.PLC_TUNE_PLAIN)
     for s in seeds[:2]:
         ids, _ = ctx.run(hg, [s], alpha, eps)
         ctx.release(ids[0])
@@ -553,7 +555,8 @@ def one_at_a_time(plc, g, seeds, alpha=0.01, eps=1e-7):
                      "edges_per_s": acc["edges"] / el,
                      "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3},
                      "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds",
-                                                            "support")}}
+                                                            "support")},
+                     "bin_min_edges": tune["plain_bin_min_edges"]}
 
 
 def bench_grid3d(plc, synth, side=215, nq=8):

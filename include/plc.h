@@ -89,8 +89,10 @@ typedef struct plc_graph plc_graph;
  * least bin_min_edges edges: destination-binned -- the round's (neighbour,
  * entry) pairs are sorted by destination range, each range's contributions
  * are summed in LDS, and every touched r[w] gets one update.  Results agree
- * to the order of the additions.  bin_min_edges: 0 = 524288, < 0 = always
- * the atomic form.  (Graphs of more than 6,291,456 = 1536 x 4096 vertices
+ * to the order of the additions.  bin_min_edges: 0 = 524288, which
+ * plc_autotune may change per graph (it also tries four times that and no
+ * binning); > 0 = that threshold, kept by plc_autotune; < 0 = always the
+ * atomic form.  (Graphs of more than 6,291,456 = 1536 x 4096 vertices
  * always use the atomic form.)
  */
 typedef struct {
@@ -426,8 +428,11 @@ typedef struct {
   int32_t plain_self, plain_scatter, plain_sweep;   /* workgroups per launch */
   int32_t batch_self, batch_scatter, batch_sweep;
   double plain_ms, batch_ms;                        /* best sample wall time */
-  int32_t candidates;                               /* shapes tried */
-  int32_t reserved;
+  int32_t candidates;                               /* configurations tried */
+  /* plain path: rounds of at least this many edges take the binned scatter
+   * (-1: none).  Tuned among the default, four times it and none when
+   * plc_options.bin_min_edges is 0; otherwise the context's setting. */
+  int32_t plain_bin_min_edges;
 } plc_tune;
 
 plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* sample, int32_t count,

@@ -90,10 +90,10 @@ class plc_tune(C.Structure):
                 ("plain_sweep", C.c_int32), ("batch_self", C.c_int32),
                 ("batch_scatter", C.c_int32), ("batch_sweep", C.c_int32),
                 ("plain_ms", C.c_double), ("batch_ms", C.c_double),
-                ("candidates", C.c_int32), ("reserved", C.c_int32)]
+                ("candidates", C.c_int32), ("plain_bin_min_edges", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class plc_kernel_time(C.Structure):

@@ -61,8 +61,9 @@ struct EventPair {
 struct Captured {
   hipGraphExec_t exec = nullptr;
   int gs = -1, gc = -1, gw = -1, rounds = -1;
-  bool matches(int s, int c, int w, int r) const {
-    return exec && gs == s && gc == c && gw == w && rounds == r;
+  long long emin = 0;  // plain rounds: the binning threshold the graph's arguments carry
+  bool matches(int s, int c, int w, int r, long long e = 0) const {
+    return exec && gs == s && gc == c && gw == w && rounds == r && emin == e;
   }
 };
 
@@ -560,6 +561,9 @@ static hipError_t ev_pair(EventPair& e) {
 
 static int shape(int tuned, int dflt) { return tuned > 0 ? tuned : dflt; }
 
+// A binning threshold no round reaches.
+constexpr long long kBinOff = 1ll << 62;
+
 // Record body(stream) into c.exec.  On failure the context stops using graphs
 // (direct launches run the same kernels) and false is returned.
 template <class F>
@@ -589,12 +593,13 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   Captured& c = g->chunk_g[R];
-  if (c.matches(gs, gc, 0, R)) return &c;
+  if (c.matches(gs, gc, 0, R, g->args.bin_emin)) return &c;
   captured_free(c);
   c.gs = gs;
   c.gc = gc;
   c.gw = 0;
   c.rounds = R;
+  c.emin = g->args.bin_emin;
   const PlainArgs& a = g->args;
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
     hipError_t r;
@@ -2006,6 +2011,21 @@ extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* 
           if (ms < best) { best = ms; bs = gs; bc = gc; bw = gw; }
         }
     g->plain_self = bs; g->plain_scatter = bc; g->plain_sweep = bw;
+    // the binning threshold, unless the context fixed it: the default, four
+    // times it, or no binning (graphs whose large rounds already hit few
+    // lines per destination, such as ring-local ones, gain nothing from it)
+    if (g->args.nbins > 0 && ctx->opt.bin_min_edges == 0) {
+      const long long emins[] = {plc::kBinEmin, 4ll * plc::kBinEmin, kBinOff};
+      long long be = g->args.bin_emin;
+      for (long long e : emins) {
+        g->args.bin_emin = e;
+        st = tune_run(ctx, g, sample, count, false, &ms);
+        if (st != PLC_OK) { ctx->timing = timing; return st; }
+        tried++;
+        if (ms < best) { best = ms; be = e; }
+      }
+      g->args.bin_emin = be;
+    }
     best_plain = best;
   }
   if (which & PLC_TUNE_BATCH) {
@@ -2039,7 +2059,8 @@ extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* 
     out->plain_ms = best_plain;
     out->batch_ms = best_batch;
     out->candidates = tried;
-    out->reserved = 0;
+    out->plain_bin_min_edges =
+        g->args.nbins <= 0 || g->args.bin_emin >= kBinOff ? -1 : (int32_t)g->args.bin_emin;
   }
   return PLC_OK;
 }

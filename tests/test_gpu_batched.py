@@ -131,7 +131,9 @@ def test_autotune_keeps_results(setup, plc):
     seeds, alpha, eps, rules = mixed_queries(g, 24, seed=77)
     tune = ctx.autotune(hg, seeds[:8], alpha[:8], eps[:8],
                         plc.PLC_TUNE_PLAIN | plc.PLC_TUNE_BATCH)
-    assert tune["candidates"] == 5 * 4 * 2 + 2 * 4  # plain self x scatter x sweep, batched
+    # plain self x scatter x sweep, three binning thresholds, batched self x scatter
+    assert tune["candidates"] == 5 * 4 * 2 + 3 + 2 * 4
+    assert tune["plain_bin_min_edges"] in (524288, 4 * 524288, -1)
     for key in ("plain_self", "plain_scatter", "plain_sweep", "batch_self", "batch_scatter"):
         assert tune[key] > 0
     ids, _ = ctx.run_batched(hg, seeds, alpha, eps, rules)

@@ -3,7 +3,8 @@
 * plain: R-MAT 2^22 (ef 16), the benchmark's 16 uniform seeds, alpha 0.01,
   eps 1e-7, after the same autotuning, with the same query flags (no
   residual kept; p and the cluster copied back); every query against the
-  oracle, and the same queries with the residual kept.
+  oracle, and the same queries with the residual kept; then all again with
+  the binning threshold fixed at its default.
 * batched: the same graph, the benchmark's 256 queries (eps log-uniform in
   [1e-7, 1e-5], alpha in {0.01, 0.05}) through 256 slots after autotuning,
   with dense slots and with compact tables (8 GiB of tables, as timed); a
@@ -61,29 +62,40 @@ def strict_report(name, reports):
 
 
 def test_plain_rmat22_bench_shapes(plc, g22):
+    """The benchmark's plain queries in its launch configuration (autotuned
+    shapes and binning threshold), then again with the binning threshold
+    fixed at its default so that the binned rounds are checked at full size
+    whatever the tuner picked."""
     g = g22
     seeds = synth.uniform_seeds(g, 16, seed=2)
-    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
-    try:
-        hg = ctx.load_graph(g.off, g.nbr)
-        tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
-        say("plain 2^22 shapes", tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"])
-        sl = [int(s) for s in seeds]
-        ids, infos = ctx.run(hg, sl, 0.01, 1e-7, flags=plc.PLC_QF_NO_RESIDUAL)
-        ids_r, _ = ctx.run(hg, sl, 0.01, 1e-7)
-        reps = []
-        for i, (qid, qr) in enumerate(zip(ids, ids_r)):
-            say("plain 2^22 seed", sl[i], "binned rounds", infos[i]["bin_rounds"])
-            orc = oracle.prnibble(g.off, g.nbr, sl[i], 0.01, 1e-7)
-            res = ctx.result(qid, release=True)
-            reps.append((i, check_query(g, res, sl[i], 0.01, 1e-7, 0, orc=orc, with_r=False)))
-            res_r = ctx.result(qr, release=True)
-            check_query(g, res_r, sl[i], 0.01, 1e-7, 0, orc=orc)
-            check_same(g, res_r, res)
-        assert strict_report("plain 2^22", reps) == 16
-        assert sum(x["bin_rounds"] for x in infos) >= 16
-    finally:
-        ctx.close()
+    sl = [int(s) for s in seeds]
+    orcs = [oracle.prnibble(g.off, g.nbr, x, 0.01, 1e-7) for x in sl]
+    for fixed in (0, 524288):
+        ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20),
+                          bin_min_edges=fixed)
+        name = "plain 2^22 (%s)" % ("tuned" if fixed == 0 else "binned from 524288 edges")
+        try:
+            hg = ctx.load_graph(g.off, g.nbr)
+            tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
+            say(name, "shapes", tune["plain_self"], tune["plain_scatter"], tune["plain_sweep"],
+                "binning threshold", tune["plain_bin_min_edges"])
+            ids, infos = ctx.run(hg, sl, 0.01, 1e-7, flags=plc.PLC_QF_NO_RESIDUAL)
+            ids_r, _ = ctx.run(hg, sl, 0.01, 1e-7)
+            reps = []
+            for i, (qid, qr) in enumerate(zip(ids, ids_r)):
+                say(name, "seed", sl[i], "binned rounds", infos[i]["bin_rounds"])
+                res = ctx.result(qid, release=True)
+                reps.append((i, check_query(g, res, sl[i], 0.01, 1e-7, 0, orc=orcs[i],
+                                            with_r=False)))
+                res_r = ctx.result(qr, release=True)
+                check_query(g, res_r, sl[i], 0.01, 1e-7, 0, orc=orcs[i])
+                check_same(g, res_r, res)
+            assert strict_report(name, reps) == 16
+            if fixed:
+                assert tune["plain_bin_min_edges"] == fixed
+                assert sum(x["bin_rounds"] for x in infos) >= 16
+        finally:
+            ctx.close()
 
 
 def _batched(plc, g, compact):
