@@ -177,6 +177,10 @@ typedef struct {
    * query finished pushing */
   int32_t table_grows;
   int64_t table_cap;
+  /* plain path only: among bin_rounds, the rounds of at least half the
+   * graph's arcs, which the bins pull from their own vertices' arcs */
+  int32_t pull_rounds;
+  int32_t reserved;
 } plc_result_info;
 
 /* Status code to a static string. */

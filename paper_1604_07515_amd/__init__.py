@@ -75,7 +75,7 @@ class plc_result_info(C.Structure):
                 ("loop_edges", C.c_int64), ("host_ns", C.c_int64),
                 ("device_ns", C.c_int64), ("bin_rounds", C.c_int32), ("flags", C.c_uint32),
                 ("bin_edges", C.c_int64), ("pipelined", C.c_int32), ("table_grows", C.c_int32),
-                ("table_cap", C.c_int64)]
+                ("table_cap", C.c_int64), ("pull_rounds", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -515,9 +515,11 @@ def plain_arena_bytes(n: int, arcs: int) -> int:
     tiles = 4 * (arcs // 1024 + 2)
     scans = 3 * 16 * (n // 1024 + 2) + 24 * (n // 1024 + 2)
     # binned scatter (graphs up to 6,291,456 vertices): pairs (8 B per edge of the
-    # largest binned round, at most 2^23) and the per-chunk run table (2049
-    # ints per 2048-edge chunk)
-    chunks = (min(max(arcs, 1), 1 << 23) + 2047) // 2048 if n <= 1536 * 4096 else 0
-    bins = n // 16 + 12 * 2048 + chunks * (8 * 2048 + 4 * 2049) + 5 * 256
+    # largest binned round, at most 2^23), the per-chunk run table (2049
+    # ints per 2048-edge chunk) and the pull records (16 B per vertex)
+    binned = n <= 1536 * 4096
+    chunks = (min(max(arcs, 1), 1 << 23) + 2047) // 2048 if binned else 0
+    bins = n // 16 + 12 * 2048 + chunks * (8 * 2048 + 4 * 2049) + 7 * 256
+    bins += 16 * n if binned else 0
     return int(per_vertex * (n + 1) + per_arc * arcs + tiles + scans + bins + (64 << 20)
                + 8 * 1025 + 2048)

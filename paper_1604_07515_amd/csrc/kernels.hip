@@ -51,7 +51,9 @@ __global__ void k_graph_init(PlainArgs a) {
     a.vr[v] = rec;
     a.p[v] = 0.0;
     a.hk_r1[v] = 0.0;
+    if (a.pull) a.pull[v] = PullRec{0.0, 0u, 0};
   }
+  if (a.pull_epoch && blockIdx.x == 0 && threadIdx.x == 0) *a.pull_epoch = 1u;
 }
 
 __device__ __forceinline__ void reset_round_book(Ctl* c) {
@@ -62,6 +64,7 @@ __device__ __forceinline__ void reset_round_book(Ctl* c) {
   c->loop_pushes = 0;
   c->loop_edges = 0;
   c->bin_rounds = 0;
+  c->pull_rounds = 0;
   c->bin_edges = 0;
   c->t_start = (long long)wall_clock64();
   c->t_end = 0;
@@ -647,8 +650,12 @@ union ScatterShared {
   BinSortLds bs;
 };
 
+__device__ __forceinline__ bool pull_round(const PlainArgs& a, long long E) {
+  return a.pull != nullptr && a.nbins > 0 && E >= a.bin_emin && E >= a.pull_emin;
+}
 __device__ __forceinline__ bool bin_round(const PlainArgs& a, long long E) {
-  return a.nbins > 0 && E >= a.bin_emin && E <= (long long)a.bin_cmax * kBinChunk;
+  return a.nbins > 0 && E >= a.bin_emin && E <= (long long)a.bin_cmax * kBinChunk &&
+         !pull_round(a, E);
 }
 
 // Exclusive scan over the workgroup of one int per thread; sh holds
@@ -775,20 +782,35 @@ __device__ void bin_sort_chunks(const PlainArgs& a, int nf, BinSortLds& L) {
   }
 }
 
-// Pass B of a binned round, then the round's close.  Exits at once when the
-// round was not binned (k_scatter then closed it).
+// Pass B of a binned round, or the pull form of a round that covers at
+// least half the graph's arcs, then the round's close.  Exits at once when
+// the round was neither (k_scatter then closed it).
+//   Pass B: each item gathers its bin's runs of (neighbour, entry) pairs
+//   from pass A and adds the entries' coefficients into an LDS array over
+//   the bin's vertices.
+//   Pull: each item walks a slice of its bin's own vertices' arcs (CSR rows
+//   in order) and adds the coefficient of every neighbour whose pull record
+//   carries this round's epoch (the frontier), with no pairs and no pass A.
+// Then every touched destination gets one update (plain when the item owns
+// the whole bin, atomic otherwise), on which its threshold crossing and
+// first touch are decided.
 __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
   Ctl* c = a.ctl;
   int t, nf;
   if (!push_active(c, a.n, &t, &nf)) return;
   if (t >= c->max_rounds || c->selfed != t) return;
   const long long E = c->etotal;
-  if (!bin_round(a, E)) return;
+  const bool pull = pull_round(a, E);
+  if (!pull && !bin_round(a, E)) return;
   __shared__ double acc[kBinWidth];          // the item's sums, zero between items
   __shared__ int32_t s_list[kBinWidth];      // first touches of the item (offsets in the bin)
   __shared__ int s_items[kMaxBins + 1];      // first item of each bin
-  __shared__ int s_rs[kBinItemChunks];       // start of the item's run in each chunk
-  __shared__ int s_rp[kBinItemChunks + 1];   // exclusive prefix of the run lengths
+  // pass B: start of the item's run in each chunk, and the exclusive prefix
+  // of the run lengths; pull: the bin's row offsets from its first arc
+  __shared__ int s_runs[2 * kBinItemChunks + 1];
+  static_assert(2 * kBinItemChunks + 1 >= kBinWidth + 1, "a bin's row offsets fit");
+  int* const s_rs = s_runs;
+  int* const s_rp = s_runs + kBinItemChunks;
   __shared__ int sh[kBlock / 64 + 1];
   __shared__ int s_nl, s_fb, s_tb, s_last;
   constexpr int kBinsPT = kMaxBins / kBlock;
@@ -799,12 +821,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
   const int nb = a.nbins;
   const int C = (int)((E + kBinChunk - 1) / kBinChunk);
   const double eps = c->eps;
+  const unsigned pull_ep = pull ? *a.pull_epoch : 0u;
   int32_t* Fn = (t & 1) ? a.fbuf0 : a.fbuf1;
   int32_t* cntn = &c->cnt[(t + 1) & 1];
   for (int j = threadIdx.x; j < kBinWidth; j += kBlock) acc[j] = 0.0;
   // items per bin: the bin's expected share of the round's edges (E vol_b /
   // 2m) over kBinQ, at least enough that an item spans <= kBinItemChunks
-  // chunks, at most one per chunk; every workgroup computes the same table
+  // chunks, at most one per chunk (pull: the bin's arcs vol_b over kBinQ);
+  // every workgroup computes the same table
   {
     const int smin = (C + kBinItemChunks - 1) / kBinItemChunks;
     int loc[kBinsPT];
@@ -814,10 +838,13 @@ __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
       const int b = (int)threadIdx.x * kBinsPT + k;
       int it = 0;
       if (b < nb) {
-        const double expect = (double)E * (double)a.bin_vol[b] / (double)a.vol_total;
+        const double expect =
+            pull ? (double)a.bin_vol[b] : (double)E * (double)a.bin_vol[b] / (double)a.vol_total;
         it = (int)ceil(expect / (double)kBinQ);
-        it = it > smin ? it : smin;
-        it = it < C ? it : C;
+        if (!pull) {
+          it = it > smin ? it : smin;
+          it = it < C ? it : C;
+        }
         it = it > 1 ? it : 1;
       }
       loc[k] = it;
@@ -847,68 +874,113 @@ __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
     const int b = lo;
     const int S = s_items[b + 1] - s_items[b];
     const int sl = it - s_items[b];
-    const int c0 = (int)((long long)sl * C / S), c1 = (int)((long long)(sl + 1) * C / S);
-    const int nc = c1 - c0;
     const int vlo = a.bin_lo[b];
     const int W = a.bin_lo[b + 1] - vlo;
     const bool own = S == 1;
-    // the item's runs
-    int rl[kRunsPT];
-    int lsum = 0;
+    if (pull) {
+      // the slice of the bin's arcs: rows vlo .. vlo + Wn (the last bin may
+      // end past n), arcs A0 .. A1 of the CSR
+      const int Wn = (int)((int64_t)vlo + W < a.n ? W : a.n - vlo);
+      const long long A0 = a.off[vlo], A1 = a.off[vlo + Wn];
+      const long long j0 = A0 + (A1 - A0) * sl / S, j1 = A0 + (A1 - A0) * (sl + 1) / S;
+      for (int r = threadIdx.x; r <= Wn; r += kBlock) s_runs[r] = (int)(a.off[vlo + r] - A0);
+      __syncthreads();
+      constexpr int kU = 4;
+      for (long long e0 = j0; e0 < j1; e0 += kBlock * kU) {
+        int32_t u[kU];
 #pragma unroll
-    for (int k = 0; k < kRunsPT; k++) {
-      const int q = (int)threadIdx.x * kRunsPT + k;
-      rl[k] = 0;
-      if (q < nc) {
-        const int st = a.bin_T[(size_t)b * a.bin_cmax + c0 + q];
-        const int en = a.bin_T[(size_t)(b + 1) * a.bin_cmax + c0 + q];
-        s_rs[q] = (c0 + q) * kBinChunk + st;
-        rl[k] = en - st;
-        if (rl[k] < 0 || en > kBinChunk) { c->fault = 1; rl[k] = 0; }
-      }
-      lsum += rl[k];
-    }
-    int L;
-    int ex = block_excl_scan_int(lsum, &L, sh);
+        for (int q = 0; q < kU; q++) {
+          const long long e = e0 + q * kBlock + (int)threadIdx.x;
+          u[q] = e < j1 ? a.nbr[e] : -1;
+        }
+        double cf[kU];
 #pragma unroll
-    for (int k = 0; k < kRunsPT; k++) {
-      const int q = (int)threadIdx.x * kRunsPT + k;
-      if (q < nc) s_rp[q] = ex;
-      ex += rl[k];
-    }
-    __syncthreads();
-    // add every contribution into the LDS array; the first toucher of an
-    // offset lists it
-    constexpr int kU = 4;
-    for (int j0 = 0; j0 < L; j0 += kBlock * kU) {
-      int2 pr[kU];
-#pragma unroll
-      for (int u = 0; u < kU; u++) {
-        const int j = j0 + u * kBlock + (int)threadIdx.x;
-        pr[u] = make_int2(-1, 0);
-        if (j < L) {
-          int l2 = 0, h2 = nc - 1;
-          while (l2 < h2) {
-            const int mid = (l2 + h2 + 1) >> 1;
-            if (s_rp[mid] <= j) l2 = mid; else h2 = mid - 1;
+        for (int q = 0; q < kU; q++) {
+          cf[q] = 0.0;
+          if (u[q] >= 0) {
+            const PullRec pr = a.pull[u[q]];
+            if (pr.stamp == pull_ep) cf[q] = pr.coef;
           }
-          pr[u] = a.bin_pairs[s_rs[l2] + (j - s_rp[l2])];
+        }
+#pragma unroll
+        for (int q = 0; q < kU; q++) {
+          bool first = false;
+          int jl = 0;
+          if (cf[q] != 0.0) {
+            // the row holding arc e: the last row whose first arc is <= e
+            const int rel = (int)(e0 + q * kBlock + (int)threadIdx.x - A0);
+            int l2 = 0, h2 = Wn - 1;
+            while (l2 < h2) {
+              const int mid = (l2 + h2 + 1) >> 1;
+              if (s_runs[mid] <= rel) l2 = mid; else h2 = mid - 1;
+            }
+            jl = l2;
+            first = atomicAdd(&acc[jl], cf[q]) == 0.0;
+          }
+          wave_append(first, jl, s_list, &s_nl);
         }
       }
-      double cf[kU];
+    } else {
+      const int c0 = (int)((long long)sl * C / S), c1 = (int)((long long)(sl + 1) * C / S);
+      const int nc = c1 - c0;
+      // the item's runs
+      int rl[kRunsPT];
+      int lsum = 0;
 #pragma unroll
-      for (int u = 0; u < kU; u++) cf[u] = pr[u].x >= 0 && pr[u].y < nf ? a.coef[pr[u].y] : 0.0;
-#pragma unroll
-      for (int u = 0; u < kU; u++) {
-        const int jl = pr[u].x - vlo;
-        bool first = false;
-        if (pr[u].x >= 0) {
-          // (contributions are positive, so exactly one addition per touched
-          // offset returns 0; an impossible zero one is not listed)
-          if (jl >= 0 && jl < W) first = atomicAdd(&acc[jl], cf[u]) == 0.0 && cf[u] != 0.0;
-          else c->fault = 1;
+      for (int k = 0; k < kRunsPT; k++) {
+        const int q = (int)threadIdx.x * kRunsPT + k;
+        rl[k] = 0;
+        if (q < nc) {
+          const int st = a.bin_T[(size_t)b * a.bin_cmax + c0 + q];
+          const int en = a.bin_T[(size_t)(b + 1) * a.bin_cmax + c0 + q];
+          s_rs[q] = (c0 + q) * kBinChunk + st;
+          rl[k] = en - st;
+          if (rl[k] < 0 || en > kBinChunk) { c->fault = 1; rl[k] = 0; }
         }
-        wave_append(first, jl, s_list, &s_nl);
+        lsum += rl[k];
+      }
+      int L;
+      int ex = block_excl_scan_int(lsum, &L, sh);
+#pragma unroll
+      for (int k = 0; k < kRunsPT; k++) {
+        const int q = (int)threadIdx.x * kRunsPT + k;
+        if (q < nc) s_rp[q] = ex;
+        ex += rl[k];
+      }
+      __syncthreads();
+      // add every contribution into the LDS array; the first toucher of an
+      // offset lists it
+      constexpr int kU = 4;
+      for (int j0 = 0; j0 < L; j0 += kBlock * kU) {
+        int2 pr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+          const int j = j0 + u * kBlock + (int)threadIdx.x;
+          pr[u] = make_int2(-1, 0);
+          if (j < L) {
+            int l2 = 0, h2 = nc - 1;
+            while (l2 < h2) {
+              const int mid = (l2 + h2 + 1) >> 1;
+              if (s_rp[mid] <= j) l2 = mid; else h2 = mid - 1;
+            }
+            pr[u] = a.bin_pairs[s_rs[l2] + (j - s_rp[l2])];
+          }
+        }
+        double cf[kU];
+#pragma unroll
+        for (int u = 0; u < kU; u++) cf[u] = pr[u].x >= 0 && pr[u].y < nf ? a.coef[pr[u].y] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; u++) {
+          const int jl = pr[u].x - vlo;
+          bool first = false;
+          if (pr[u].x >= 0) {
+            // (contributions are positive, so exactly one addition per touched
+            // offset returns 0; an impossible zero one is not listed)
+            if (jl >= 0 && jl < W) first = atomicAdd(&acc[jl], cf[u]) == 0.0 && cf[u] != 0.0;
+            else c->fault = 1;
+          }
+          wave_append(first, jl, s_list, &s_nl);
+        }
       }
     }
     __syncthreads();
@@ -978,9 +1050,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
       c->pushes += nf;
       c->edges += E;
       c->bin_rounds += 1;
+      if (pull) c->pull_rounds += 1;
       c->bin_edges += E;
       c->cnt[t & 1] = 0;
       c->round = t + 1;
+      if (a.pull_epoch) *a.pull_epoch += 1u;
       if (slot >= 0) a.work_log[2 * slot + 1] = 1;
     }
   }
@@ -1009,6 +1083,15 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, Scatt
   if (!push_active(c, a.n, &t, &nf)) return;
   if (HK ? t >= c->hk_N : t >= c->max_rounds) return;
   if (c->selfed != t) return;  // no entries built for this round (a self loop stopped before it)
+  if (MODE == kModePR && pull_round(a, c->etotal)) {
+    // a pull round: the frontier's coefficients, stamped with the round's
+    // epoch, for k_bin_apply to pull (which also closes the round)
+    const unsigned ep = *a.pull_epoch;
+    const int32_t* F = (t & 1) ? a.fbuf1 : a.fbuf0;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nf; i += gridDim.x * kBlock)
+      a.pull[F[i]] = PullRec{a.coef[i], ep, 0};
+    return;
+  }
   if (MODE == kModePR && bin_round(a, c->etotal)) {
     bin_sort_chunks(a, nf, sm.bs);  // pass A; k_bin_apply adds and closes the round
     return;
@@ -1120,6 +1203,7 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, Scatt
       c->edges += E;
       c->cnt[t & 1] = 0;
       c->round = t + 1;
+      if (a.pull_epoch) *a.pull_epoch += 1u;
       if (slot >= 0) a.work_log[2 * slot + 1] = 1;
     }
   }

@@ -454,10 +454,18 @@ extern "C" plc_status plc_graph_load(plc_ctx* ctx, int64_t n, int64_t num_arcs,
     a.bin_pairs = static_cast<int2*>(take(8 * (size_t)a.bin_cmax * plc::kBinChunk));
     a.nbins = nb;
     a.bin_emin = ctx->opt.bin_min_edges > 0 ? ctx->opt.bin_min_edges : plc::kBinEmin;
+    // the pull form for rounds over at least half the arcs (records cleared
+    // by the graph init kernel)
+    a.pull = static_cast<plc::PullRec*>(take(sizeof(plc::PullRec) * (size_t)n));
+    a.pull_epoch = static_cast<unsigned*>(take(256));
+    a.pull_emin = std::max<long long>(1, (num_arcs + 1) / 2);
   } else {
     a.nbins = 0;
     a.bin_cmax = 0;
     a.bin_emin = 0;
+    a.pull = nullptr;
+    a.pull_epoch = nullptr;
+    a.pull_emin = 0;
   }
   if (nomem) {
     graph_release_blocks(ctx, g);
@@ -939,6 +947,7 @@ static plc_status record_result(plc_ctx* ctx, plc_graph* g, uint64_t* id_out,
                      std::chrono::steady_clock::now() - ctx->q_t0).count();
   info.device_ns = h.t_end > h.t_start ? (int64_t)((double)(h.t_end - h.t_start) * ctx->clock_ns) : 0;
   info.bin_rounds = h.bin_rounds;
+  info.pull_rounds = h.pull_rounds;
   info.bin_edges = h.bin_edges;
   info.flags = ctx->cur_flags;
   info.pipelined = ctx->cur_pipe;

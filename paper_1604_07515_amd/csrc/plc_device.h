@@ -103,7 +103,7 @@ struct __align__(64) Ctl {
   long long loop_pushes, loop_edges;
   // rounds whose scatter went through the destination bins, and their edges
   int32_t bin_rounds;
-  int32_t pad2;
+  int32_t pull_rounds;  // among bin_rounds: rounds in the pull form
   long long bin_edges;
   // constant-rate clock (wall_clock64) at the query's initialisation and at
   // the end of its sweep
@@ -111,6 +111,14 @@ struct __align__(64) Ctl {
 };
 
 // Arguments shared by the plain-path kernels (all device pointers).
+// Per-vertex pull record: the vertex's coefficient cn rho / d in the round
+// whose epoch is stamped.
+struct __align__(16) PullRec {
+  double coef;
+  uint32_t stamp;
+  int32_t pad;
+};
+
 struct PlainArgs {
   int64_t n;
   long long vol_total;
@@ -164,6 +172,15 @@ struct PlainArgs {
   const long long* bin_vol;    // [nbins] sum of degrees over the bin
   int32_t* bin_T;              // [(nbins + 1) x bin_cmax]: start of bin b's run in chunk c
   int2* bin_pairs;             // [bin_cmax x kBinChunk]: (neighbour, entry) by bin per chunk
+  // Pull form of a binned round, for rounds of at least pull_emin edges
+  // (half the graph's arcs): each bin sums, over its own vertices' arcs, the
+  // coefficients of the neighbours on the round's frontier, which the
+  // round's scatter launch stamps with the round's epoch.  The epoch advances
+  // at every round close and is never reset, so records of earlier rounds
+  // and queries never match.  pull = null turns it off.
+  PullRec* pull;               // [n]
+  unsigned* pull_epoch;
+  long long pull_emin;
 };
 
 // Launch configuration.

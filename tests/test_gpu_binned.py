@@ -104,9 +104,11 @@ def test_binned_rounds_happen(ctx_bin):
 
 def test_binned_split_bin_star(ctx_bin):
     """Star seeded at the hub: the second round sends every leaf's
-    contribution to the hub, whose bin is split over two workgroups (4096 and
-    5904 pairs; atomic updates of the split bin), and the third reaches all
-    leaves.  The hub collects 10^4 equal contributions per round.  Summed one
+    contribution to the hub, and the third reaches all leaves.  Every round
+    covers at least half the star's arcs, so it takes the pull form, and the
+    hub's bin (its 10^4 arcs and 63 leaves) is split over three workgroups
+    whose partial sums reach the hub by atomic updates.  The hub collects
+    10^4 equal contributions per round.  Summed one
     by one (the oracle) or as two partial sums (the split bin), such sums
     differ by up to ~2e-13 relative per collection, and the difference
     compounds each time the hub collects again: with alpha = 0.01 and
@@ -177,3 +179,24 @@ def test_binned_direct_launches_and_timing(plc):
         check_same(g, a, b)
         check_same(g, a, cc)
         check_query(g, a, s, 0.01, 1e-7, OPT)
+
+
+@pytest.mark.parametrize("rule,alpha", [(OPT, 0.01), (ORIG, 0.02)])
+def test_pull_rounds(ctx_bin, ctx_atomic, rule, alpha):
+    """Rounds over at least half the graph's arcs take the pull form (each
+    bin sums its own vertices' arcs from the frontier's stamped
+    coefficients): R-MAT 2^16 from the minimum vertex of its largest
+    component (the saturating C1 query) spends most of its rounds there.
+    Oracle parity, and agreement with the atomic scatter."""
+    gb, hb = graph(ctx_bin, "rmat16")
+    _, ha = graph(ctx_atomic, "rmat16")
+    x = synth.largest_component_min_vertex(gb)
+    ids, infos = ctx_bin.run(hb, [x], alpha, 1e-7, rule)
+    res = ctx_bin.result(ids[0], release=True)
+    info = infos[0]
+    say("pull: rounds", info["rounds"], "binned", info["bin_rounds"], "pulled",
+        info["pull_rounds"])
+    assert 10 <= info["pull_rounds"] <= info["bin_rounds"]
+    check_query(gb, res, x, alpha, 1e-7, rule)
+    ia, _ = ctx_atomic.run(ha, [x], alpha, 1e-7, rule)
+    check_same(gb, res, ctx_atomic.result(ia[0], release=True))
