@@ -392,7 +392,29 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
     el_i, _ = one_pass("instrumented")
     tm = ctx.timing_get()
     ctx.timing(False)
+    # a sweep at this scale: Nibble (T = 2, nothing truncated) from the top
+    # hub covers every vertex within two hops of it (one warm run, one timed
+    # run, one with the sweep's events on)
+    hub = int(hubs[0])
+    qid, _ = ctx.run_nibble(hg, hub, 1e-300, 2)
+    ctx.release(qid)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    qid, hinfo = ctx.run_nibble(hg, hub, 1e-300, 2)
+    el_h = time.perf_counter() - t2
+    ctx.release(qid)
+    ctx.timing(True)
+    qid, _ = ctx.run_nibble(hg, hub, 1e-300, 2)
+    ctx.release(qid)
+    th = ctx.timing_get()
+    ctx.timing(False)
     ctx.close()
+    hub_sweep = {"query": "Nibble, T 2, eps 1e-300, from the top hub (vertex %d)" % hub,
+                 "support": hinfo["support"], "kstar": hinfo["kstar"],
+                 "pushed_edges": hinfo["edges"], "ms": el_h * 1e3,
+                 "sweep_ms": th["sweep"]["ms"], "sweep_support_arcs": th["sweep"]["units"]}
+    log("  large hub sweep: support %d in %.1f ms (sweep %.1f ms)" % (
+        hinfo["support"], el_h * 1e3, th["sweep"]["ms"]))
     return {"workload": "rmat%d_ef16_1024seeds_32hubs" % scale, "n": g.n, "arcs": g.arcs,
             "state": "compact tables", "slots": got, "table_budget_gib": table_gib,
             "eps": [1e-8, 1e-6], "alpha": 0.01, "queries": nq, "failed_nomem": acc["nomem"],
@@ -401,7 +423,8 @@ def bench_large(plc, synth, scale=26, nq=1024, slots=1024, table_gib=160):
             "max_rounds": acc["rounds"], "kernels": tm,
             "what": "one warm-up pass, then the timed pass (no per-kernel events), then an "
                     "instrumented pass for the kernel durations (%.2f s)" % el_i,
-            "roofline": roofline(tm, "k_b_scatter<CompactState>", counted=False)}
+            "roofline": roofline(tm, "k_b_scatter<CompactState>", counted=False),
+            "hub_sweep": hub_sweep}
 
 
 def bench_rules(plc, synth, g, seeds):
