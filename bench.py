@@ -146,8 +146,9 @@ def timed_steps(ctx, step, steps, warmup, instrument=True):
 
 
 def account(acc, infos, ids, ctx, fetch=False):
-    """Sum the query counters; fetch copies each result's p and cluster to
-    the host before the release."""
+    """Sum the query counters; fetch copies every result's p and cluster to
+    the host (all of the step's results with one GPU round trip) before the
+    release."""
     for qid, info in zip(ids, infos):
         acc["edges"] += info["edges"]
         acc["pushes"] += info["pushes"]
@@ -155,9 +156,10 @@ def account(acc, infos, ids, ctx, fetch=False):
         acc["support"] += info["support"]
         acc["queries"] += 1
         acc["bin_rounds"] = acc.get("bin_rounds", 0) + info["bin_rounds"]
-        if fetch:
-            ctx.result(qid, release=True)
-        else:
+    if fetch:
+        ctx.results(ids, release=True)
+    else:
+        for qid in ids:
             ctx.release(qid)
 
 
@@ -205,7 +207,8 @@ def bench_plain(plc, synth, g, steps, warmup):
                       "what": "per query: device clock from its initialisation kernel to the "
                               "end of its sweep"},
         "result_copy": "p and the cluster of every query copied to the host inside the "
-                       "timed steps (PLC_QF_NO_RESIDUAL: r is not kept)",
+                       "timed steps, the step's 16 results with one GPU round trip "
+                       "(plc_result_copy_many; PLC_QF_NO_RESIDUAL: r is not kept)",
         "without_result_copy": {"edges_per_s": acc2["edges"] / el2,
                                 "queries_per_s": acc2["queries"] / el2,
                                 "ms_per_step": el2 * 1e3 / steps},
@@ -314,7 +317,8 @@ def bench_serving(plc, synth, scale, nq, slots=64, compact=False, measured=10000
            "state": "compact tables" if compact else "dense slots", "slots": got,
            "alpha": 0.01, "eps": [1e-7, 1e-4], "seeds": "proportional to degree",
            "result_copy": "each result's p and cluster copied to the host before it counts "
-                          "as done (PLC_QF_NO_RESIDUAL)",
+                          "as done, the results of one engine step with one GPU round trip "
+                          "(plc_result_copy_many; PLC_QF_NO_RESIDUAL)",
            "saturation": {"queries": nq, "queries_per_s": sat.queries_per_s,
                           "edges_per_s": sat.edges / sat.wall_s,
                           "p50_ms": sat.percentile_ms(50), "p99_ms": sat.percentile_ms(99)},

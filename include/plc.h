@@ -457,6 +457,22 @@ plc_status plc_result_info_get(plc_ctx* ctx, uint64_t id, plc_result_info* out);
 plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_ids, double* sweep_p,
                            int32_t* r_ids, double* r_vals);
 
+/*
+ * Several results at once, for serving loops that collect every query a
+ * step finished: for each i < count the same as plc_result_copy(ctx,
+ * ids[i], sweep_ids[i], sweep_p[i], r_ids[i], r_vals[i]), where a NULL
+ * pointer array skips that part for every result and a NULL entry for one.
+ * One kernel gathers the parts into pinned, device-mapped host staging
+ * memory that the context keeps (grown as needed, freed with the context),
+ * one wait, then host copies into the caller's buffers: one GPU round trip
+ * for the whole set instead of one per result.  PLC_E_NOTFOUND for an
+ * unknown id and PLC_E_NOMEM for a result without vectors (nothing copied
+ * then), PLC_E_NOMEM also when the staging memory cannot be allocated.
+ */
+plc_status plc_result_copy_many(plc_ctx* ctx, int32_t count, const uint64_t* ids,
+                                int32_t* const* sweep_ids, double* const* sweep_p,
+                                int32_t* const* r_ids, double* const* r_vals);
+
 /* Return a finished query's arena memory.  Does not wait for the GPU: any
  * work that reuses the memory is queued behind the query's pending result
  * copy on the context's stream.  PLC_E_NOTFOUND for an unknown id. */

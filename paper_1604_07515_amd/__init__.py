@@ -39,7 +39,7 @@ SYMBOLS = ("plc_status_str", "plc_init", "plc_destroy", "plc_graph_load", "plc_g
            "plc_graph_info_get", "plc_run", "plc_run_set", "plc_run_hkpr", "plc_run_nibble",
            "plc_run_beta", "plc_run_noalloc",
            "plc_result_info_get",
-           "plc_result_copy",
+           "plc_result_copy", "plc_result_copy_many",
            "plc_release", "plc_arena_free_bytes", "plc_timing_enable", "plc_timing_get",
            "plc_batch_reserve", "plc_submit", "plc_progress", "plc_poll", "plc_wait",
            "plc_query_bytes_estimate", "plc_run_batched", "plc_autotune")
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                           C.POINTER(plc_result_info)], I32),
         "plc_result_info_get": ([P, U64, C.POINTER(plc_result_info)], I32),
         "plc_result_copy": ([P, U64, P, P, P, P], I32),
+        "plc_result_copy_many": ([P, I32, P, P, P, P, P], I32),
         "plc_release": ([P, U64], I32),
         "plc_arena_free_bytes": ([P, C.POINTER(SZ), C.POINTER(SZ)], I32),
         "plc_timing_enable": ([P, I32], I32),
@@ -447,6 +448,34 @@ class Context:
         if release:
             self.release(qid)
         return Result(info.as_dict(), ids, p, rid, rv)
+
+    def results(self, qids, release: bool = False) -> list:
+        """result() for several finished queries with one GPU round trip
+        (plc_result_copy_many)."""
+        qids = [int(q) for q in qids]
+        if not qids:
+            return []
+        infos, vecs = [], []
+        for qid in qids:
+            info = plc_result_info()
+            _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)),
+                   "plc_result_info_get")
+            N, R = info.support, info.r_nnz
+            if info.flags & PLC_QF_NO_RESIDUAL:
+                R = 0  # the result keeps no residual vector
+            infos.append(info)
+            vecs.append((np.empty(N, np.int32), np.empty(N, np.float64),
+                         np.empty(R, np.int32), np.empty(R, np.float64)))
+        k = len(qids)
+        arrs = [(C.c_void_p * k)(*[v[j].ctypes.data if len(v[j]) else None for v in vecs])
+                for j in range(4)]
+        ids = np.asarray(qids, np.uint64)
+        _check(self.lib.plc_result_copy_many(self.handle, k, _ptr(ids), *arrs),
+               "plc_result_copy_many")
+        if release:
+            for qid in qids:
+                self.release(qid)
+        return [Result(info.as_dict(), *v) for info, v in zip(infos, vecs)]
 
     def release(self, qid: int):
         _check(self.lib.plc_release(self.handle, qid), "plc_release")

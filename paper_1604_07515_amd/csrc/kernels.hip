@@ -1916,6 +1916,31 @@ hipError_t launch_copy_result(hipStream_t s, const PlainArgs& a, int32_t* ids, d
   return hipGetLastError();
 }
 
+// Several results' parts into one destination (the host's pinned staging
+// memory): one workgroup per part at a time, 16-byte words where both ends
+// allow it.
+__global__ __launch_bounds__(kBlock) void k_gather_results(const GatherJob* jobs, int njobs,
+                                                           uint32_t* dst) {
+  for (int j = blockIdx.x; j < njobs; j += gridDim.x) {
+    const GatherJob J = jobs[j];
+    const uint32_t* src = J.src;
+    uint32_t* out = dst + J.dst_off;
+    const uint64_t nw = J.words;
+    const bool wide = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    const uint64_t n4 = wide ? nw / 4 : 0;
+    for (uint64_t i = threadIdx.x; i < n4; i += kBlock)
+      reinterpret_cast<uint4*>(out)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (uint64_t i = 4 * n4 + threadIdx.x; i < nw; i += kBlock) out[i] = src[i];
+  }
+}
+
+hipError_t launch_gather_results(hipStream_t s, const GatherJob* jobs, int njobs, uint32_t* dst) {
+  if (njobs <= 0) return hipSuccess;
+  const int grid = njobs < 1024 ? njobs : 1024;
+  hipLaunchKernelGGL(k_gather_results, dim3(grid), dim3(kBlock), 0, s, jobs, njobs, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max_count) {
   hipLaunchKernelGGL(k_sweep_keys, dim3(grid), dim3(kBlock), 0, s, a, (long long)max_count);
   SortArgs sa;

@@ -159,6 +159,11 @@ struct plc_ctx {
   Arena arena;
   plc_options opt{};
   Ctl* ctl_host = nullptr;  // pinned
+  // plc_result_copy_many: pinned, device-mapped staging (jobs, then data),
+  // grown as needed
+  char* stage_h = nullptr;
+  char* stage_d = nullptr;
+  size_t stage_bytes = 0;
   std::map<uint64_t, Result> results;
   std::map<uint64_t, plc_graph*> inflight;  // submitted to a batch engine, not finished
   uint64_t next_id = 1;
@@ -278,6 +283,7 @@ extern "C" plc_status plc_destroy(plc_ctx* ctx) {
   free_events(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->ctl_host) (void)hipHostFree(ctx->ctl_host);
+  if (ctx->stage_h) (void)hipHostFree(ctx->stage_h);
   delete ctx;
   return PLC_OK;
 }
@@ -1160,6 +1166,79 @@ extern "C" plc_status plc_result_copy(plc_ctx* ctx, uint64_t id, int32_t* sweep_
   if (r_ids && R) HIPCHK(ctx, hipMemcpyAsync(r_ids, r.rid, 4 * R, hipMemcpyDeviceToHost, s));
   if (r_vals && R) HIPCHK(ctx, hipMemcpyAsync(r_vals, r.rval, 8 * R, hipMemcpyDeviceToHost, s));
   HIPCHK(ctx, hipStreamSynchronize(s));
+  return PLC_OK;
+}
+
+extern "C" plc_status plc_result_copy_many(plc_ctx* ctx, int32_t count, const uint64_t* ids,
+                                           int32_t* const* sweep_ids, double* const* sweep_p,
+                                           int32_t* const* r_ids, double* const* r_vals) {
+  if (!ctx || count < 0 || (count > 0 && !ids)) return PLC_E_INVALID;
+  if (ctx->broken) return PLC_E_HIP;
+  if (count == 0) return PLC_OK;
+  // the parts to copy: (source, bytes, host destination); data offsets in
+  // the staging memory 16-byte aligned
+  struct Part {
+    const void* src;
+    size_t bytes;
+    void* dst;
+    size_t off;
+  };
+  std::vector<Part> parts;
+  parts.reserve(4 * (size_t)count);
+  size_t data = 0;
+  for (int32_t i = 0; i < count; i++) {
+    auto it = ctx->results.find(ids[i]);
+    if (it == ctx->results.end()) return PLC_E_NOTFOUND;
+    const Result& r = it->second;
+    if (!r.block) return PLC_E_NOMEM;
+    const size_t N = (size_t)r.info.support, R = r.rid ? (size_t)r.info.r_nnz : 0;
+    auto add = [&](const void* src, size_t bytes, void* dst) {
+      if (!dst || !bytes) return;
+      parts.push_back(Part{src, bytes, dst, data});
+      data += (bytes + 15) & ~(size_t)15;
+    };
+    add(r.ids, 4 * N, sweep_ids ? sweep_ids[i] : nullptr);
+    add(r.p, 8 * N, sweep_p ? sweep_p[i] : nullptr);
+    add(r.rid, 4 * R, r_ids ? r_ids[i] : nullptr);
+    add(r.rval, 8 * R, r_vals ? r_vals[i] : nullptr);
+  }
+  if (parts.empty()) return PLC_OK;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = ctx->stream;
+  const size_t jobs_bytes = (sizeof(plc::GatherJob) * parts.size() + 255) & ~(size_t)255;
+  const size_t need = jobs_bytes + data;
+  if (need > ctx->stage_bytes) {
+    // (the stream is idle here: every earlier call ended with a wait)
+    size_t cap = std::max<size_t>(ctx->stage_bytes, (size_t)1 << 20);
+    while (cap < need) cap <<= 1;
+    if (ctx->stage_h) (void)hipHostFree(ctx->stage_h);
+    ctx->stage_h = nullptr;
+    ctx->stage_d = nullptr;
+    ctx->stage_bytes = 0;
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, cap, hipHostMallocMapped) != hipSuccess) {
+      (void)hipGetLastError();
+      return PLC_E_NOMEM;
+    }
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(h);
+      return PLC_E_HIP;
+    }
+    ctx->stage_h = static_cast<char*>(h);
+    ctx->stage_d = static_cast<char*>(d);
+    ctx->stage_bytes = cap;
+  }
+  plc::GatherJob* jobs = reinterpret_cast<plc::GatherJob*>(ctx->stage_h);
+  for (size_t k = 0; k < parts.size(); k++)
+    jobs[k] = plc::GatherJob{static_cast<const uint32_t*>(parts[k].src), parts[k].off / 4,
+                             parts[k].bytes / 4};
+  HIPCHK(ctx, plc::launch_gather_results(
+                  s, reinterpret_cast<const plc::GatherJob*>(ctx->stage_d), (int)parts.size(),
+                  reinterpret_cast<uint32_t*>(ctx->stage_d + jobs_bytes)));
+  HIPCHK(ctx, hipStreamSynchronize(s));
+  for (const Part& pt : parts) std::memcpy(pt.dst, ctx->stage_h + jobs_bytes + pt.off, pt.bytes);
   return PLC_OK;
 }
 

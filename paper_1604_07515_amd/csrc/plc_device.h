@@ -271,4 +271,15 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max
 hipError_t launch_copy_result(hipStream_t s, const PlainArgs& a, int32_t* ids, double* p,
                               int32_t* rid, double* rval, int N, int R, int grid);
 
+// One part of a result to gather: `words` 4-byte words from src (device
+// memory) to word dst_off of the gather destination.
+struct GatherJob {
+  const uint32_t* src;
+  uint64_t dst_off;
+  uint64_t words;
+};
+// Gather njobs parts into dst (device-visible, e.g. mapped pinned host
+// memory); jobs may itself live in mapped host memory.
+hipError_t launch_gather_results(hipStream_t s, const GatherJob* jobs, int njobs, uint32_t* dst);
+
 }  // namespace plc

@@ -85,12 +85,13 @@ def serve(ctx, g, seeds, alphas, epss, arrivals, release: bool = True,
             steps += 1
             busy += 1
             max_fl = max(max_fl, left + len(done))
+            if fetch and done:
+                # every result the step finished, copied with one GPU round trip
+                for res in ctx.results(done, release=release):
+                    edges += res.info["edges"]
             for qid in done:
                 i = index.pop(qid)
-                if fetch:
-                    res = ctx.result(qid, release=release)
-                    edges += res.info["edges"]
-                elif release:
+                if not fetch and release:
                     info = ctx.result_info(qid)
                     edges += info["edges"]
                     ctx.release(qid)

@@ -204,3 +204,24 @@ def test_batched_flags_and_device_time(setup, plc):
         assert len(b.r_ids) == 0
         check_same(g, a, b)
         assert 0 < ia["device_ns"] < 10 ** 10 and 0 < ib["device_ns"] < 10 ** 10
+
+
+def test_result_copy_many_matches_one_by_one(setup, plc):
+    """plc_result_copy_many returns, for several results at once, what
+    plc_result_copy returns for each (with and without the residual, and
+    across a staging-memory growth); unknown ids are refused."""
+    g, ctx, hg = setup
+    seeds, alpha, eps, rules = mixed_queries(g, 40, seed=91)
+    for flags in (0, plc.PLC_QF_NO_RESIDUAL):
+        ids, _ = ctx.run_batched(hg, seeds, alpha, eps, rules, flags=flags)
+        many = ctx.results(ids)
+        for i, (qid, m) in enumerate(zip(ids, many)):
+            one = ctx.result(qid, release=True)
+            assert m.info == one.info
+            for a, b in ((m.sweep_ids, one.sweep_ids), (m.sweep_p, one.sweep_p),
+                         (m.r_ids, one.r_ids), (m.r_vals, one.r_vals)):
+                np.testing.assert_array_equal(a, b)
+            check_query(g, m, int(seeds[i]), float(alpha[i]), float(eps[i]), int(rules[i]),
+                        with_r=flags == 0)
+    with pytest.raises(plc.PlcError):
+        ctx.results([123456789])
