@@ -1332,6 +1332,7 @@ static hipError_t sweep_kernels(hipStream_t s, const BatchArgs& a, int nseg, int
   sa.done = &a.ctl->done[0];
   sa.active = nullptr;
   sa.active_value = 0;
+  sa.rank = nullptr;
   hipError_t e = launch_sort(s, sa, max_elems, grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sw_rank<St>, dim3(grid), dim3(kBlock), 0, s, a);

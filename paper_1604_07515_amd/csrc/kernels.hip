@@ -1825,6 +1825,7 @@ hipError_t launch_beta_pre(hipStream_t s, const PlainArgs& a, int grid, int64_t 
   sa.done = &a.ctl->done[DONE_SORT];
   sa.active = nullptr;
   sa.active_value = 0;
+  sa.rank = nullptr;
   hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_beta_select, dim3(grid), dim3(kBlock), 0, s, a);
@@ -1951,6 +1952,9 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max
   sa.done = &a.ctl->done[DONE_SORT];
   sa.active = &a.ctl->status;
   sa.active_value = ST_SWEEPING;
+  // the volume prefix is written only after the sort: its words hold the
+  // small-count path's rank accumulators meanwhile
+  sa.rank = reinterpret_cast<unsigned long long*>(a.svol);
   hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vol_scan, dim3(grid), dim3(kBlock), 0, s, a);

@@ -19,10 +19,22 @@ struct SortArgs {
   unsigned* done;          // last-workgroup counter (device, zero between launches)
   const int32_t* active;   // optional gate: the sort runs only if *active == active_value
   int32_t active_value;
+  // Optional: one word per element for the small-count path (the per-element
+  // rank accumulators of the one-launch merge); null selects merge passes
+  // at every count.
+  unsigned long long* rank;
 };
 
-// Queue the block sort and every merge pass needed for up to max_count
-// elements; passes beyond the actual count return at once.
+// Counts up to this many elements take the small-count path when
+// SortArgs::rank is set: after the block sort, one launch places every
+// element at its rank among all tiles instead of the merge passes.
+constexpr int64_t kRankMaxCount = 65536;
+
+// Queue the sort of up to max_count elements (the element count itself is
+// read on the device): the small-count path when rank is set and max_count
+// is at most kRankMaxCount, else every merge pass needed for max_count
+// elements after the block sort (passes beyond the actual count return at
+// once).
 hipError_t launch_sort(hipStream_t st, const SortArgs& s, int64_t max_count, int grid);
 
 }  // namespace plc

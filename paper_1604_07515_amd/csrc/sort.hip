@@ -16,6 +16,12 @@
 // outputs.  The element count lives in
 // device memory; passes whose run length already covers it return at once,
 // so the whole sequence is queued without a host round trip.
+//
+// Small counts (a bound of at most kRankMaxCount elements known when the
+// sort is queued) replace the merge passes with one launch: each element's
+// place is its position in its own block-sorted tile plus its count in
+// every other tile, found by a binary search in that tile held in LDS, and
+// the last of those additions places it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,10 +45,30 @@ constexpr SortElem kMaxElem = {~0ull, INT32_MAX, INT32_MAX};
 // different banks.
 __device__ __forceinline__ int lds_pad(int i) { return i + i / kBT; }
 
-__device__ __forceinline__ bool elem_lt(const SortElem& a, const SortElem& b) {
-  if (a.seg != b.seg) return a.seg < b.seg;
-  if (a.key != b.key) return a.key < b.key;
-  return a.id < b.id;
+// The comparison and the selects take whole elements by value and use no
+// short-circuit operators: every field of both operands is loaded up front
+// (one 16-byte load each) instead of one dependent load per field compared.
+__device__ __forceinline__ bool elem_lt(const SortElem a, const SortElem b) {
+  const bool seg_lt = a.seg < b.seg, seg_eq = a.seg == b.seg;
+  const bool key_lt = a.key < b.key, key_eq = a.key == b.key;
+  return seg_lt | (seg_eq & (key_lt | (key_eq & (a.id < b.id))));
+}
+
+__device__ __forceinline__ SortElem elem_sel(bool c, const SortElem a, const SortElem b) {
+  SortElem r;
+  r.key = c ? a.key : b.key;
+  r.id = c ? a.id : b.id;
+  r.seg = c ? a.seg : b.seg;
+  return r;
+}
+
+// Element i of a sorted run in LDS (index through idx), or the largest
+// element once i reaches the run's length: the load uses a clamped index,
+// so it stays an LDS load and never needs the constant from memory.
+template <typename F>
+__device__ __forceinline__ SortElem run_head(const SortElem* sh, F idx, int i, int len) {
+  const SortElem v = sh[idx(i < len ? i : len - 1)];
+  return elem_sel(i < len, v, kMaxElem);
 }
 
 __device__ __forceinline__ bool sort_enabled(const SortArgs& s) {
@@ -51,11 +77,11 @@ __device__ __forceinline__ bool sort_enabled(const SortArgs& s) {
 
 // Compare-exchange: afterwards a <= b when up, a >= b otherwise.
 __device__ __forceinline__ void cswap(SortElem& a, SortElem& b, bool up) {
-  if (elem_lt(b, a) == up) {
-    SortElem t = a;
-    a = b;
-    b = t;
-  }
+  const bool sw = elem_lt(b, a) == up;
+  const SortElem lo = elem_sel(sw, b, a);
+  const SortElem hi = elem_sel(sw, a, b);
+  a = lo;
+  b = hi;
 }
 
 __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
@@ -72,7 +98,8 @@ __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
 #pragma unroll
     for (int k = 0; k < kBT; k++) {
       const int i = k * kBSBlk + t;
-      sh[lds_pad(i)] = base + i < N ? buf[base + i] : kMaxElem;
+      const int gi = base + i < N ? base + i : N - 1;
+      sh[lds_pad(i)] = elem_sel(base + i < N, buf[gi], kMaxElem);
     }
     __syncthreads();
     // elements kBT*t .. kBT*t + kBT - 1, sorted in registers (bitonic network)
@@ -105,25 +132,28 @@ __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
       int hi = d < L ? d : L;
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (elem_lt(sh[lds_pad(B + d - 1 - mid)], sh[lds_pad(A + mid)])) hi = mid; else lo = mid + 1;
+        const SortElem b = sh[lds_pad(B + d - 1 - mid)];
+        const SortElem a = sh[lds_pad(A + mid)];
+        if (elem_lt(b, a)) hi = mid; else lo = mid + 1;
       }
       // the two run heads stay in registers; an exhausted run shows the
       // largest element, equal to the tile padding, so either choice
       // between the two then outputs the same value
       int ia = lo, ib = d - lo;
-      SortElem ha = ia < L ? sh[lds_pad(A + ia)] : kMaxElem;
-      SortElem hb = ib < L ? sh[lds_pad(B + ib)] : kMaxElem;
+      SortElem ha = run_head(sh, [&](int i) { return lds_pad(A + i); }, ia, L);
+      SortElem hb = run_head(sh, [&](int i) { return lds_pad(B + i); }, ib, L);
 #pragma unroll
       for (int k = 0; k < kBT; k++) {
-        if (!elem_lt(hb, ha)) {
-          x[k] = ha;
-          ia++;
-          ha = ia < L ? sh[lds_pad(A + ia)] : kMaxElem;
-        } else {
-          x[k] = hb;
-          ib++;
-          hb = ib < L ? sh[lds_pad(B + ib)] : kMaxElem;
-        }
+        const bool ta = !elem_lt(hb, ha);
+        x[k] = elem_sel(ta, ha, hb);
+        ia += ta;
+        ib += !ta;
+        // one load: the next head of the run just taken
+        const int r0 = ta ? A : B;
+        const int ri = ta ? ia : ib;
+        const SortElem nx = run_head(sh, [&](int i) { return lds_pad(r0 + i); }, ri, L);
+        ha = elem_sel(ta, nx, ha);
+        hb = elem_sel(ta, hb, nx);
       }
       __syncthreads();
 #pragma unroll
@@ -133,11 +163,74 @@ __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
 #pragma unroll
     for (int k = 0; k < kBT; k++) {
       const int i = k * kBSBlk + t;
-      if (base + i < N) buf[base + i] = sh[lds_pad(i)];
+      if (base + i < N) {
+        buf[base + i] = sh[lds_pad(i)];
+        if (s.rank != nullptr) s.rank[base + i] = (unsigned long long)i;
+      }
     }
     __syncthreads();
   }
 }
+
+// ------------------------------------------------------ small-count path
+
+constexpr int kRankBlk = 512;                          // threads of the rank merge
+constexpr int kRankGrid = 512;                         // its workgroups, split among the tiles
+static_assert(kRankMaxCount % kTileB == 0, "whole block-sort tiles");
+
+// Places every element of the block-sorted tiles at its rank in the whole
+// order.  Workgroup (j, g) of the per workgroups of tile j holds tile j in
+// LDS and takes every per-th element outside it: each lane counts the
+// elements of tile j that precede its element (those not greater when tile
+// j comes first, those less when it comes later, so equal elements of
+// different tiles keep tile order) and adds the count to the element's rank
+// word (set by the block sort to its position in its own tile), whose upper
+// half counts the additions; the addition that completes the T - 1 of them
+// writes the element out.  Tiles beyond tiles_max (a count above the bound
+// the launch was sized for) are taken in further turns.
+__global__ __launch_bounds__(kRankBlk) void k_rank_merge(SortArgs s, int tiles_max, int per) {
+  if (!sort_enabled(s)) return;
+  const int N = *s.count;
+  const int T = (N + kTileB - 1) / kTileB;
+  if (T <= 1) return;
+  const int flip = *s.flip;
+  const SortElem* src = s.buf[flip];
+  SortElem* dst = s.buf[flip ^ 1];
+  __shared__ SortElem sh[kTileB];
+  __shared__ int s_last;
+  const int g = blockIdx.x % per;
+  for (int j = blockIdx.x / per; j < T; j += tiles_max) {
+    const int base = j * kTileB;
+    const int len = N - base < kTileB ? N - base : kTileB;
+    __syncthreads();
+    for (int x = threadIdx.x; x < len; x += kRankBlk) sh[x] = src[base + x];
+    __syncthreads();
+    const int others = N - len;
+    for (int q = g * kRankBlk + threadIdx.x; q < others; q += per * kRankBlk) {
+      const int k = q < base ? q : q + len;
+      const SortElem e = src[k];
+      int lo = 0, hi = len;
+      if (k >= base) {
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (elem_lt(e, sh[mid])) hi = mid; else lo = mid + 1;
+        }
+      } else {
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (elem_lt(sh[mid], e)) lo = mid + 1; else hi = mid;
+        }
+      }
+      const unsigned long long old = atomicAdd(&s.rank[k], (1ull << 32) | (unsigned long long)lo);
+      if ((int)(old >> 32) == T - 2) dst[(long long)(old & 0xffffffffull) + lo] = e;
+    }
+  }
+  if (last_block(s.done, &s_last, false)) {
+    if (threadIdx.x == 0) *s.flip = flip ^ 1;
+  }
+}
+
+// ------------------------------------------------------------ merge passes
 
 // Merge-path splits of one output tile: the number of A elements among the
 // first d0 (threads 0..127) and d1 (threads 128..255) outputs of merge(A, B),
@@ -184,6 +277,15 @@ __device__ void merge_splits(const SortElem* A, int la, const SortElem* B, int l
   __syncthreads();
 }
 
+// Element i of the run of length len staged at sm[r0..], or the largest
+// element past its end; the index is clamped into the staging tile so the
+// load is always an in-bounds LDS load.
+__device__ __forceinline__ SortElem staged_head(const SortElem* sm, int r0, int i, int len) {
+  int li = r0 + (i < len ? i : len - 1);
+  li = li < 0 ? 0 : (li < kTileS ? li : kTileS - 1);
+  return elem_sel(i < len, sm[li], kMaxElem);
+}
+
 __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
   if (!sort_enabled(s)) return;
   const int N = *s.count;
@@ -221,12 +323,18 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
         if (elem_lt(sm[na + (d - 1 - mid)], sm[mid])) hi = mid; else lo = mid + 1;
       }
       int ia = lo, ib = d - lo;
+      // run heads in registers, an exhausted run showing the largest
+      // element (no element of a sort equals it)
+      SortElem ha = staged_head(sm, 0, ia, na);
+      SortElem hb = staged_head(sm, na, ib, nb);
       for (int k = 0; k < kPerThr && d + k < na + nb; k++) {
-        bool takeA;
-        if (ia >= na) takeA = false;
-        else if (ib >= nb) takeA = true;
-        else takeA = elem_lt(sm[ia], sm[na + ib]);
-        dst[o0 + d + k] = takeA ? sm[ia++] : sm[na + ib++];
+        const bool ta = !elem_lt(hb, ha);
+        dst[o0 + d + k] = elem_sel(ta, ha, hb);
+        ia += ta;
+        ib += !ta;
+        const SortElem nx = staged_head(sm, ta ? 0 : na, ta ? ia : ib, ta ? na : nb);
+        ha = elem_sel(ta, nx, ha);
+        hb = elem_sel(ta, hb, nx);
       }
     }
     __syncthreads();
@@ -238,6 +346,14 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
 
 hipError_t launch_sort(hipStream_t st, const SortArgs& s, int64_t max_count, int grid) {
   hipLaunchKernelGGL(k_block_sort, dim3(grid), dim3(kBSBlk), 0, st, s);
+  if (s.rank != nullptr && max_count <= kRankMaxCount) {
+    const int tiles = (int)((max_count + kTileB - 1) / kTileB);
+    if (tiles > 1) {
+      const int per = kRankGrid / tiles;
+      hipLaunchKernelGGL(k_rank_merge, dim3(tiles * per), dim3(kRankBlk), 0, st, s, tiles, per);
+    }
+    return hipGetLastError();
+  }
   for (int64_t L = kTileB; L < max_count; L <<= 1)
     hipLaunchKernelGGL(k_merge_pass, dim3(grid), dim3(kSortBlk), 0, st, s, (int)L);
   return hipGetLastError();
