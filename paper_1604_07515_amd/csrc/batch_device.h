@@ -13,9 +13,11 @@
 //           path; the scatter's atomic needs no probing.  Reset through the
 //           touched list when the query retires.
 //   compact (CompactState) tab/tp are a per-query open-addressing table of
-//           capacity mask+1 (a power of 2, linear probing, at most half
-//           full), allocated from the arena at admission and grown between
-//           rounds, so a query holds memory in proportion to the vertices it
+//           tcap records (a multiple of 1024, linear probing from a
+//           multiply-high home position; sized so that it is at most half
+//           full and at most 3/4 full after the next round's worst case),
+//           allocated from the arena at admission and grown between rounds,
+//           so a query holds memory in proportion to the vertices it
 //           touched rather than to n.  d(v) and the hot code sit in the
 //           record beside the key (claimed with it in one 64-bit
 //           compare-and-swap, from a graph-wide array), so the scatter's
