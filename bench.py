@@ -268,12 +268,20 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256, compact=False):
         tune["batch_self"], tune["batch_scatter"], tune["candidates"]))
 
     def step(lat, acc):
+        # the batch in one call, then every query's p and cluster copied to
+        # the host (the batch's results with one GPU round trip); the batch's
+        # latency ends when its results are on the host
         q0 = time.perf_counter()
-        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps)
+        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps, flags=plc.PLC_QF_NO_RESIDUAL)
+        account(acc, infos, ids, ctx, fetch=True)
         lat.append(time.perf_counter() - q0)
+
+    def step_resident(lat, acc):
+        ids, infos = ctx.run_batched(hg, qs.seeds, qs.alpha, qs.eps)
         account(acc, infos, ids, ctx)
 
     elapsed, lat, acc, tm = timed_steps(ctx, step, steps, warmup)
+    el2, _, acc2, _ = timed_steps(ctx, step_resident, steps, 1, instrument=False)
     ctx.close()
     nq = acc["queries"]
     return {
@@ -281,7 +289,14 @@ def bench_batched(plc, synth, g, steps, warmup, slots=256, compact=False):
         "state": "compact tables" if compact else "dense slots", "slots": got, "edges_per_s": acc["edges"] / elapsed, "queries_per_s": nq / elapsed,
         "ms_per_step": elapsed * 1e3 / steps,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
-                       "what": "per batch of 256"},
+                       "what": "per batch of 256, until its results are on the host"},
+        "result_copy": "p and the cluster of every query copied to the host inside the "
+                       "timed steps, the batch's 256 results with one GPU round trip "
+                       "(plc_result_copy_many; PLC_QF_NO_RESIDUAL: r is not kept)",
+        "without_result_copy": {"edges_per_s": acc2["edges"] / el2,
+                                "queries_per_s": acc2["queries"] / el2,
+                                "ms_per_step": el2 * 1e3 / steps,
+                                "what": "the residual kept on the device, nothing copied"},
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support")},
         "eps": [float(qs.eps.min()), float(qs.eps.max())], "alpha": [0.01, 0.05],
         "kernels": tm,
@@ -767,10 +782,10 @@ def main():
         log("c1 (R-MAT 2^16 from vertex %d): %.2f ms per query, %.3g edges/s, %d rounds, "
             "%d binned" % (c1["seed"], c1["seconds_per_query"] * 1e3, c1["edges_per_s"],
                            c1["per_query"]["rounds"], c1["per_query"]["bin_rounds"]))
-    bat = bench_batched(plc, synth, g, max(2, args.steps // 2), 1) if want("batched") else None
+    bat = bench_batched(plc, synth, g, max(3, args.steps // 2), 2) if want("batched") else None
     if bat:
         log("batched: %.3g edges/s, %.1f queries/s" % (bat["edges_per_s"], bat["queries_per_s"]))
-    bat_c = (bench_batched(plc, synth, g, max(2, args.steps // 2), 1, compact=True)
+    bat_c = (bench_batched(plc, synth, g, max(3, args.steps // 2), 2, compact=True)
              if want("batched") else None)
     if bat_c:
         log("batched (compact tables): %.3g edges/s, %.1f queries/s" % (

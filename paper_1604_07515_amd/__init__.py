@@ -181,6 +181,15 @@ def _ptr(a: np.ndarray) -> C.c_void_p:
     return C.c_void_p(a.ctypes.data)
 
 
+def _parts(counts, dtype):
+    """Host arrays for one kind of vector of several results (one array per
+    result, as a lone result gets) and their addresses (0 for an empty one)."""
+    views = [np.empty(int(c), dtype) for c in counts]
+    ptrs = np.fromiter((v.__array_interface__["data"][0] if len(v) else 0 for v in views),
+                       np.uint64, len(views))
+    return ptrs, views
+
+
 @dataclass
 class Result:
     """Vectors of a finished query (host copies)."""
@@ -455,27 +464,29 @@ class Context:
         qids = [int(q) for q in qids]
         if not qids:
             return []
-        infos, vecs = [], []
-        for qid in qids:
+        k = len(qids)
+        infos = []
+        n = np.empty(k, np.int64)
+        nr = np.empty(k, np.int64)
+        for j, qid in enumerate(qids):
             info = plc_result_info()
             _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)),
                    "plc_result_info_get")
-            N, R = info.support, info.r_nnz
-            if info.flags & PLC_QF_NO_RESIDUAL:
-                R = 0  # the result keeps no residual vector
             infos.append(info)
-            vecs.append((np.empty(N, np.int32), np.empty(N, np.float64),
-                         np.empty(R, np.int32), np.empty(R, np.float64)))
-        k = len(qids)
-        arrs = [(C.c_void_p * k)(*[v[j].ctypes.data if len(v[j]) else None for v in vecs])
-                for j in range(4)]
+            n[j] = info.support
+            # a result that keeps no residual vector has no r parts
+            nr[j] = 0 if info.flags & PLC_QF_NO_RESIDUAL else info.r_nnz
+        parts = [_parts(n, np.int32), _parts(n, np.float64), _parts(nr, np.int32),
+                 _parts(nr, np.float64)]
         ids = np.asarray(qids, np.uint64)
-        _check(self.lib.plc_result_copy_many(self.handle, k, _ptr(ids), *arrs),
+        _check(self.lib.plc_result_copy_many(self.handle, k, _ptr(ids),
+                                             *[ptrs.ctypes.data for ptrs, _ in parts]),
                "plc_result_copy_many")
         if release:
             for qid in qids:
                 self.release(qid)
-        return [Result(info.as_dict(), *v) for info, v in zip(infos, vecs)]
+        return [Result(info.as_dict(), *(views[j] for _, views in parts))
+                for j, info in enumerate(infos)]
 
     def release(self, qid: int):
         _check(self.lib.plc_release(self.handle, qid), "plc_release")
