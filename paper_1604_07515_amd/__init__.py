@@ -78,7 +78,12 @@ class plc_result_info(C.Structure):
                 ("table_cap", C.c_int64), ("pull_rounds", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k in self.names()}
+
+    @classmethod
+    def names(cls) -> list:
+        """Field names of the info dict (the reserved word left out)."""
+        return [k for k, _ in cls._fields_ if k != "reserved"]
 
 
 PLC_TUNE_PLAIN = 1
@@ -465,17 +470,16 @@ class Context:
         if not qids:
             return []
         k = len(qids)
-        infos = []
-        n = np.empty(k, np.int64)
-        nr = np.empty(k, np.int64)
+        arr = (plc_result_info * k)()
         for j, qid in enumerate(qids):
-            info = plc_result_info()
-            _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(info)),
+            _check(self.lib.plc_result_info_get(self.handle, qid, C.byref(arr[j])),
                    "plc_result_info_get")
-            infos.append(info)
-            n[j] = info.support
-            # a result that keeps no residual vector has no r parts
-            nr[j] = 0 if info.flags & PLC_QF_NO_RESIDUAL else info.r_nnz
+        rec = np.frombuffer(arr, dtype=np.dtype(plc_result_info))
+        n = rec["support"].astype(np.int64)
+        # a result that keeps no residual vector has no r parts
+        nr = np.where(rec["flags"] & PLC_QF_NO_RESIDUAL, 0, rec["r_nnz"]).astype(np.int64)
+        names = plc_result_info.names()
+        infos = [dict(zip(names, row)) for row in rec[names].tolist()]
         parts = [_parts(n, np.int32), _parts(n, np.float64), _parts(nr, np.int32),
                  _parts(nr, np.float64)]
         ids = np.asarray(qids, np.uint64)
@@ -485,8 +489,7 @@ class Context:
         if release:
             for qid in qids:
                 self.release(qid)
-        return [Result(info.as_dict(), *(views[j] for _, views in parts))
-                for j, info in enumerate(infos)]
+        return [Result(info, *(views[j] for _, views in parts)) for j, info in enumerate(infos)]
 
     def release(self, qid: int):
         _check(self.lib.plc_release(self.handle, qid), "plc_release")
