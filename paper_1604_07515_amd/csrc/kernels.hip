@@ -2,7 +2,7 @@
 // round-synchronous PR-Nibble (Sec. 3.3) and the parallel sweep cut
 // (Sec. 3.1, Theorem 1).
 //
-// Round t of PR-Nibble is two launches:
+// Round t of PR-Nibble is three launches:
 //   k_self    vertexMap(Frontier, UpdateSelf): snapshot rho_v = r[v], update
 //             p[v] and r[v], compute the per-entry coefficient cn*rho/d(v), and
 //             (single-pass decoupled look-back scan) the start of each entry's
@@ -13,7 +13,13 @@
 //             reads, FP64 atomic add into r[w].  The filter of the paper is
 //             folded in: r only grows during a scatter, so w joins the next
 //             frontier exactly when one atomic's (old, old + c) pair straddles
-//             eps*d(w); that atomic appends w.
+//             eps*d(w); that atomic appends w.  On rounds of at least the
+//             binning threshold it is pass A of the binned scatter instead
+//             (pairs sorted into destination bins), and on rounds over half
+//             the arcs it only stamps the frontier's coefficients.
+//   k_bin_apply  pass B of a binned round (LDS sums per bin, one update per
+//             touched destination) or the pull form; it exits at once on the
+//             other rounds.
 // A frontier of at most one scan block is handled by k_self alone: its last
 // workgroup to arrive runs such rounds back to back (self step, scan, edge
 // scatter, round close) until the frontier grows, empties or a round has
@@ -1448,8 +1454,8 @@ __device__ __forceinline__ bool sweep_ready(const Ctl* c) {
 // Sort keys: non-increasing p/d is ascending order of the bit-inverted IEEE
 // pattern of the positive ratio; equal ratios order by ascending id.
 // The sweep sequence is queued for supports of at most `bound` vertices (it
-// sets the number of merge passes); a larger support leaves the query
-// unswept, for a sweep queued with a larger bound.
+// sets the sort's launches); a larger support leaves the query unswept, for
+// a sweep queued with a larger bound.
 __global__ __launch_bounds__(kBlock) void k_sweep_keys(PlainArgs a, long long bound) {
   Ctl* c = a.ctl;
   if (!sweep_ready(c) || (long long)c->support_cnt > bound) return;

@@ -628,7 +628,8 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
 }
 
 // Graph of the plain sweep sequence for supports of at most max_count
-// vertices (a power of 2: it sets the number of merge passes).
+// vertices (a power of 2: it sets the sort's launches, one rank merge up to
+// 65536 elements, merge passes above).
 static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count) {
   const int gw = shape(g->plain_sweep, ctx->grid_sweep);
   Captured& c = g->sweep_g[max_count];
@@ -855,8 +856,8 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
 }
 
 // Queue the plain sweep for supports of at most `bound` vertices (a power
-// of 2: it sets the number of merge passes); with timing on, between the
-// context's sweep events.
+// of 2: it sets the sort's launches); with timing on, between the context's
+// sweep events.
 static hipError_t queue_sweep(plc_ctx* ctx, plc_graph* g, int64_t bound) {
   hipStream_t s = ctx->stream;
   Captured* sg = ctx->use_graphs && !ctx->timing ? plain_sweep_graph(ctx, g, bound) : nullptr;

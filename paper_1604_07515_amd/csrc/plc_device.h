@@ -260,7 +260,7 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 // t0 stamps k_scatter's start and t1 k_bin_apply's end.
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr, int slot = -1, int grid_bin = 1024);
-// max_count: bound on the support size, sets the number of merge passes; a
+// max_count: bound on the support size, sets the sort's launches; a
 // query with a larger support (or one still pushing) is left unswept, so the
 // sweep may be queued before the push is known to have ended.  The sweep
 // writes its results to a.sid, a.sp (support order, p) and a.rid, a.rval

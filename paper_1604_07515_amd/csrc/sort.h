@@ -15,7 +15,7 @@ struct __align__(16) SortElem {
 struct SortArgs {
   SortElem* buf[2];        // ping-pong buffers; *flip says which holds the data
   const int32_t* count;    // element count (device)
-  int32_t* flip;           // 0 or 1 (device); flipped by every merge pass that runs
+  int32_t* flip;           // 0 or 1 (device); flipped by every merge launch that runs
   unsigned* done;          // last-workgroup counter (device, zero between launches)
   const int32_t* active;   // optional gate: the sort runs only if *active == active_value
   int32_t active_value;
