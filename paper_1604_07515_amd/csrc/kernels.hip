@@ -1889,13 +1889,18 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0,
                           hipEvent_t t1, int slot, int grid_bin) {
   if (slot >= kMaxChunk) return hipErrorInvalidValue;
+  // k_bin_apply only where a round can be binned or pulled (an empty
+  // launch still costs a dispatch every round)
+  const bool apply = bins_possible(a);
   if (t0) {
-    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, nullptr, 0, a, slot);
-    hipExtLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, nullptr, t1, 0, a,
-                          slot);
+    hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, apply ? nullptr : t1, 0,
+                          a, slot);
+    if (apply)
+      hipExtLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, nullptr, t1, 0, a,
+                            slot);
   } else {
     hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a, slot);
-    hipLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, a, slot);
+    if (apply) hipLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, a, slot);
   }
   return hipGetLastError();
 }

@@ -575,9 +575,6 @@ static hipError_t ev_pair(EventPair& e) {
 
 static int shape(int tuned, int dflt) { return tuned > 0 ? tuned : dflt; }
 
-// A binning threshold no round reaches.
-constexpr long long kBinOff = 1ll << 62;
-
 // Record body(stream) into c.exec.  On failure the context stops using graphs
 // (direct launches run the same kernels) and false is returned.
 template <class F>
@@ -2104,7 +2101,7 @@ extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* 
     // times it, or no binning (graphs whose large rounds already hit few
     // lines per destination, such as ring-local ones, gain nothing from it)
     if (g->args.nbins > 0 && ctx->opt.bin_min_edges == 0) {
-      const long long emins[] = {plc::kBinEmin, 4ll * plc::kBinEmin, kBinOff};
+      const long long emins[] = {plc::kBinEmin, 4ll * plc::kBinEmin, plc::kBinOff};
       long long be = g->args.bin_emin;
       for (long long e : emins) {
         g->args.bin_emin = e;
@@ -2149,7 +2146,7 @@ extern "C" plc_status plc_autotune(plc_ctx* ctx, plc_graph* g, const plc_query* 
     out->batch_ms = best_batch;
     out->candidates = tried;
     out->plain_bin_min_edges =
-        g->args.nbins <= 0 || g->args.bin_emin >= kBinOff ? -1 : (int32_t)g->args.bin_emin;
+        !plc::bins_possible(g->args) ? -1 : (int32_t)g->args.bin_emin;
   }
   return PLC_OK;
 }

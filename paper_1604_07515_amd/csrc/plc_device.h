@@ -212,10 +212,16 @@ constexpr int kBinItemChunks = 2048;   // chunks one pass-B item may span
 constexpr int kBinQ = 4096;            // expected pairs per pass-B item
 constexpr long long kBinEmin = 1 << 19;  // default smallest binned round (edges)
 constexpr long long kBinEmax = 1 << 23;  // largest binned round the pair buffer is sized for
+constexpr long long kBinOff = 1ll << 62;  // a threshold no round reaches: binning off
 // larger graphs use the atomic scatter only (their width-bound bins alone
 // would crowd out the volume-balanced ones)
 constexpr long long kBinMaxVertices = (long long)kMaxBins * 3 / 4 * kBinWidth;
 static_assert(kBinChunk <= 65536 && kMaxBins <= 32768, "pass A packs (bin, rank) in 32 bits");
+
+// Whether a round of this graph can be binned or pulled (both need bins and
+// a reachable threshold); otherwise k_bin_apply never has work and the
+// scatter closes every round itself.
+inline bool bins_possible(const PlainArgs& a) { return a.nbins > 0 && a.bin_emin < kBinOff; }
 
 // Host-side launchers (return hipError_t of the launch).
 hipError_t launch_graph_init(hipStream_t s, const PlainArgs& a);
