@@ -69,11 +69,13 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scatter_hbm_traffic_rmat22.md"
 PLAIN_SCATTER = "k_scatter + k_bin_apply"
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, bin_min_edges=None):
     """Per-launch HBM traffic of `kernel` from the committed hardware-counter
     summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter
     reads for a device copy of known size), or None when the kernel's sources
-    changed since the counters were taken."""
+    changed since the counters were taken, or when the record names the
+    plain path's binning threshold it was taken at and the live run bins from
+    another (bin_min_edges: the live threshold, -1 when no round can bin)."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             block = f.read().split("```json", 1)[1].split("```", 1)[0]
@@ -84,17 +86,20 @@ def measured_traffic(kernel):
                 h.update(f.read())
     except (OSError, IndexError, KeyError, ValueError):
         return None
+    if "plain_bin_min_edges" in rec and rec["plain_bin_min_edges"] != bin_min_edges:
+        return None
     return rec if h.hexdigest()[:16] == rec["source_sha256_16"] else None
 
 
-def roofline(tm, kernel, counted=True):
+def roofline(tm, kernel, counted=True, bin_min_edges=None):
     """Roofline of the scatter kernel from the instrumented replay; the
     counter-based traffic only where the counters were taken on this same
-    workload (counted=False for the others)."""
+    workload (counted=False for the others) and, for the plain scatter, at
+    the same binning threshold."""
     sc = tm["scatter"]
     by = SCATTER_B_PER_EDGE * sc["units"] + SCATTER_B_PER_ENTRY * sc["entries"]
     gbs = by / (sc["ms"] * 1e-3) / 1e9 if sc["ms"] > 0 else 0.0
-    tr = measured_traffic(kernel) if counted else None
+    tr = measured_traffic(kernel, bin_min_edges) if counted else None
     return {
         "kernel": "%s (edgeMap UpdateNgh)" % kernel, "bound": "hbm", "achieved": gbs,
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
@@ -163,9 +168,10 @@ def account(acc, infos, ids, ctx, fetch=False):
             ctx.release(qid)
 
 
-def bench_plain(plc, synth, g, steps, warmup):
+def bench_plain(plc, synth, g, steps, warmup, bin_min_edges=0):
     seeds = synth.uniform_seeds(g, 16, seed=2)
-    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20),
+                      bin_min_edges=bin_min_edges)
     hg = ctx.load_graph(g.off, g.nbr)
     tune = ctx.autotune(hg, seeds, 0.01, 1e-7, plc.PLC_TUNE_PLAIN)
     log("  plain launch shapes: self %d, scatter %d, sweep %d workgroups, binned rounds from %d "
@@ -214,7 +220,8 @@ def bench_plain(plc, synth, g, steps, warmup):
                                 "ms_per_step": el2 * 1e3 / steps},
         "per_query": {k: acc[k] / nq for k in ("edges", "pushes", "rounds", "support",
                                                  "bin_rounds")},
-        "kernels": tm, "roofline": roofline(tm, PLAIN_SCATTER),
+        "kernels": tm,
+        "roofline": roofline(tm, PLAIN_SCATTER, bin_min_edges=tune["plain_bin_min_edges"]),
         "launch_shapes": {k: tune[k] for k in ("plain_self", "plain_scatter", "plain_sweep",
                                                "plain_bin_min_edges")},
     }
@@ -746,6 +753,10 @@ def main():
                          "(0 = skip)")
     ap.add_argument("--cpu-mc-budget", type=float, default=10.0,
                     help="seconds for the multicore (OpenMP) CPU baseline (0 = skip)")
+    ap.add_argument("--plain-bin-min-edges", type=int, default=0, metavar="EDGES",
+                    help="the plain leg's binning threshold: 0 = picked by the autotuner "
+                         "(default), > 0 = rounds of at least EDGES edges binned, < 0 = none "
+                         "(fixes the configuration for hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a device copy of MIB MiB three times (reference kernel "
                          "for hardware byte counters)")
@@ -774,7 +785,8 @@ def main():
     g = synth.rmat(22, 16, seed=1)
     log("graph 2^22: n=%d arcs=%d maxdeg=%d (%.1fs)" % (g.n, g.arcs, g.deg.max(), time.time() - t0))
     want = lambda w: (args.only is None and w not in args.skip) or args.only == w
-    plain = bench_plain(plc, synth, g, args.steps, args.warmup) if want("plain") else None
+    plain = (bench_plain(plc, synth, g, args.steps, args.warmup, args.plain_bin_min_edges)
+             if want("plain") else None)
     if plain:
         log("plain: %.3g edges/s, %.1f queries/s" % (plain["edges_per_s"], plain["queries_per_s"]))
     c1 = bench_c1(plc, synth) if want("c1") else None

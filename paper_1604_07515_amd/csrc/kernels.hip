@@ -1702,6 +1702,13 @@ __global__ __launch_bounds__(kBlock) void k_cut_scan(PlainArgs a) {
     }
     __syncthreads();
   }
+  // p and the sweep rank of every support vertex are read by no later
+  // kernel (k_vol_scan read p, k_cut_count the rank): reset them
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+    const int32_t v = a.support[i];
+    a.vr[v].rank = 0;
+    a.p[v] = 0.0;
+  }
 }
 
 // Reduce the per-block candidates of k_cut_scan (one workgroup).
@@ -1726,65 +1733,17 @@ __device__ void cut_final(const PlainArgs& a, Ctl* c, int N) {
   }
 }
 
-// Workgroup 0 reduces k_cut_scan's per-block candidates to the best prefix;
-// all gather the nonzeros of r over the touched list into the result and
-// reset the query's dense state (r of every touched vertex; p and the sweep
-// rank of every support vertex: both were read by
-// earlier sweep kernels only); the last workgroup marks the sweep finished.
+// One workgroup reduces k_cut_scan's per-block candidates to the best
+// prefix and marks the sweep finished.  The query's dense state is reset by
+// then: r of every touched vertex by the block sort's side job, p and the
+// sweep rank of every support vertex by k_cut_scan.
 __global__ __launch_bounds__(kBlock) void k_sweep_finish(PlainArgs a) {
   Ctl* c = a.ctl;
   if (c->status != ST_SWEEPING) return;
-  if (blockIdx.x == 0 && c->N > 0) cut_final(a, c, c->N);
-  __shared__ long long sh[kBlock / 64 + 1];
-  __shared__ long long s_base;
-  __shared__ int s_last;
-  int32_t* const out_rid = c->out.rid;
-  double* const out_rval = c->out.rval;
-  const long long rcap = c->out.rcap;
-  const int T = (int64_t)c->touched_cnt > a.n ? (int)a.n : c->touched_cnt;
-  const int N = (int64_t)c->support_cnt > a.n ? (int)a.n : c->support_cnt;
-  // kScanBlock touched entries per workgroup step: read and clear r, then
-  // place the nonzeros with one workgroup scan and one global atomic
-  for (int base = blockIdx.x * kScanBlock; base < T; base += gridDim.x * kScanBlock) {
-    int32_t v[kScanItems];
-    double rv[kScanItems];
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-      const int i = base + k * kBlock + (int)threadIdx.x;
-      v[k] = i < T ? a.touched[i] : -1;
-    }
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) rv[k] = v[k] >= 0 ? a.vr[v[k]].r : 0.0;
-    long long cnt = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-      if (v[k] >= 0) a.vr[v[k]].r = 0.0;
-      cnt += rv[k] != 0.0;
-    }
-    long long tot;
-    const long long off = block_excl_scan<kBlock>(cnt, &tot, sh);
-    if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&c->rnnz, (int)tot) : 0;
-    __syncthreads();
-    long long slot = s_base + off;
-#pragma unroll
-    for (int k = 0; k < kScanItems; k++) {
-      if (rv[k] != 0.0) {
-        if (slot < rcap) { out_rid[slot] = v[k]; out_rval[slot] = rv[k]; } else c->fault = 1;
-        slot++;
-      }
-    }
-    __syncthreads();
-  }
-  for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
-    int32_t v = a.support[i];
-    a.vr[v].rank = 0;
-    a.p[v] = 0.0;
-  }
-  if (last_block(&c->done[DONE_FINISH], &s_last, false)) {
-    if (threadIdx.x == 0) {
-      c->t_end = (long long)wall_clock64();
-      c->status = ST_SWEPT;
-    }
+  if (c->N > 0) cut_final(a, c, c->N);
+  if (threadIdx.x == 0) {
+    c->t_end = (long long)wall_clock64();
+    c->status = ST_SWEPT;
   }
 }
 
@@ -1966,14 +1925,27 @@ hipError_t launch_sweep(hipStream_t s, const PlainArgs& a, int grid, int64_t max
   // the volume prefix is written only after the sort: its words hold the
   // small-count path's rank accumulators meanwhile
   sa.rank = reinterpret_cast<unsigned long long*>(a.svol);
+  // the block sort's workgroups without a tile gather the nonzeros of r over
+  // the touched list into the result buffers and reset r (no later sweep
+  // kernel reads r)
+  static_assert(sizeof(VRec) % sizeof(double) == 0, "r read with a stride of whole records");
+  sa.side_ids = a.touched;
+  sa.side_count = &a.ctl->touched_cnt;
+  sa.side_val = &a.vr[0].r;
+  sa.side_stride = (int)(sizeof(VRec) / sizeof(double));
+  sa.side_out_id = a.rid;
+  sa.side_out_val = a.rval;
+  sa.side_out_cnt = &a.ctl->rnnz;
+  sa.side_out_cap = a.n;
+  sa.side_fault = &a.ctl->fault;
   hipError_t e = launch_sort(s, sa, max_count < a.n ? max_count : a.n, grid);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_vol_scan, dim3(grid), dim3(kBlock), 0, s, a);
-  // the count and the final gather walk many short, latency-bound steps:
-  // a larger grid keeps each workgroup to about one
+  // the count walks many short, latency-bound steps: a larger grid keeps
+  // each workgroup to about one
   hipLaunchKernelGGL(k_cut_count, dim3(4 * grid), dim3(kBlock), 0, s, a);
   hipLaunchKernelGGL(k_cut_scan, dim3(grid), dim3(kBlock), 0, s, a);
-  hipLaunchKernelGGL(k_sweep_finish, dim3(4 * grid), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_sweep_finish, dim3(1), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -23,6 +23,22 @@ struct SortArgs {
   // rank accumulators of the one-launch merge); null selects merge passes
   // at every count.
   unsigned long long* rank;
+  // Optional side job of the block-sort launch, taken first by its
+  // workgroups that hold no tile: for each id in side_ids[0 .. *side_count)
+  // (at most side_out_cap of them), the double at side_val[id * side_stride]
+  // is read and set to +0.0, and every nonzero one is appended as (id,
+  // value) to side_out_id / side_out_val at slots taken from *side_out_cnt
+  // (a slot at or past side_out_cap sets *side_fault instead).  The order
+  // of the appended pairs is unspecified.  Null side_ids: no side job.
+  const int32_t* side_ids = nullptr;
+  const int32_t* side_count = nullptr;
+  double* side_val = nullptr;
+  int side_stride = 0;
+  int32_t* side_out_id = nullptr;
+  double* side_out_val = nullptr;
+  int32_t* side_out_cnt = nullptr;
+  long long side_out_cap = 0;
+  int32_t* side_fault = nullptr;
 };
 
 // Counts up to this many elements take the small-count path when

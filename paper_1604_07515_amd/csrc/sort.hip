@@ -22,6 +22,10 @@
 // place is its position in its own block-sorted tile plus its count in
 // every other tile, found by a binary search in that tile held in LDS, and
 // the last of those additions places it.
+//
+// The block-sort launch can carry a side job (SortArgs::side_ids) for its
+// workgroups that hold no tile: with supports of a few tiles most of the
+// launch's workgroups would otherwise only exit.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -82,6 +86,62 @@ __device__ __forceinline__ void cswap(SortElem& a, SortElem& b, bool up) {
   const SortElem hi = elem_sel(sw, a, b);
   a = lo;
   b = hi;
+}
+
+constexpr int kSideItems = 4;                    // side-job entries per thread and step
+constexpr int kSideStep = kBSBlk * kSideItems;
+
+// The block-sort launch's side job (SortArgs::side_ids), in steps of
+// kSideStep ids per workgroup: the workgroups are renumbered so that those
+// holding no tile take the first steps; the ones that sorted a tile join
+// only when there are more steps than workgroups without one.  Each step
+// places its nonzeros with one workgroup scan and one global atomic.
+__device__ void side_job(const SortArgs& s, int ntiles) {
+  long long T = *s.side_count;
+  if (T > s.side_out_cap) T = s.side_out_cap;
+  if (T <= 0) return;
+  __shared__ long long sh[kBSBlk / 64 + 1];
+  __shared__ long long s_base;
+  const int G = gridDim.x;
+  const int busy = ntiles < G ? ntiles : G;
+  const int w = ((int)blockIdx.x - busy + G) % G;
+  const int t = threadIdx.x;
+  for (long long base = (long long)w * kSideStep; base < T; base += (long long)G * kSideStep) {
+    int32_t v[kSideItems];
+    double x[kSideItems];
+#pragma unroll
+    for (int k = 0; k < kSideItems; k++) {
+      const long long i = base + k * kBSBlk + t;
+      v[k] = i < T ? s.side_ids[i] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < kSideItems; k++)
+      x[k] = v[k] >= 0 ? s.side_val[(long long)v[k] * s.side_stride] : 0.0;
+    long long cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kSideItems; k++) {
+      if (v[k] >= 0) s.side_val[(long long)v[k] * s.side_stride] = 0.0;
+      cnt += x[k] != 0.0;
+    }
+    long long tot;
+    const long long off = block_excl_scan<kBSBlk>(cnt, &tot, sh);
+    if (t == 0) s_base = tot > 0 ? atomicAdd(s.side_out_cnt, (int32_t)tot) : 0;
+    __syncthreads();
+    long long slot = s_base + off;
+#pragma unroll
+    for (int k = 0; k < kSideItems; k++) {
+      if (x[k] != 0.0) {
+        if (slot < s.side_out_cap) {
+          s.side_out_id[slot] = v[k];
+          s.side_out_val[slot] = x[k];
+        } else {
+          *s.side_fault = 1;
+        }
+        slot++;
+      }
+    }
+    __syncthreads();
+  }
 }
 
 __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
@@ -170,6 +230,7 @@ __global__ __launch_bounds__(kBSBlk) void k_block_sort(SortArgs s) {
     }
     __syncthreads();
   }
+  if (s.side_ids != nullptr) side_job(s, ntiles);
 }
 
 // ------------------------------------------------------ small-count path

@@ -1,6 +1,8 @@
 """Host-side Python logic that needs no GPU: the serving loop's arrival
 process and the benchmark's roofline bookkeeping (the traffic figure is
-reported only while the profiled kernel sources are unchanged)."""
+reported only while the profiled kernel sources are unchanged and, for the
+plain scatter, the live run bins rounds from the threshold the counters were
+taken at)."""
 import json
 import os
 import shutil
@@ -49,7 +51,8 @@ def test_traffic_requires_unchanged_sources(tmp_path, monkeypatch):
     shutil.copy(prof, fake / "profiles" / os.path.basename(prof))
     monkeypatch.setattr(bench, "ROOT", str(fake))
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake / "profiles" / os.path.basename(prof)))
-    live = bench.measured_traffic(key)
+    emin = rec[key].get("plain_bin_min_edges")
+    live = bench.measured_traffic(key, emin)
     current = bench.hashlib.sha256()
     for src in rec[key]["sources"]:
         current.update(open(os.path.join(ROOT, src), "rb").read())
@@ -57,6 +60,9 @@ def test_traffic_requires_unchanged_sources(tmp_path, monkeypatch):
         assert live is not None and live["traffic_bytes_per_launch"] > 0
     else:
         assert live is None  # the sources changed since the counters were taken
+    if emin is not None:
+        # counters taken at one binning threshold say nothing of another
+        assert bench.measured_traffic(key, -1 if emin > 0 else 524288) is None
     victim = fake / rec[key]["sources"][0]
     victim.write_bytes(victim.read_bytes() + b"\n")
     assert bench.measured_traffic(key) is None
