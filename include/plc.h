@@ -93,7 +93,12 @@ typedef struct plc_graph plc_graph;
  * plc_autotune may change per graph (it also tries four times that and no
  * binning); > 0 = that threshold, kept by plc_autotune; < 0 = always the
  * atomic form.  (Graphs of more than 6,291,456 = 1536 x 4096 vertices
- * always use the atomic form.)
+ * always use the atomic form.)  With 0 the library also learns from the
+ * last queries at which launches of a query's first chunk of rounds such
+ * rounds fall, and queues the binned form's second pass only there: a round
+ * of that size elsewhere in the first chunk takes the atomic form (the same
+ * result up to the order of the additions; plc_result_info.bin_rounds
+ * counts the rounds that did bin).
  */
 typedef struct {
   int32_t max_rounds;  /* watchdog on PR-Nibble rounds per query; 0 = 1<<20 */

@@ -70,6 +70,7 @@ __device__ __forceinline__ void reset_round_book(Ctl* c) {
   c->loop_pushes = 0;
   c->loop_edges = 0;
   c->bin_rounds = 0;
+  c->bin_pairs = 0u;
   c->pull_rounds = 0;
   c->bin_edges = 0;
   c->t_start = (long long)wall_clock64();
@@ -1081,7 +1082,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_apply(PlainArgs a, int slot) {
 //     to list j+1; each entry's own rho / 2 is added by the workgroup whose
 //     tile holds the entry's first edge.
 template <int MODE>
-__device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, ScatterShared& sm) {
+__device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, ScatterShared& sm,
+                                             int pair = -1, bool apply = true) {
   constexpr bool HK = MODE == kModeHK;
   constexpr bool LEVELS = MODE != kModePR;
   Ctl* c = a.ctl;
@@ -1089,7 +1091,15 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, Scatt
   if (!push_active(c, a.n, &t, &nf)) return;
   if (HK ? t >= c->hk_N : t >= c->max_rounds) return;
   if (c->selfed != t) return;  // no entries built for this round (a self loop stopped before it)
-  if (MODE == kModePR && pull_round(a, c->etotal)) {
+  // which launch pairs of a first chunk carry rounds that could bin or pull
+  // (the host queues k_bin_apply behind those pairs only); without
+  // k_bin_apply behind it the round takes the atomic form
+  if (MODE == kModePR && pair >= 0 && blockIdx.x == 0 && threadIdx.x == 0 &&
+      (pull_round(a, c->etotal) || bin_round(a, c->etotal)))
+    c->bin_pairs |= 1u << pair;
+  if (MODE == kModePR && !apply) {
+    // (falls through to the atomic form)
+  } else if (MODE == kModePR && pull_round(a, c->etotal)) {
     // a pull round: the frontier's coefficients, stamped with the round's
     // epoch, for k_bin_apply to pull (which also closes the round)
     const unsigned ep = *a.pull_epoch;
@@ -1097,8 +1107,7 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, Scatt
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < nf; i += gridDim.x * kBlock)
       a.pull[F[i]] = PullRec{a.coef[i], ep, 0};
     return;
-  }
-  if (MODE == kModePR && bin_round(a, c->etotal)) {
+  } else if (MODE == kModePR && bin_round(a, c->etotal)) {
     bin_sort_chunks(a, nf, sm.bs);  // pass A; k_bin_apply adds and closes the round
     return;
   }
@@ -1215,9 +1224,9 @@ __device__ __forceinline__ void scatter_body(const PlainArgs& a, int slot, Scatt
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a, int slot) {
+__global__ __launch_bounds__(kBlock) void k_scatter(PlainArgs a, int slot, int pair, int apply) {
   __shared__ ScatterShared sm;
-  scatter_body<kModePR>(a, slot, sm);
+  scatter_body<kModePR>(a, slot, sm, pair, apply != 0);
 }
 __global__ __launch_bounds__(kBlock) void k_hk_scatter(PlainArgs a) {
   __shared__ ScatterShared sm;
@@ -1846,19 +1855,20 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 }
 
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0,
-                          hipEvent_t t1, int slot, int grid_bin) {
-  if (slot >= kMaxChunk) return hipErrorInvalidValue;
+                          hipEvent_t t1, int slot, int grid_bin, int pair, bool apply_wanted) {
+  if (slot >= kMaxChunk || pair >= 32) return hipErrorInvalidValue;
   // k_bin_apply only where a round can be binned or pulled (an empty
   // launch still costs a dispatch every round)
-  const bool apply = bins_possible(a);
+  const bool apply = apply_wanted && bins_possible(a);
+  const int ap = apply ? 1 : 0;
   if (t0) {
     hipExtLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, t0, apply ? nullptr : t1, 0,
-                          a, slot);
+                          a, slot, pair, ap);
     if (apply)
       hipExtLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, nullptr, t1, 0, a,
                             slot);
   } else {
-    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a, slot);
+    hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kBlock), 0, s, a, slot, pair, ap);
     if (apply) hipLaunchKernelGGL(k_bin_apply, dim3(grid_bin), dim3(kBlock), 0, s, a, slot);
   }
   return hipGetLastError();

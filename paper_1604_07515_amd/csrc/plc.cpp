@@ -62,8 +62,9 @@ struct Captured {
   hipGraphExec_t exec = nullptr;
   int gs = -1, gc = -1, gw = -1, rounds = -1;
   long long emin = 0;  // plain rounds: the binning threshold the graph's arguments carry
-  bool matches(int s, int c, int w, int r, long long e = 0) const {
-    return exec && gs == s && gc == c && gw == w && rounds == r && emin == e;
+  uint32_t mask = ~0u;  // plain first chunks: pairs followed by k_bin_apply (bit i: pair i)
+  bool matches(int s, int c, int w, int r, long long e = 0, uint32_t m = ~0u) const {
+    return exec && gs == s && gc == c && gw == w && rounds == r && emin == e && mask == m;
   }
 };
 
@@ -150,6 +151,9 @@ struct plc_graph {
   int batch_self = 0, batch_scatter = 0, batch_sweep = 0;
   BatchEngine* batch = nullptr;
   std::map<int, Captured> chunk_g;  // plain path: R rounds of (self, scatter), by R
+  // plain path: a query's first chunk of R rounds, by R; its pairs queue
+  // k_bin_apply as Captured::mask says and report rounds that could bin
+  std::map<int, Captured> first_g;
   std::map<int64_t, Captured> sweep_g;  // plain path: the sweep, by sort bound (power of 2)
 };
 
@@ -176,6 +180,9 @@ struct plc_ctx {
   int32_t cur_pipe = 0;           // plain path: plc_result_info.pipelined of the running query
   std::deque<int> round_hist;  // plain path: working self launches of the last queries
   std::deque<int> support_hist;  // plain path: support sizes of the last queries
+  // plain path: Ctl::bin_pairs of the last queries whose first chunk reported
+  // them (the pairs of a first chunk whose rounds could bin or pull)
+  std::deque<uint32_t> pair_hist;
   std::chrono::steady_clock::time_point q_t0;  // plain path: start of the running query
   std::chrono::steady_clock::time_point next_t0;  // plain path: start of the queued next query
   hipEvent_t rb_event = nullptr;  // plain path: recorded after the running query's read-back
@@ -256,6 +263,8 @@ static void batch_free(plc_ctx* ctx, plc_graph* g);
 static void graph_captures_free(plc_graph* g) {
   for (auto& kv : g->chunk_g) captured_free(kv.second);
   g->chunk_g.clear();
+  for (auto& kv : g->first_g) captured_free(kv.second);
+  g->first_g.clear();
   for (auto& kv : g->sweep_g) captured_free(kv.second);
   g->sweep_g.clear();
 }
@@ -599,24 +608,49 @@ static bool capture(plc_ctx* ctx, Captured& c, F&& body) {
   return true;
 }
 
-// Graph of R plain rounds (self, scatter).
-static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R) {
+// The launch pairs of a first chunk that queue k_bin_apply: those whose
+// rounds could bin or pull in any of the last queries (all of them until a
+// query has reported, or when the context fixed the binning threshold;
+// pairs from 32 on always queue it).  Binned rounds sit
+// at the same few pairs from query to query (those of the largest frontiers),
+// and k_bin_apply exits at once after every other round at the cost of a
+// dispatch; a round at a pair without it takes the atomic form and reports
+// itself, so the next first chunks queue k_bin_apply there.
+static uint32_t first_chunk_mask(const plc_ctx* ctx) {
+  // (only with the binning threshold left to the library: a threshold the
+  // caller fixed bins every round of that size)
+  if (ctx->opt.bin_min_edges != 0 || ctx->pair_hist.empty()) return ~0u;
+  uint32_t m = 0;
+  for (uint32_t b : ctx->pair_hist) m |= b;
+  return m;
+}
+
+// Graph of R plain rounds (self, scatter).  first: a query's first chunk,
+// whose pair i reports in Ctl::bin_pairs a round that could bin or pull and
+// queues k_bin_apply only where bit i of first_chunk_mask is set (always
+// from pair 32 on).
+static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R, bool first = false) {
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
-  Captured& c = g->chunk_g[R];
-  if (c.matches(gs, gc, 0, R, g->args.bin_emin)) return &c;
+  const uint32_t mask = first ? first_chunk_mask(ctx) : ~0u;
+  Captured& c = first ? g->first_g[R] : g->chunk_g[R];
+  if (c.matches(gs, gc, 0, R, g->args.bin_emin, mask)) return &c;
   captured_free(c);
   c.gs = gs;
   c.gc = gc;
   c.gw = 0;
   c.rounds = R;
   c.emin = g->args.bin_emin;
+  c.mask = mask;
   const PlainArgs& a = g->args;
   const bool ok = capture(ctx, c, [&](hipStream_t cs) -> hipError_t {
     hipError_t r;
     for (int i = 0; i < R; i++) {
+      const bool tracked = first && i < 32;
+      const bool apply = !tracked || ((mask >> i) & 1u);
       if ((r = plc::launch_self(cs, a, gs)) != hipSuccess) return r;
-      if ((r = plc::launch_scatter(cs, a, gc, nullptr, nullptr, -1, ctx->grid_bin)) != hipSuccess)
+      if ((r = plc::launch_scatter(cs, a, gc, nullptr, nullptr, -1, ctx->grid_bin,
+                                   tracked ? i : -1, apply)) != hipSuccess)
         return r;
     }
     return hipSuccess;
@@ -707,7 +741,7 @@ static int first_chunk(const plc_ctx* ctx) {
 static int prelaunch(plc_ctx* ctx, plc_graph* g, const plc_query& q) {
   if (!ctx->use_graphs || ctx->timing) return 0;
   const int R = first_chunk(ctx);
-  Captured* cg = plain_chunk_graph(ctx, g, R);
+  Captured* cg = plain_chunk_graph(ctx, g, R, true);
   if (!cg) return 0;
   hipStream_t s = ctx->stream;
   if (plc::launch_query_init_guarded(s, g->args, q.seed, (int32_t)q.rule, q.alpha, q.eps,
@@ -759,14 +793,17 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     while (spec_bound < mx) spec_bound <<= 1;
   }
   bool swept = false;
+  bool reports = pre > 0;  // the first chunk reports Ctl::bin_pairs (a first-chunk graph)
   Ctl& h = *ctx->ctl_host;
   for (bool first = true;; first = false) {
     const int R = chunk;
     if (!(first && pre > 0)) {
       // while timing is on, rounds are launched directly (graphs carry no
       // events) (the beta variant's rounds are launched directly too)
-      Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta ? plain_chunk_graph(ctx, g, R)
-                                                                  : nullptr;
+      Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta
+                         ? plain_chunk_graph(ctx, g, R, first)
+                         : nullptr;
+      if (first && cg) reports = true;
       if (ctx->timing) HIPCHK(ctx, hipMemsetAsync(a.work_log, 0, 4 * 2 * (size_t)R, s));
       if (cg)
         HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
@@ -848,6 +885,10 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
   if (ctx->round_hist.size() > 16) ctx->round_hist.pop_front();
   ctx->support_hist.push_back(swept ? h.N : h.support_cnt);
   if (ctx->support_hist.size() > 16) ctx->support_hist.pop_front();
+  if (reports) {
+    ctx->pair_hist.push_back(h.bin_pairs);
+    if (ctx->pair_hist.size() > 16) ctx->pair_hist.pop_front();
+  }
   if (swept) return record_result(ctx, g, id_out, info_out);
   return sweep_and_record(ctx, g, id_out, info_out);
 }

@@ -64,7 +64,7 @@ struct __align__(64) Ctl {
   int32_t round;          // rounds pushed so far; frontier of round t is fbuf[t&1], size cnt[t&1]
   int32_t cnt[2];
   int32_t ntiles;         // edge tiles of the current round (or of the sweep's edges)
-  int32_t pad0;
+  uint32_t bin_pairs;     // bit i: the round of a first chunk's launch pair i could bin or pull
   long long etotal;       // sum of degrees of the current frontier (or vol(S_N) in the sweep)
   long long pushes, edges;
   int32_t support_cnt;    // |support list|
@@ -263,9 +263,13 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 // The scatter of a PR-Nibble round: k_scatter (the atomic scatter, or pass A
 // of the binned scatter for rounds of a.bin_emin edges and more), then
 // k_bin_apply (pass B; exits at once after an atomic round).  With t0 set,
-// t0 stamps k_scatter's start and t1 k_bin_apply's end.
+// t0 stamps k_scatter's start and t1 k_bin_apply's end.  apply = false
+// leaves k_bin_apply out: the round then takes the atomic form whatever its
+// size.  pair in [0, 32): the launch pair's index in a first chunk; a round
+// that could bin or pull sets bit pair of the control block's bin_pairs.
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
-                          hipEvent_t t1 = nullptr, int slot = -1, int grid_bin = 1024);
+                          hipEvent_t t1 = nullptr, int slot = -1, int grid_bin = 1024,
+                          int pair = -1, bool apply = true);
 // max_count: bound on the support size, sets the sort's launches; a
 // query with a larger support (or one still pushing) is left unswept, so the
 // sweep may be queued before the push is known to have ended.  The sweep

@@ -100,6 +100,40 @@ def test_plain_rmat22_bench_shapes(plc, g22):
             ctx.close()
 
 
+def test_plain_rmat22_learned_bin_launches(plc, g22):
+    """With the binning threshold left to the library, a query's first chunk
+    queues the binned form's second pass only at the launches where the last
+    queries had rounds of that size.  The same 16 queries twice: in the
+    second pass every one of them bins exactly the rounds that a context
+    with the threshold fixed at the same 524288 edges bins (their own reports
+    selected the launches), and both passes give the fixed context's results
+    (counters exactly, p and r within the tolerance, the sweep modulo
+    near-ties)."""
+    g = g22
+    sl = [int(s) for s in synth.uniform_seeds(g, 16, seed=2)]
+    out = {}
+    for fixed in (524288, 0):
+        ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20),
+                          bin_min_edges=fixed)
+        try:
+            hg = ctx.load_graph(g.off, g.nbr)
+            passes = []
+            for rep in range(1 if fixed else 2):
+                ids, infos = ctx.run(hg, sl, 0.01, 1e-7)
+                passes.append((infos, ctx.results(ids, release=True)))
+            out[fixed] = passes
+        finally:
+            ctx.close()
+    (fi, fr), = out[524288]
+    say("fixed threshold: binned rounds per query", [x["bin_rounds"] for x in fi])
+    assert sum(x["bin_rounds"] for x in fi) >= 16
+    for k, (infos, res) in enumerate(out[0]):
+        say("learned, pass", k, "binned rounds per query", [x["bin_rounds"] for x in infos])
+        for a, b in zip(res, fr):
+            check_same(g, a, b)
+    assert [x["bin_rounds"] for x in out[0][1][0]] == [x["bin_rounds"] for x in fi]
+
+
 def _batched(plc, g, compact):
     qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
     tables = (8 << 30) if compact else 0
