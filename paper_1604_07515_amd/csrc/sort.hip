@@ -90,6 +90,7 @@ __device__ __forceinline__ void cswap(SortElem& a, SortElem& b, bool up) {
 
 constexpr int kSideItems = 4;                    // side-job entries per thread and step
 constexpr int kSideStep = kBSBlk * kSideItems;
+constexpr int kSideGrid = 512;                   // block-sort workgroups when a side job rides along
 
 // The block-sort launch's side job (SortArgs::side_ids), in steps of
 // kSideStep ids per workgroup: the workgroups are renumbered so that those
@@ -406,7 +407,10 @@ __global__ __launch_bounds__(kSortBlk) void k_merge_pass(SortArgs s, int L) {
 }
 
 hipError_t launch_sort(hipStream_t st, const SortArgs& s, int64_t max_count, int grid) {
-  hipLaunchKernelGGL(k_block_sort, dim3(grid), dim3(kBSBlk), 0, st, s);
+  // a side job takes the workgroups without a tile: two per CU fit the
+  // tile's LDS, so up to that many keep the gather from outlasting the sort
+  const int bs_grid = s.side_ids != nullptr && grid < kSideGrid ? kSideGrid : grid;
+  hipLaunchKernelGGL(k_block_sort, dim3(bs_grid), dim3(kBSBlk), 0, st, s);
   if (s.rank != nullptr && max_count <= kRankMaxCount) {
     const int tiles = (int)((max_count + kTileB - 1) / kTileB);
     if (tiles > 1) {
