@@ -151,9 +151,10 @@ struct plc_graph {
   int batch_self = 0, batch_scatter = 0, batch_sweep = 0;
   BatchEngine* batch = nullptr;
   std::map<int, Captured> chunk_g;  // plain path: R rounds of (self, scatter), by R
-  // plain path: a query's first chunk of R rounds, by R; its pairs queue
-  // k_bin_apply as Captured::mask says and report rounds that could bin
-  std::map<int, Captured> first_g;
+  // plain path: a query's first chunk of R rounds, by (R << 32 | mask); its
+  // pairs queue k_bin_apply as the mask says and report rounds that could
+  // bin (a mask that comes back finds its graph still recorded)
+  std::map<uint64_t, Captured> first_g;
   std::map<int64_t, Captured> sweep_g;  // plain path: the sweep, by sort bound (power of 2)
 };
 
@@ -616,6 +617,8 @@ static bool capture(plc_ctx* ctx, Captured& c, F&& body) {
 // and k_bin_apply exits at once after every other round at the cost of a
 // dispatch; a round at a pair without it takes the atomic form and reports
 // itself, so the next first chunks queue k_bin_apply there.
+constexpr size_t kFirstGraphs = 64;  // first-chunk graphs kept per graph
+
 static uint32_t first_chunk_mask(const plc_ctx* ctx) {
   // (only with the binning threshold left to the library: a threshold the
   // caller fixed bins every round of that size)
@@ -633,7 +636,12 @@ static Captured* plain_chunk_graph(plc_ctx* ctx, plc_graph* g, int R, bool first
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   const uint32_t mask = first ? first_chunk_mask(ctx) : ~0u;
-  Captured& c = first ? g->first_g[R] : g->chunk_g[R];
+  const uint64_t key = ((uint64_t)R << 32) | mask;
+  if (first && g->first_g.size() >= kFirstGraphs && !g->first_g.count(key)) {
+    for (auto& kv : g->first_g) captured_free(kv.second);  // bound the recorded masks
+    g->first_g.clear();
+  }
+  Captured& c = first ? g->first_g[key] : g->chunk_g[R];
   if (c.matches(gs, gc, 0, R, g->args.bin_emin, mask)) return &c;
   captured_free(c);
   c.gs = gs;
