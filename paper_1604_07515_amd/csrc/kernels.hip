@@ -19,7 +19,10 @@
 //             the arcs it only stamps the frontier's coefficients.
 //   k_bin_apply  pass B of a binned round (LDS sums per bin, one update per
 //             touched destination) or the pull form; it exits at once on the
-//             other rounds.
+//             other rounds.  The host leaves it out where no round can bin,
+//             and in a query's first chunk behind the launches where recent
+//             queries had no round large enough (k_scatter then takes the
+//             atomic form whatever the round's size).
 // A frontier of at most one scan block is handled by k_self alone: its last
 // workgroup to arrive runs such rounds back to back (self step, scan, edge
 // scatter, round close) until the frontier grows, empties or a round has
@@ -29,6 +32,11 @@
 // block and return at once when the query has finished, so rounds (and the
 // sweep, guarded the same way) can be queued ahead of the host's
 // termination check.
+//
+// The sweep: k_sweep_keys, the sort (sort.hip; its block-sort launch also
+// gathers the nonzeros of r over the touched list and resets r, on the
+// workgroups that hold no tile), k_vol_scan, k_cut_count, k_cut_scan (which
+// also resets p and the ranks) and a one-workgroup k_sweep_finish.
 //
 // Arithmetic matches the paper's updates evaluated in a fixed way: the
 // constants cs, cn, keep are rounded once, p[v] + cs*rho, keep*rho and
