@@ -134,6 +134,29 @@ def test_plain_rmat22_learned_bin_launches(plc, g22):
     assert [x["bin_rounds"] for x in out[0][1][0]] == [x["bin_rounds"] for x in fi]
 
 
+def test_plain_rmat22_support_above_2_21_with_residual(plc, g22):
+    """PR-Nibble from the benchmark's first seed at eps 1e-8: a support of
+    about 2.4 M vertices (more block-sort tiles than the launch has
+    workgroups, so the residual's gather runs on workgroups that sorted
+    tiles, and the deepest merge passes) and about 1.8 M nonzeros of r,
+    checked against the oracle with the residual."""
+    g = g22
+    x = int(synth.uniform_seeds(g, 16, seed=2)[0])
+    ctx = plc.Context(arena_bytes=plc.plain_arena_bytes(g.n, g.arcs) + (512 << 20))
+    try:
+        hg = ctx.load_graph(g.off, g.nbr)
+        say("case plain 2^22 seed", x, "alpha 0.01 eps 1e-8")
+        ids, infos = ctx.run(hg, [x], 0.01, 1e-8)
+        res = ctx.result(ids[0], release=True)
+        say("support", infos[0]["support"], "r nonzeros", infos[0]["r_nnz"])
+        assert infos[0]["support"] > 512 * 4096
+        assert infos[0]["r_nnz"] > (1 << 20)
+        rep = check_query(g, res, x, 0.01, 1e-8, 0)
+        say("report", rep)
+    finally:
+        ctx.close()
+
+
 def _batched(plc, g, compact):
     qs = synth.batched_queries(g, 256, seed=2, eps_lo=1e-7, eps_hi=1e-5)
     tables = (8 << 30) if compact else 0
