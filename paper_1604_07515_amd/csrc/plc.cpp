@@ -688,16 +688,23 @@ static Captured* plain_sweep_graph(plc_ctx* ctx, plc_graph* g, int64_t max_count
 // Queue `rounds` rounds as direct launches; with timing on, each kernel
 // carries start and stop events on its own dispatch timestamps
 // (ctx->ev_self[i], ctx->ev_scatter[i] for round i of the chunk) and marks
-// a.work_log[2i] / [2i + 1] when it did work.
+// a.work_log[2i] / [2i + 1] when it did work.  first: a query's first chunk,
+// with the same k_bin_apply launches and reports as its graph (so the timed
+// launches are the ones the graphs replay).
 
-static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, bool beta) {
+static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, bool beta,
+                               bool first = false) {
   const PlainArgs& a = g->args;
   hipStream_t s = ctx->stream;
   const int gs = shape(g->plain_self, ctx->grid_self);
   const int gc = shape(g->plain_scatter, ctx->grid_scatter);
   const int gw = shape(g->plain_sweep, ctx->grid_sweep);
+  const uint32_t mask = first && !beta ? first_chunk_mask(ctx) : ~0u;
   for (int i = 0; i < rounds; i++) {
     hipError_t r;
+    const bool tracked = first && !beta && i < 32;
+    const int pair = tracked ? i : -1;
+    const bool apply = !tracked || ((mask >> i) & 1u);
     if (beta && (r = plc::launch_beta_pre(s, a, gw, g->n)) != hipSuccess) return r;
     if (ctx->timing) {
       size_t k = (size_t)i;
@@ -708,11 +715,12 @@ static hipError_t queue_rounds(plc_ctx* ctx, const plc_graph* g, int rounds, boo
       if ((r = plc::launch_self(s, a, gs, ctx->ev_self[k].a, ctx->ev_self[k].b, i)) != hipSuccess)
         return r;
       if ((r = plc::launch_scatter(s, a, gc, ctx->ev_scatter[k].a, ctx->ev_scatter[k].b, i,
-                                   ctx->grid_bin)) != hipSuccess)
+                                   ctx->grid_bin, pair, apply)) != hipSuccess)
         return r;
     } else {
       if ((r = plc::launch_self(s, a, gs)) != hipSuccess) return r;
-      if ((r = plc::launch_scatter(s, a, gc, nullptr, nullptr, -1, ctx->grid_bin)) != hipSuccess)
+      if ((r = plc::launch_scatter(s, a, gc, nullptr, nullptr, -1, ctx->grid_bin, pair,
+                                   apply)) != hipSuccess)
         return r;
     }
     if (beta && (r = plc::launch_beta_post(s, a, gw)) != hipSuccess) return r;
@@ -801,7 +809,7 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
     while (spec_bound < mx) spec_bound <<= 1;
   }
   bool swept = false;
-  bool reports = pre > 0;  // the first chunk reports Ctl::bin_pairs (a first-chunk graph)
+  bool reports = pre > 0;  // the first chunk reports Ctl::bin_pairs
   Ctl& h = *ctx->ctl_host;
   for (bool first = true;; first = false) {
     const int R = chunk;
@@ -811,12 +819,12 @@ static plc_status run_one(plc_ctx* ctx, plc_graph* g, const plc_query& q, uint64
       Captured* cg = ctx->use_graphs && !ctx->timing && !use_beta
                          ? plain_chunk_graph(ctx, g, R, first)
                          : nullptr;
-      if (first && cg) reports = true;
+      if (first && !use_beta) reports = true;  // graph or direct launches, both tracked
       if (ctx->timing) HIPCHK(ctx, hipMemsetAsync(a.work_log, 0, 4 * 2 * (size_t)R, s));
       if (cg)
         HIPCHK(ctx, hipGraphLaunch(cg->exec, s));
       else
-        HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta));
+        HIPCHK(ctx, queue_rounds(ctx, g, R, use_beta, first));
     }
     if (spec_bound) HIPCHK(ctx, queue_sweep(ctx, g, spec_bound));
     const EventPair* ev_s = ctx->ev_self.data();
