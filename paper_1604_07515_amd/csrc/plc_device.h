@@ -263,9 +263,9 @@ hipError_t launch_self(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t
 // The scatter of a PR-Nibble round: k_scatter (the atomic scatter, or pass A
 // of the binned scatter for rounds of a.bin_emin edges and more), then
 // k_bin_apply (pass B; exits at once after an atomic round).  With t0 set,
-// t0 stamps k_scatter's start and t1 k_bin_apply's end.  apply = false
-// leaves k_bin_apply out: the round then takes the atomic form whatever its
-// size.  pair in [0, 32): the launch pair's index in a first chunk; a round
+// t0 stamps k_scatter's start and t1 the end of the last kernel queued.
+// apply = false leaves k_bin_apply out (t1 then stamps k_scatter's end): the
+// round then takes the atomic form whatever its size.  pair in [0, 32): the launch pair's index in a first chunk; a round
 // that could bin or pull sets bit pair of the control block's bin_pairs.
 hipError_t launch_scatter(hipStream_t s, const PlainArgs& a, int grid, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr, int slot = -1, int grid_bin = 1024,
